@@ -1,0 +1,143 @@
+"""Seeded synthetic inputs for QRDM / QRP (numpy, host side).
+
+This module only builds matrices: it holds none of the factorization's
+arithmetic and is shared by the tests, the benchmark and the oracle side.
+All matrices are float64, Fortran (column-major) order.
+
+The paper evaluates on numerically singular matrices of the SJSU Singular
+Matrix Database (Section 5), which is not available here; these prescribed
+spectrum matrices stand in for it.  Each generator states its recipe.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS = np.finfo(np.float64).eps
+
+
+def haar(n: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed orthogonal n x n: QR of a Gaussian, columns x sign(diag R)."""
+    g = rng.standard_normal((n, n))
+    q, r = np.linalg.qr(g)
+    q *= np.sign(np.diag(r))[None, :]
+    return np.asfortranarray(q)
+
+
+def haar_cols(m: int, k: int, rng: np.random.Generator) -> np.ndarray:
+    """m x k with Haar-distributed orthonormal columns (k <= m)."""
+    g = rng.standard_normal((m, k))
+    q, r = np.linalg.qr(g)
+    q *= np.sign(np.diag(r))[None, :]
+    return np.asfortranarray(q)
+
+
+def from_spectrum(m: int, n: int, sigma: np.ndarray, seed: int) -> np.ndarray:
+    """A = U diag(sigma) V^T with U (m x p), V (n x p) Haar columns, p = len(sigma)."""
+    rng = np.random.default_rng(seed)
+    p = len(sigma)
+    u = haar_cols(m, p, rng)
+    v = haar_cols(n, p, rng)
+    a = (u * np.asarray(sigma)[None, :]) @ v.T
+    return np.asfortranarray(a)
+
+
+def geometric_rank(n: int, r: int, top: float, bottom: float, tail: float) -> np.ndarray:
+    """sigma_1..r geometric top->bottom, sigma_{r+1..n} = tail."""
+    s = np.full(n, tail, dtype=np.float64)
+    s[:r] = np.geomspace(top, bottom, r)
+    return s
+
+
+def small_rank64(seed: int = 0, n: int = 256) -> np.ndarray:
+    """256 x 256, sigma_1..64 geometric 1 -> 1e-3, sigma_65..256 = 1e-15."""
+    return from_spectrum(n, n, geometric_rank(n, 64, 1.0, 1e-3, 1e-15), seed)
+
+
+def half_rank_noise(n: int = 4096, seed: int = 0) -> np.ndarray:
+    """n x n, sigma_1..n/2 geometric 1 -> 1e-8, the rest 1e-16*|g_i|, g ~ N(0,1)."""
+    rng = np.random.default_rng(seed + 7919)
+    r = n // 2
+    s = np.empty(n)
+    s[:r] = np.geomspace(1.0, 1e-8, r)
+    s[r:] = 1e-16 * np.abs(rng.standard_normal(n - r))
+    return from_spectrum(n, n, s, seed)
+
+
+def kahan(n: int = 4096, theta: float = 1.2) -> np.ndarray:
+    """Kahan matrix K_n(theta) = diag(s^i) (I - c * strictly-upper ones), c = cos, s = sin."""
+    c, s = np.cos(theta), np.sin(theta)
+    k = -c * np.triu(np.ones((n, n)), 1) + np.eye(n)
+    d = s ** np.arange(n)
+    return np.asfortranarray(d[:, None] * k)
+
+
+def geometric_full(n: int = 8192, seed: int = 0) -> np.ndarray:
+    """n x n, sigma geometric 1 -> 1e-16 over all n."""
+    return from_spectrum(n, n, np.geomspace(1.0, 1e-16, n), seed)
+
+
+def devils_stairs(n: int = 8192, step: int = 512, seed: int = 0) -> np.ndarray:
+    """n x n, sigma_i = 10^-floor((i-1)/step): steps of `step` values dropping 10x each."""
+    s = 10.0 ** (-np.floor(np.arange(n) / step))
+    return from_spectrum(n, n, s, seed)
+
+
+def gaussian(m: int, n: int, seed: int = 0) -> np.ndarray:
+    """A_ij ~ N(0, 1) iid."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((m, n)))
+
+
+def rank1(m: int, n: int, seed: int = 0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(np.outer(rng.standard_normal(m), rng.standard_normal(n)))
+
+
+def orthogonal_columns(m: int, norms: np.ndarray, seed: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """A = Q0 diag(s) Pi0: orthogonal columns with prescribed norms s in a random
+    column order.  Returns (A, order) where column j of A has norm norms[order[j]]."""
+    rng = np.random.default_rng(seed)
+    k = len(norms)
+    q = haar_cols(m, k, rng)
+    order = rng.permutation(k)
+    a = q[:, order] * np.asarray(norms)[order][None, :]
+    return np.asfortranarray(a), order
+
+
+def three_directions(m: int = 16, seed: int = 0) -> np.ndarray:
+    """Three unit columns at 0, 120 and 240 degrees in a random plane of R^m."""
+    rng = np.random.default_rng(seed)
+    q = haar_cols(m, 2, rng)
+    ang = np.array([0.0, 2.0 * np.pi / 3.0, 4.0 * np.pi / 3.0])
+    coef = np.stack([np.cos(ang), np.sin(ang)])
+    return np.asfortranarray(q @ coef)
+
+
+def batch_shapes(count: int = 2048, seed: int = 0, mmin: int = 32, mmax: int = 512,
+                 nmin: int = 16) -> list[tuple[int, int, int]]:
+    """(m, n, r): m ~ U{mmin..mmax}, n ~ U{nmin..m}, r ~ U{ceil(n/4)..n}."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(rng.integers(mmin, mmax + 1))
+        n = int(rng.integers(nmin, m + 1))
+        r = int(rng.integers((n + 3) // 4, n + 1))
+        out.append((m, n, r))
+    return out
+
+
+def batch_matrix(m: int, n: int, r: int, seed_seq: np.random.SeedSequence) -> np.ndarray:
+    """U[:, :r] diag(sigma) V[:, :r]^T, sigma_j = 10^(-14 (j-1)/(r-1)), zero beyond r."""
+    rng = np.random.default_rng(seed_seq)
+    sig = np.logspace(0.0, -14.0, r) if r > 1 else np.ones(1)
+    u = haar_cols(m, r, rng)
+    v = haar_cols(n, r, rng)
+    return np.asfortranarray((u * sig[None, :]) @ v.T)
+
+
+def batch(count: int = 2048, seed: int = 0, mmin: int = 32, mmax: int = 512, nmin: int = 16):
+    """The uneven least-squares batch: list of Fortran float64 matrices and their (m, n, r)."""
+    shapes = batch_shapes(count, seed, mmin, mmax, nmin)
+    seqs = np.random.SeedSequence(seed).spawn(count)
+    mats = [batch_matrix(m, n, r, s) for (m, n, r), s in zip(shapes, seqs)]
+    return mats, shapes
