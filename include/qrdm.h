@@ -1,0 +1,162 @@
+/*
+ * qrdm.h -- C ABI of libqrdm.so: rank-revealing QR with Deviation
+ * Maximization pivoting (QRDM) and with classical column pivoting (QRP) on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: M. Dessole, F. Marcuzzi, "Deviation Maximization for Rank-Revealing
+ * QR Factorizations", arXiv 2106.03138.  QRDM computes A*P = Q*R (Section 3,
+ * eq. QRpivoting) by Algorithm 4 (QRDM2): the Deviation Maximization block
+ * column choice (Algorithm 1), a Householder panel that stops early when a
+ * column is nearly dependent (eq. lenght_check), a compact-WY trailing update
+ * and the partial column norm update.  QRP is Algorithm 2 (Section 3.1), the
+ * column-at-a-time pivoting that LAPACK xgeqp3 implements.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are double precision, column-major, leading dimension lda >= m
+ *     (LAPACK layout).  All array pointers are DEVICE pointers unless marked
+ *     "host".  The caller allocates and owns every argument array; the library
+ *     owns only an internal workspace cached per device (qrdm_release frees it).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *     on it; entry points that return host values (rank, stats) synchronize it.
+ *   - Output layout (same as LAPACK xgeqp3): R on and above the diagonal; the
+ *     Householder vectors v_i (v_i[i] = 1 implicit) below the diagonal of the
+ *     first `rank` columns; tau_house[i] the scalar of H_i = I - tau_i v_i v_i^T
+ *     (tau_house[i] = 0 for i >= number of reflectors); perm[j] (0-based) the
+ *     original index of the column now at position j, so A_in[:, perm] = Q R.
+ *     When the stopping criterion ends the factorization at rank r < min(m,n),
+ *     rows/columns >= r hold the updated trailing block R22 (not triangular),
+ *     so A_in[:, perm] = Q [R11 R12; 0 R22] exactly.
+ *   - Return codes: 0 = success; -i = the i-th argument is invalid (checked
+ *     before any launch; nothing is written); QRDM_ERR_* > 0 otherwise.
+ *   - Calls are not re-entrant: two concurrent calls on one device share the
+ *     cached workspace and must be serialized by the caller.
+ */
+#ifndef QRDM_H
+#define QRDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QRDM_OK 0
+#define QRDM_ERR_NONFINITE 1   /* NaN/Inf in A (or a column norm overflows); A unchanged */
+#define QRDM_ERR_NOMEM 2       /* workspace allocation failed; nothing written            */
+#define QRDM_ERR_UNSUPPORTED 3 /* size outside what the kernels support (see below)      */
+#define QRDM_ERR_HIP 1000      /* QRDM_ERR_HIP + hipError_t of a failed runtime call      */
+
+/* Stopping criterion, Section 3.4, eq. (practical stopping criterion). */
+#define QRDM_STOP_PAPER 0   /* stop when sqrt(n-n_s) max_i||c_i|| <= eps_1 max_i||a_i||     */
+#define QRDM_STOP_MAXNORM 1 /* stop when max_i||c_i|| <= eps_1 max_i||a_i||                 */
+#define QRDM_STOP_NONE 2    /* full factorization; rank = where the PAPER test first held  */
+
+#define QRDM_PREC_FP64 0  /* everything in FP64; trailing update on FP64 MFMA             */
+#define QRDM_PREC_MIXED 1 /* trailing update on FP32 MFMA with FP32 accumulation; panel,
+                             norms, recompute and the rank decision stay FP64              */
+
+#define QRDM_KMAX_LIMIT 128 /* largest supported block size k_DM                          */
+
+typedef struct {
+    double tau;         /* candidate threshold, Algorithm 1; 0 < tau <= 1 (default 0.15)  */
+    double delta;       /* cosine bound, Algorithm 1; 0 <= delta <= 1 (default 0.9)      */
+    int32_t kmax;       /* block size k_DM, eq. (candidate_set_limited_by_kDM); 1..128 (64) */
+    int32_t stop_rule;  /* QRDM_STOP_* (default QRDM_STOP_PAPER)                          */
+    double eps1_scale;  /* eps_1 = eps1_scale * eps_w; <= 0 selects n (eq. choice1), where
+                           eps_w = 2^-52 in FP64 mode and 2^-23 (FP32) in mixed mode; the
+                           switch to scalar pivoting uses max partial norm <= n eps_w amax */
+    int32_t precision;  /* QRDM_PREC_* (default FP64)                                     */
+    int32_t poll_lag;   /* host polls the device loop state this many blocks behind
+                           (0 = synchronize every block; default 4)                       */
+    int32_t profile;    /* 1 = time the trailing GEMMs with HIP events on `stream`
+                           (results in qrdm_stats; adds event overhead); default 0        */
+} qrdm_params;
+
+typedef struct {
+    int64_t nblocks;     /* outer steps executed                                          */
+    int64_t nbreaks;     /* blocks whose panel stopped early (l < k_s)                    */
+    int64_t nfallback;   /* scalar-pivoting steps, eq. (column_norm_bound_DM)             */
+    int64_t nrecompute;  /* partial norms recomputed from the data                        */
+    int64_t ncols_factored; /* number of reflectors applied                               */
+    /* filled when params.profile = 1 (zero otherwise):                                    */
+    double gemm1_ms;     /* summed event time of the V^T A GEMM launches                   */
+    double gemm2_ms;     /* summed event time of the A -= V Z GEMM launches                */
+    double gemm_flop;    /* algorithmic flops of ONE of the two GEMMs, summed over blocks:
+                            sum 2 t l w (t rows, l reflectors, w trailing columns)         */
+    double total_ms;     /* event time of the whole factorization loop                    */
+} qrdm_stats;
+
+/* One record per outer step, for tests and tracing. */
+typedef struct {
+    int64_t ns;       /* columns factored before this step */
+    int32_t nL;       /* candidate list length             */
+    int32_t ks;       /* accepted columns                  */
+    int32_t l;        /* reflectors kept after the break   */
+    int32_t fallback; /* 1 = scalar pivoting step          */
+    double umax;      /* max partial norm at selection     */
+} qrdm_block;
+
+/* Fills *p with the paper's defaults: tau = 0.15, delta = 0.9 (Section 5) and
+ * k_DM = 64 (Section 5, block size study); stop rule PAPER, eps_1 = eps*n. */
+void qrdm_default_params(qrdm_params *p);
+
+/*
+ * QRDM, Algorithm 4 (QRDM2) with Algorithm 1 (DM), FP64, stop rule PAPER.
+ *   A          [in/out] m x n, lda >= max(1,m); overwritten by R and the reflectors.
+ *   tau_house  [out] min(m,n) doubles.
+ *   perm       [out] n int32.
+ *   rank       [out, host] numerical rank from eq. (practical stopping criterion).
+ * Supported sizes: m, n <= 32768 columns for the selection; m <= 65536.
+ */
+int qrdm_factor(double *A, int64_t m, int64_t n, int64_t lda, double tau, double delta,
+                int32_t kmax, double *tau_house, int32_t *perm, int64_t *rank, void *stream);
+
+/*
+ * QRDM with all parameters.  stats (host, may be NULL) receives counters.
+ * log (host, may be NULL) receives up to log_cap block records and *nlog the
+ * number of blocks; passing a log forces poll_lag = 0.
+ */
+int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p,
+                   double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats,
+                   qrdm_block *log, int64_t log_cap, int64_t *nlog, void *stream);
+
+/*
+ * QRP, Algorithm 2 (Section 3.1), blocked like LAPACK xgeqp3: one pivot per
+ * step with the partial norm update; the trailing matrix is updated every
+ * `nb` columns with a BLAS-3 product.  Same outputs and rank rule as
+ * qrdm_factor (stop_rule from p, may be NULL for PAPER).
+ */
+int qrp_factor(double *A, int64_t m, int64_t n, int64_t lda, double *tau_house, int32_t *perm,
+               int64_t *rank, void *stream);
+int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p, int32_t nb,
+                  double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats, void *stream);
+
+/*
+ * Column 2-norms of A (device out[n]), the first step of Algorithm 4.
+ * Returns QRDM_ERR_NONFINITE if any column holds NaN/Inf.
+ */
+int qrdm_colnorms(const double *A, int64_t m, int64_t n, int64_t lda, double *out, void *stream);
+
+/*
+ * One Deviation Maximization step (Algorithm 1) on the trailing block
+ * [A]_{ns:m, ns:n} given its partial norms vn1 (device, n entries, entries
+ * >= ns are read), exactly as the factorization performs it.  Host outputs:
+ * L[kmax] candidate list (norm desc, position asc), *nL, theta[kmax*kmax]
+ * (row-major nL x nL cosine matrix, may be NULL), J[kmax] accepted columns,
+ * *ks.  A is not modified.
+ */
+int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns, const double *vn1,
+                 double tau, double delta, int32_t kmax, int32_t *L, int32_t *nL, double *theta,
+                 int32_t *J, int32_t *ks, void *stream);
+
+/* Frees the workspace cached for the current device. */
+void qrdm_release(void);
+
+/* Text for a return code (static storage). */
+const char *qrdm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QRDM_H */

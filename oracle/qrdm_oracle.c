@@ -103,6 +103,14 @@ static double rel_margin(double a, double b) {
     return fabs(a - b) / s;
 }
 
+/* Margin of a decision between a and b when both carry an absolute rounding
+ * noise of about nu: 0 if |a - b| <= nu (a noise-level decision, which two
+ * correct implementations may take differently), else the relative margin. */
+static double noise_margin(double a, double b, double nu) {
+    if (fabs(a - b) <= nu) return 0.0;
+    return rel_margin(a, b);
+}
+
 /* Column 2-norm of x[0..len): plain sum of squares (R9). */
 static double norm2(const double *x, int64_t len) {
     double s = 0.0;
@@ -131,7 +139,7 @@ static int cand_cmp(const void *pa, const void *pb) {
 static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
                       const double *vn1, double tau, double delta, int64_t cap,
                       int64_t *L, int *nL, double *theta, int64_t *J, int *ks,
-                      oracle_block *rec, cand_t *work, double *G) {
+                      oracle_block *rec, cand_t *work, double *G, double nu) {
     int64_t t = m - ns;
     /* step 1: J = { argmax u }, lowest position on ties (R2) */
     int64_t jmax = ns;
@@ -143,7 +151,7 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
     int64_t nc = 0;
     double mthr = INFINITY;
     for (int64_t j = ns; j < n; ++j) {
-        mthr = fmin(mthr, rel_margin(vn1[j], thr));
+        mthr = fmin(mthr, noise_margin(vn1[j], thr, nu));
         if (vn1[j] >= thr) { work[nc].v = vn1[j]; work[nc].j = j; ++nc; }
     }
     /* Section 4: order by norm (sort), keep the first min(k, k_DM) (R3, R4) */
@@ -151,7 +159,7 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
     int64_t nl = nc < cap ? nc : cap;
     double morder = INFINITY;
     int64_t nchk = nc < cap + 1 ? nc : cap + 1;
-    for (int64_t a = 0; a + 1 < nchk; ++a) morder = fmin(morder, rel_margin(work[a + 1].v, work[a].v));
+    for (int64_t a = 0; a + 1 < nchk; ++a) morder = fmin(morder, noise_margin(work[a + 1].v, work[a].v, nu));
     for (int64_t a = 0; a < nl; ++a) L[a] = work[a].j;
     *nL = (int)nl;
     /* step 4: cosine matrix, Theta = D^-1 (C^T C) D^-1 with C = [A]_{ns:m, L} (R5) */
@@ -189,7 +197,17 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
             if (th > worst) worst = th;
             if (!(th < delta)) ok = 0;
         }
-        if (da > 0.0) mcos = fmin(mcos, fabs(worst - delta));
+        if (da > 0.0) {
+            /* a cosine of columns of norm d carries an error of about nu/d */
+            double dmin = da;
+            for (int b = 0; b < k; ++b) {
+                int64_t bi = 0;
+                while (L[bi] != J[b]) ++bi;
+                dmin = fmin(dmin, sqrt(G[bi * nl + bi]));
+            }
+            double mc = fabs(worst - delta);
+            mcos = fmin(mcos, (mc <= nu / dmin) ? 0.0 : mc);
+        }
         if (ok) J[k++] = L[a];
     }
     *ks = k;
@@ -276,6 +294,10 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
         vn2[j] = vn1[j];
         if (vn1[j] > amax) amax = vn1[j];
     }
+    /* absolute rounding-noise scale of partial norms, for the margins only */
+    double fro2 = 0.0;
+    for (int64_t j = 0; j < n; ++j) fro2 += vn1[j] * vn1[j];
+    const double nu = 4.0 * O_EPS * sqrt(fro2);
     int64_t rank = -1;
     if (amax == 0.0) { /* R15 */
         *rank_out = 0;
@@ -300,7 +322,8 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
         if (rank < 0) {
             double lhs = (prm->stop_rule == O_STOP_MAXNORM) ? umax : sqrt((double)(n - ns)) * umax;
             double rhs = eps1 * amax;
-            rec.m_stop = rel_margin(lhs, rhs);
+            double nu_l = (prm->stop_rule == O_STOP_MAXNORM) ? nu : sqrt((double)(n - ns)) * nu;
+            rec.m_stop = (fabs(lhs - rhs) <= nu_l) ? 0.0 : rel_margin(lhs, rhs);
             if (lhs <= rhs) {
                 rank = ns;
                 if (prm->stop_rule != O_STOP_NONE) {
@@ -312,7 +335,7 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
         }
         /* eq. (column_norm_bound_DM): scalar pivoting near the noise level (R13) */
         double fb_thr = O_EPS * (double)n * amax;
-        rec.m_fb = rel_margin(umax, fb_thr);
+        rec.m_fb = noise_margin(umax, fb_thr, nu);
         int64_t cap = kcap < (p - ns) ? kcap : (p - ns);
         int ks = 1, nl = 1;
         if (umax <= fb_thr || cap == 1) {
@@ -323,10 +346,10 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
             double second = -1.0;
             for (int64_t j = ns; j < n; ++j)
                 if (j != jmax && vn1[j] > second) second = vn1[j];
-            rec.m_order = (second >= 0.0) ? rel_margin(second, umax) : INFINITY;
+            rec.m_order = (second >= 0.0) ? noise_margin(second, umax, nu) : INFINITY;
             rec.ncand = 1; rec.nL = 1; rec.jmax = (int32_t)jmax; rec.umax = umax;
         } else {
-            dm_select(A, m, n, lda, ns, vn1, prm->tau, prm->delta, cap, L, &nl, NULL, J, &ks, &rec, work, G);
+            dm_select(A, m, n, lda, ns, vn1, prm->tau, prm->delta, cap, L, &nl, NULL, J, &ks, &rec, work, G, nu);
         }
         /* eq. (lenght_check): eps_s = tau * max u (R12) */
         double eps_s = prm->tau * umax;
@@ -354,7 +377,7 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
             for (int64_t r = 1; r < len; ++r) sp += x[r] * x[r];
             double nrm = sqrt(alpha * alpha + sp);
             if (i >= 1) {
-                mbreak = fmin(mbreak, rel_margin(nrm, eps_s));
+                mbreak = fmin(mbreak, noise_margin(nrm, eps_s, nu));
                 if (nrm < eps_s) break;
             }
             double beta, ti;
@@ -497,7 +520,7 @@ int oracle_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t n
     double *G = malloc(sizeof(double) * (size_t)(cap * cap));
     if (!work || !G) { free(work); free(G); return O_ERR_NOMEM; }
     int nl = 0, k = 0;
-    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, L, &nl, theta, J, &k, NULL, work, G);
+    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, L, &nl, theta, J, &k, NULL, work, G, 0.0);
     *nL = nl;
     *ks = k;
     free(work);

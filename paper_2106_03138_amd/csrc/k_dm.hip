@@ -1,0 +1,591 @@
+// Deviation Maximization block column selection (Algorithm 1 of the paper,
+// with the implementation choices of Section 4) on gfx950.
+//
+//  k_select       one workgroup: n_s <- n_s + l; max partial norm and its
+//                 position; stopping test (eq. practical stopping criterion);
+//                 switch to scalar pivoting near the noise level (eq.
+//                 column_norm_bound_DM); the candidate list
+//                 {j : u_j >= tau max u} (eq. def_candidate_set) in norm order,
+//                 cut to k_DM entries (eq. candidate_set_limited_by_kDM) by a
+//                 radix select on the IEEE bit patterns of the norms.
+//  k_gram         C = A[n_s:m, L] gathered into LDS, partial Gram C^T C on
+//                 FP64 MFMA (16x16x4), one partial per row slab.
+//  k_gram_reduce  fixed-order sum of the partials.
+//  k_dm_finish    cosines Theta = D^-1 G D^-1 with D = sqrt(diag G) (Section 4,
+//                 option (ii)), greedy |theta| < delta acceptance in candidate
+//                 order, and the column transpositions of Section 4 ("swap
+//                 column n_s+i with column j_i"), simulated in registers of one
+//                 wavefront; vn1/vn2/perm are permuted here.
+//  k_swap         moves the affected columns of A (all m rows) through LDS.
+#include <float.h>
+
+#include "qrdm_internal.h"
+
+// ============================================================== k_select
+#define SEL_THREADS 1024
+#define SEL_WAVES (SEL_THREADS / 64)
+#define SEL_KEYS 32  // keys per thread: supports n - n_s <= 32768
+
+__device__ __forceinline__ bool better(double va, int ja, double vb, int jb) {
+    return va > vb || (va == vb && ja < jb);
+}
+
+// exclusive prefix sum over the 1024 threads (position order = thread order)
+__device__ int block_excl_scan(int v, int *wsum, int *total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < SEL_WAVES; ++i) {
+            int x = wsum[i];
+            wsum[i] = acc;
+            acc += x;
+        }
+        *total = acc;
+    }
+    __syncthreads();
+    int r = wsum[w] + incl - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
+    QrdmCtl *ctl = a.ctl;
+    __shared__ double s_bv[SEL_WAVES];
+    __shared__ int s_bj[SEL_WAVES];
+    __shared__ int s_wsum[SEL_WAVES];
+    __shared__ int s_total;
+    __shared__ int s_hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_krem;
+    __shared__ double s_cv[QK_KM];
+    __shared__ int s_cj[QK_KM];
+    __shared__ int s_branch;  // 0 = stop, 1 = single pivot, 2 = DM list
+    __shared__ double s_umax;
+    __shared__ int s_jmax;
+
+    const int tid = threadIdx.x;
+    if (ctl->done) return;
+    const int64_t ns = ctl->ns + ctl->l;
+    const int64_t nblk = ctl->nblocks;
+    __syncthreads();
+    const int64_t p = p_of(a);
+    if (tid == 0) {
+        ctl->ns = ns;
+        ctl->l = 0;
+        ctl->ks = 0;
+        ctl->nL = 0;
+        ctl->nswap = 0;
+        ctl->bar = 0;
+        ctl->bar2 = 0;
+        ctl->fallback = 0;
+    }
+    if (ns >= p) {
+        if (tid == 0) {
+            ctl->done = 1;
+            if (ctl->rank < 0) ctl->rank = ns;
+        }
+        return;
+    }
+    const int64_t w = a.n - ns;
+    const int chunk = (int)((w + SEL_THREADS - 1) / SEL_THREADS);
+    const int64_t j0 = ns + (int64_t)tid * chunk;
+    double keys[SEL_KEYS];
+#pragma unroll
+    for (int q = 0; q < SEL_KEYS; ++q) {
+        int64_t j = j0 + q;
+        keys[q] = (q < chunk && j < a.n) ? a.vn1[j] : -1.0;  // -1 marks "no column"
+    }
+    // ---- max partial norm, lowest position on ties
+    double bv = -1.0;
+    int bj = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < SEL_KEYS; ++q)
+        if (keys[q] > bv) { bv = keys[q]; bj = (int)(j0 + q); }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(bv, o, 64);
+        int oj = __shfl_xor(bj, o, 64);
+        if (better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
+    }
+    if ((tid & 63) == 0) { s_bv[tid >> 6] = bv; s_bj[tid >> 6] = bj; }
+    __syncthreads();
+    if (tid == 0) {
+        double uv = s_bv[0];
+        int uj = s_bj[0];
+        for (int i = 1; i < SEL_WAVES; ++i)
+            if (better(s_bv[i], s_bj[i], uv, uj)) { uv = s_bv[i]; uj = s_bj[i]; }
+        double amax = ctl->amax;
+        if (nblk == 0) { amax = uv; ctl->amax = amax; }
+        int branch = 2;
+        if (amax == 0.0) {
+            ctl->rank = 0;
+            branch = 0;
+        } else if (ctl->rank < 0) {
+            double lhs = (a.stop_rule == 1) ? uv : sqrt((double)(a.n - ns)) * uv;
+            if (lhs <= a.eps1 * amax) {
+                ctl->rank = ns;
+                if (a.stop_rule != 2) branch = 0;
+            }
+        }
+        int64_t cap = a.kmax < (p - ns) ? a.kmax : (p - ns);
+        if (branch == 2) {
+            bool fb = uv <= a.fbeps * amax;
+            if (fb || cap == 1) {
+                branch = 1;
+                ctl->fallback = fb ? 1 : 0;
+                if (fb) ctl->nfallback += 1;
+            }
+        }
+        if (branch == 0) {
+            ctl->done = 1;
+        } else {
+            ctl->umax = uv;
+            ctl->jmax = uj;
+            ctl->eps_s = a.tau * uv;
+            ctl->nblocks = nblk + 1;
+        }
+        if (branch == 1) {
+            ctl->L[0] = uj;
+            ctl->nL = 1;
+        }
+        s_branch = branch;
+        s_umax = uv;
+        s_jmax = uj;
+    }
+    __syncthreads();
+    if (s_branch != 2) return;
+    const double thr = a.tau * s_umax;
+    const int cap = (int)(a.kmax < (p - ns) ? a.kmax : (p - ns));
+    // ---- count candidates
+    int cnt = 0;
+#pragma unroll
+    for (int q = 0; q < SEL_KEYS; ++q) cnt += (keys[q] >= thr) ? 1 : 0;
+    int off = block_excl_scan(cnt, s_wsum, &s_total);
+    const int total = s_total;
+    int nsel;
+    if (total <= cap) {
+        int pos = off;
+#pragma unroll
+        for (int q = 0; q < SEL_KEYS; ++q)
+            if (keys[q] >= thr) { s_cv[pos] = keys[q]; s_cj[pos] = (int)(j0 + q); ++pos; }
+        nsel = total;
+    } else {
+        // radix select of the cap-th largest key (bit patterns of non-negative
+        // doubles order like the values)
+        unsigned long long prefix = 0, pmask = 0;
+        if (tid == 0) s_krem = cap;
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            if (tid < 256) s_hist[tid] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < SEL_KEYS; ++q) {
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(keys[q]);
+                const bool in = (keys[q] >= thr) && ((kb & pmask) == prefix);
+                const int dg = (int)((kb >> shift) & 255);
+                // lanes sharing the first active lane's digit add once (keys cluster
+                // in few bins); the others add individually
+                const unsigned long long act = __ballot(in);
+                if (act) {
+                    const int lead = __ffsll((long long)act) - 1;
+                    const int ld = __shfl(dg, lead, 64);
+                    const unsigned long long same = __ballot(in && dg == ld);
+                    if ((threadIdx.x & 63) == lead) atomicAdd(&s_hist[ld], __popcll(same));
+                    if (in && dg != ld) atomicAdd(&s_hist[dg], 1);
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {
+                // bins in descending digit order; lane handles 4 consecutive
+                const int krem = s_krem;
+                int h[4];
+                int ls = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) { h[u] = s_hist[255 - (4 * tid + u)]; ls += h[u]; }
+                int incl = ls;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    int y = __shfl_up(incl, o, 64);
+                    if (tid >= o) incl += y;
+                }
+                int excl = incl - ls;
+                if (excl < krem && krem <= incl) {
+                    int c = excl, found = 0, dig = 0, before = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool hit = !found && (c + h[u] >= krem);
+                        if (hit) { found = 1; dig = 255 - (4 * tid + u); before = c; }
+                        c += h[u];
+                    }
+                    s_krem = krem - before;
+                    s_prefix = prefix | ((unsigned long long)dig << shift);
+                }
+            }
+            __syncthreads();
+            prefix = s_prefix;
+            pmask |= (255ull << shift);
+            __syncthreads();
+        }
+        const int need_eq = s_krem;  // keys equal to the cut value to take
+        const int ngt = cap - need_eq;
+        int cgt = 0, ceq = 0;
+#pragma unroll
+        for (int q = 0; q < SEL_KEYS; ++q) {
+            if (keys[q] >= 0.0) {
+                unsigned long long kb = (unsigned long long)__double_as_longlong(keys[q]);
+                cgt += (kb > prefix) ? 1 : 0;
+                ceq += (kb == prefix) ? 1 : 0;
+            }
+        }
+        int ogt = block_excl_scan(cgt, s_wsum, &s_total);
+        int oeq = block_excl_scan(ceq, s_wsum, &s_total);
+#pragma unroll
+        for (int q = 0; q < SEL_KEYS; ++q) {
+            if (keys[q] >= 0.0) {
+                unsigned long long kb = (unsigned long long)__double_as_longlong(keys[q]);
+                if (kb > prefix) {
+                    s_cv[ogt] = keys[q]; s_cj[ogt] = (int)(j0 + q); ++ogt;
+                } else if (kb == prefix) {
+                    if (oeq < need_eq) { s_cv[ngt + oeq] = keys[q]; s_cj[ngt + oeq] = (int)(j0 + q); }
+                    ++oeq;
+                }
+            }
+        }
+        nsel = cap;
+    }
+    __syncthreads();
+    // ---- order the list: norm descending, position ascending
+    if (tid < nsel) {
+        const double v = s_cv[tid];
+        const int j = s_cj[tid];
+        int r = 0;
+        for (int e = 0; e < nsel; ++e) r += better(s_cv[e], s_cj[e], v, j) ? 1 : 0;
+        ctl->L[r] = j;
+    }
+    if (tid == 0) ctl->nL = nsel;
+}
+
+hipError_t launch_select(QrdmArgs a, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(SEL_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+// ================================================================ k_gram
+#define GR_ROWS 256   // rows of C per workgroup
+#define GR_CHUNK 64   // rows staged in LDS at a time
+#define GR_LD (GR_CHUNK + 1)
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gram(QrdmArgs a, double *Gp) {
+    const QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int nL = ctl->nL;
+    if (nL <= 1) return;
+    const int64_t ns = ctl->ns;
+    const int64_t t = a.m - ns;
+    const int64_t r0 = (int64_t)blockIdx.x * GR_ROWS;
+    if (r0 >= t) return;
+    __shared__ double Cs[QK_KM * GR_LD];
+    __shared__ int sL[QK_KM];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nt = (nL + 15) >> 4;  // 16-wide tiles per dimension
+    const int nLp = nt * 16;
+    for (int q = tid; q < nLp; q += 256) sL[q] = (q < nL) ? ctl->L[q] : -1;
+    dbl4 acc[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int ntiles = nt * nt;
+    const int64_t rend = (r0 + GR_ROWS < t) ? r0 + GR_ROWS : t;
+    __syncthreads();
+    // chunk element u*256 + tid -> column q = u*4 + tid/64, row r = tid%64
+    const int rr = tid & 63, qq = tid >> 6;
+    double creg[32];
+    auto fetch = [&](int64_t rc) {
+        const int64_t row = rc + rr;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int q = u * 4 + qq;
+            const int col = (q < nLp) ? sL[q] : -1;
+            creg[u] = (col >= 0 && row < rend) ? a.A[(int64_t)col * a.lda + ns + row] : 0.0;
+        }
+    };
+    fetch(r0);
+    for (int64_t rc = r0; rc < rend; rc += GR_CHUNK) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int q = u * 4 + qq;
+            if (q < nLp) Cs[q * GR_LD + rr] = creg[u];
+        }
+        __syncthreads();
+        if (rc + GR_CHUNK < rend) fetch(rc + GR_CHUNK);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int tile = wv + 4 * u;
+            if (tile < ntiles) {
+                const int ti = tile / nt, tj = tile % nt;
+                const double *ca = Cs + (ti * 16 + (lane & 15)) * GR_LD + (lane >> 4);
+                const double *cb = Cs + (tj * 16 + (lane & 15)) * GR_LD + (lane >> 4);
+#pragma unroll 4
+                for (int k = 0; k < GR_CHUNK; k += 4) {
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[k], cb[k], acc[u], 0, 0, 0);
+                }
+            }
+        }
+    }
+    double *out = Gp + (int64_t)blockIdx.x * QK_KM * QK_KM;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int tile = wv + 4 * u;
+        if (tile < ntiles) {
+            const int ti = tile / nt, tj = tile % nt;
+            const int col = tj * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // f64 16x16x4 MFMA: register v of lane holds D[4v + lane/16][lane%16]
+                const int row = ti * 16 + 4 * v + (lane >> 4);
+                out[row * QK_KM + col] = acc[u][v];
+            }
+        }
+    }
+}
+
+hipError_t launch_gram(QrdmArgs a, double *Gp, int64_t t_bound, hipStream_t s) {
+    if (t_bound <= 0) return hipSuccess;
+    dim3 grid((unsigned)((t_bound + GR_ROWS - 1) / GR_ROWS));
+    hipLaunchKernelGGL(k_gram, grid, dim3(256), 0, s, a, Gp);
+    return hipGetLastError();
+}
+
+int gram_partials(int64_t t_bound) { return (int)((t_bound + GR_ROWS - 1) / GR_ROWS); }
+
+__global__ void __launch_bounds__(256) k_gram_reduce(QrdmArgs a, const double *Gp, double *G) {
+    const QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int nL = ctl->nL;
+    if (nL <= 1) return;
+    const int64_t t = a.m - ctl->ns;
+    const int np = (int)((t + GR_ROWS - 1) / GR_ROWS);
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= nL * nL) return;
+    const int i = e / nL, j = e % nL;
+    double s = 0.0;
+    for (int w = 0; w < np; ++w) s += Gp[(int64_t)w * QK_KM * QK_KM + i * QK_KM + j];
+    G[i * QK_KM + j] = s;
+}
+
+hipError_t launch_gram_reduce(QrdmArgs a, const double *Gp, double *G, int64_t t_bound, hipStream_t s) {
+    (void)t_bound;
+    int kk = a.kmax < QK_KM ? a.kmax : QK_KM;
+    dim3 grid((unsigned)((kk * kk + 255) / 256));
+    hipLaunchKernelGGL(k_gram_reduce, grid, dim3(256), 0, s, a, Gp, G);
+    return hipGetLastError();
+}
+
+// ============================================================= k_dm_finish
+__device__ __forceinline__ int sel4(int r0, int r1, int r2, int r3, int k) {
+    return k == 0 ? r0 : (k == 1 ? r1 : (k == 2 ? r2 : r3));
+}
+
+__global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, double *theta_out) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    __shared__ double sd[QK_KM];
+    __shared__ double sG[QK_KM * QK_KM];
+    __shared__ int sJ[QK_KM];
+    __shared__ int sjslot[QK_KM];
+    __shared__ int soutpos[QK_KM];
+    __shared__ int s_ks;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nL = ctl->nL;
+    const int64_t ns = ctl->ns;
+    if (nL > 1) {
+        for (int base = 0; base < nL * nL; base += 256 * 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                v[u] = (e < nL * nL) ? G[(e / nL) * QK_KM + (e % nL)] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = base + u * 256 + tid;
+                if (e < nL * nL) sG[(e / nL) * QK_KM + (e % nL)] = v[u];
+            }
+        }
+        __syncthreads();
+        G = sG;
+        for (int q = tid; q < nL; q += 256) sd[q] = sqrt(G[q * QK_KM + q]);
+        __syncthreads();
+        if (theta_out) {
+            for (int e = tid; e < nL * nL; e += 256) {
+                int i = e / nL, j = e % nL;
+                theta_out[e] = G[i * QK_KM + j] / (sd[i] * sd[j]);
+            }
+        }
+        if (tid < 64) {
+            // greedy acceptance in candidate order, one wavefront; lane owns
+            // candidates lane and lane+64
+            bool acc0 = (lane == 0), acc1 = false;
+            for (int i = 1; i < nL; ++i) {
+                const double di = sd[i];
+                bool bad = false;
+                if (lane < i && acc0) {
+                    double th = fabs(G[i * QK_KM + lane] / (di * sd[lane]));
+                    bad = !(th < a.delta);
+                }
+                if (lane + 64 < i && acc1) {
+                    double th = fabs(G[i * QK_KM + lane + 64] / (di * sd[lane + 64]));
+                    bad = bad || !(th < a.delta);
+                }
+                const bool any_bad = __any(bad);
+                const bool ok = !any_bad && (di > 0.0);
+                if (ok) {
+                    if (i == lane) acc0 = true;
+                    if (i == lane + 64) acc1 = true;
+                }
+            }
+            // compact accepted candidates in order
+            unsigned long long b0 = __ballot(acc0), b1 = __ballot(acc1);
+            int c0 = __popcll(b0);
+            if (acc0) sJ[__popcll(b0 & ((1ull << lane) - 1))] = ctl->L[lane];
+            if (acc1) sJ[c0 + __popcll(b1 & ((1ull << lane) - 1))] = ctl->L[lane + 64];
+            if (lane == 0) s_ks = c0 + __popcll(b1);
+        }
+    } else {
+        if (tid == 0) { sJ[0] = ctl->L[0]; s_ks = 1; }
+    }
+    __syncthreads();
+    const int ks = s_ks;
+    // ---- transpositions: for i = 0..ks-1 swap position ns+i with the current
+    // position of column J_i.  Slots: 0..ks-1 = positions ns..ns+ks-1, then the
+    // accepted columns outside that range in list order.
+    if (tid < 64) {
+        int nout = 0;
+        for (int base = 0; base < ks; base += 64) {
+            const int i = base + lane;
+            const bool valid = i < ks;
+            const int jp = valid ? sJ[i] : 0;
+            const bool outside = valid && (jp >= ns + ks);
+            unsigned long long bo = __ballot(outside);
+            const int oi = nout + __popcll(bo & ((1ull << lane) - 1));
+            if (valid) {
+                sjslot[i] = outside ? ks + oi : (int)(jp - ns);
+                if (outside) soutpos[oi] = jp;
+            }
+            nout += __popcll(bo);
+        }
+        const int nslots = ks + nout;
+        // cont[s]: slot whose original column sits in slot s; posof[c]: slot of column c
+        int c0 = lane, c1 = lane + 64, c2 = lane + 128, c3 = lane + 192;
+        int p0 = c0, p1 = c1, p2 = c2, p3 = c3;
+        for (int i = 0; i < ks; ++i) {
+            const int js = sjslot[i];
+            const int ps = i;
+            const int q = __shfl(sel4(p0, p1, p2, p3, js >> 6), js & 63, 64);
+            const int c = __shfl(sel4(c0, c1, c2, c3, ps >> 6), ps & 63, 64);
+            // cont[ps] = js; cont[q] = c; posof[c] = q; posof[js] = ps
+            if (lane == (ps & 63)) {
+                int k = ps >> 6;
+                if (k == 0) c0 = js; else if (k == 1) c1 = js; else if (k == 2) c2 = js; else c3 = js;
+            }
+            if (lane == (q & 63)) {
+                int k = q >> 6;
+                if (k == 0) c0 = c; else if (k == 1) c1 = c; else if (k == 2) c2 = c; else c3 = c;
+            }
+            if (lane == (c & 63)) {
+                int k = c >> 6;
+                if (k == 0) p0 = q; else if (k == 1) p1 = q; else if (k == 2) p2 = q; else p3 = q;
+            }
+            if (lane == (js & 63)) {
+                int k = js >> 6;
+                if (k == 0) p0 = ps; else if (k == 1) p1 = ps; else if (k == 2) p2 = ps; else p3 = ps;
+            }
+        }
+        // moves: slot s receives the column that was at slot cont[s]
+        int nmv = 0;
+        double ov1[4], ov2[4];
+        int opm[4], dpos[4], spos[4];
+        bool mv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = lane + 64 * u;
+            const int cs = sel4(c0, c1, c2, c3, u);
+            mv[u] = (sl < nslots) && (cs != sl);
+            dpos[u] = (sl < ks) ? (int)(ns + sl) : (sl < nslots ? soutpos[sl - ks] : 0);
+            spos[u] = (cs < ks) ? (int)(ns + cs) : (cs < nslots ? soutpos[cs - ks] : 0);
+            if (mv[u]) {
+                ov1[u] = a.vn1[spos[u]];
+                ov2[u] = a.vn2[spos[u]];
+                opm[u] = a.perm[spos[u]];
+            }
+        }
+        __builtin_amdgcn_s_barrier();  // single wave: orders the reads above before the writes
+        __threadfence_block();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            unsigned long long bm = __ballot(mv[u]);
+            const int o = nmv + __popcll(bm & ((1ull << lane) - 1));
+            if (mv[u]) {
+                a.vn1[dpos[u]] = ov1[u];
+                a.vn2[dpos[u]] = ov2[u];
+                a.perm[dpos[u]] = opm[u];
+                ctl->swp_dst[o] = dpos[u];
+                ctl->swp_src[o] = spos[u];
+            }
+            nmv += __popcll(bm);
+        }
+        if (lane == 0) {
+            ctl->nswap = nmv;
+            ctl->ks = ks;
+        }
+        for (int i = lane; i < ks; i += 64) ctl->J[i] = sJ[i];
+    }
+}
+
+hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dm_finish, dim3(1), dim3(256), 0, s, a, G, theta_out);
+    return hipGetLastError();
+}
+
+// ================================================================= k_swap
+#define SW_ROWS 32
+
+__global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
+    const QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int nsw = ctl->nswap;
+    if (nsw == 0) return;
+    const int64_t r0 = (int64_t)blockIdx.x * SW_ROWS;
+    if (r0 >= a.m) return;
+    __shared__ double buf[QK_SWAP_MAX * SW_ROWS];
+    __shared__ int sdst[QK_SWAP_MAX], ssrc[QK_SWAP_MAX];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nsw; e += 256) { sdst[e] = ctl->swp_dst[e]; ssrc[e] = ctl->swp_src[e]; }
+    __syncthreads();
+    const int rows = (int)((a.m - r0) < SW_ROWS ? (a.m - r0) : SW_ROWS);
+    for (int idx = tid; idx < nsw * SW_ROWS; idx += 256) {
+        const int e = idx / SW_ROWS, r = idx % SW_ROWS;
+        if (r < rows) buf[idx] = a.A[(int64_t)ssrc[e] * a.lda + r0 + r];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nsw * SW_ROWS; idx += 256) {
+        const int e = idx / SW_ROWS, r = idx % SW_ROWS;
+        if (r < rows) a.A[(int64_t)sdst[e] * a.lda + r0 + r] = buf[idx];
+    }
+}
+
+hipError_t launch_swap(QrdmArgs a, hipStream_t s) {
+    dim3 grid((unsigned)((a.m + SW_ROWS - 1) / SW_ROWS));
+    hipLaunchKernelGGL(k_swap, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}

@@ -1,0 +1,452 @@
+// Host driver and C ABI of libqrdm.so (declared in include/qrdm.h).
+//
+// The outer loop of Algorithm 4 (QRDM2) is a fixed sequence of kernel
+// launches per block; the loop state (n_s, k_s, l, the stop decision, the
+// candidate and accepted lists) lives in a device control block and never
+// crosses to the host during the loop.  Grids are sized from a lower bound on
+// n_s that the host learns by polling a small snapshot of the control block
+// `poll_lag` blocks behind the launch front; kernels of blocks enqueued after
+// the loop has finished exit at once.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/qrdm.h"
+#include "qrdm_internal.h"
+
+int gram_partials(int64_t t_bound);
+int panel_lds_bytes(int rows_per_wg, int kmax);
+
+namespace {
+
+struct Snapshot {  // first bytes of QrdmCtl copied back for polling
+    int64_t ns;
+    int64_t rank;
+    int32_t l, ks, nL, done, fallback, jmax;
+};
+
+struct Workspace {
+    int device = -1;
+    size_t bytes = 0;
+    char *base = nullptr;
+    Snapshot *host_snap = nullptr;  // pinned ring
+    int ring = 0;
+    std::vector<hipEvent_t> events;
+};
+
+Workspace g_ws;
+
+// timing events of the profiling mode (grown on demand, kept for reuse)
+std::vector<hipEvent_t> g_prof_ev;
+int prof_events(size_t count) {
+    while (g_prof_ev.size() < count) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        g_prof_ev.push_back(e);
+    }
+    return 0;
+}
+
+struct Layout {
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, zp, z, perm_dbg, total;
+};
+
+const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
+const int kSplitRows = 1024;    // rows per GEMM1 split
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int64_t m, int64_t n) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const int64_t mm = std::max<int64_t>(m, 1), nn = std::max<int64_t>(n, 1);
+    L.ctl = take(sizeof(QrdmCtl));
+    L.vn1 = take(sizeof(double) * nn);
+    L.vn2 = take(sizeof(double) * nn);
+    L.gp = take(sizeof(double) * (size_t)gram_partials(mm) * QK_KM * QK_KM);
+    L.g = take(sizeof(double) * QK_KM * QK_KM);
+    L.theta = take(sizeof(double) * QK_KM * QK_KM);
+    const int64_t pmax = (mm + kMinRowsPerWg - 1) / kMinRowsPerWg;
+    L.pb = take(sizeof(double) * 2 * (size_t)pmax * 2 * QK_KM);
+    L.tm = take(sizeof(double) * QK_KM * QK_KM);
+    L.vw = take(sizeof(double) * (size_t)QK_KM * mm);
+    L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
+    const int64_t nsplit = (mm + kSplitRows - 1) / kSplitRows;
+    L.zp = take(sizeof(double) * (size_t)nsplit * QK_KM * nn);
+    L.z = take(sizeof(double) * (size_t)QK_KM * nn);
+    L.perm_dbg = take(sizeof(int32_t) * nn);
+    L.total = off;
+    return L;
+}
+
+int hip_err(hipError_t e) { return e == hipSuccess ? 0 : QRDM_ERR_HIP + (int)e; }
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        hipError_t _e = (x);                        \
+        if (_e != hipSuccess) return hip_err(_e);   \
+    } while (0)
+
+int ensure_workspace(size_t bytes, int ring) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_ws.base && g_ws.device == dev && g_ws.bytes >= bytes && g_ws.ring >= ring) return 0;
+    if (g_ws.base) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_ws.base);
+        g_ws.base = nullptr;
+    }
+    if (g_ws.host_snap) {
+        (void)hipHostFree(g_ws.host_snap);
+        g_ws.host_snap = nullptr;
+    }
+    for (auto e : g_ws.events) (void)hipEventDestroy(e);
+    g_ws.events.clear();
+    const char *fault = getenv("QRDM_FAULT");
+    if (fault && strcmp(fault, "alloc") == 0) return QRDM_ERR_NOMEM;
+    size_t want = std::max(bytes, g_ws.bytes);
+    if (hipMalloc((void **)&g_ws.base, want) != hipSuccess) {
+        g_ws.base = nullptr;
+        g_ws.bytes = 0;
+        (void)hipGetLastError();
+        return QRDM_ERR_NOMEM;
+    }
+    int r = std::max(ring, 8);
+    if (hipHostMalloc((void **)&g_ws.host_snap, sizeof(Snapshot) * r, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(g_ws.base);
+        g_ws.base = nullptr;
+        return QRDM_ERR_NOMEM;
+    }
+    g_ws.events.resize(r);
+    for (int i = 0; i < r; ++i) HIP_TRY(hipEventCreateWithFlags(&g_ws.events[i], hipEventDisableTiming));
+    g_ws.bytes = want;
+    g_ws.device = dev;
+    g_ws.ring = r;
+    return 0;
+}
+
+int check_common(const double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p) {
+    if (m < 0) return -2;
+    if (n < 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (p) {
+        if (!(p->tau > 0.0 && p->tau <= 1.0)) return -5;
+        if (!(p->delta >= 0.0 && p->delta <= 1.0)) return -5;
+        if (p->kmax < 1 || p->kmax > QRDM_KMAX_LIMIT) return -5;
+        if (p->stop_rule < 0 || p->stop_rule > 2) return -5;
+        if (p->precision < 0 || p->precision > 1) return -5;
+        if (p->poll_lag < 0) return -5;
+        if (p->profile < 0 || p->profile > 1) return -5;
+    }
+    if (m > 0 && n > 0 && !A) return -1;
+    return 0;
+}
+
+QrdmCtl initial_ctl() {
+    QrdmCtl c;
+    memset(&c, 0, sizeof c);
+    c.rank = -1;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+void qrdm_default_params(qrdm_params *p) {
+    if (!p) return;
+    p->tau = 0.15;
+    p->delta = 0.9;
+    p->kmax = 64;
+    p->stop_rule = QRDM_STOP_PAPER;
+    p->eps1_scale = 0.0;
+    p->precision = QRDM_PREC_FP64;
+    p->poll_lag = 4;
+    p->profile = 0;
+}
+
+const char *qrdm_strerror(int code) {
+    if (code == QRDM_OK) return "success";
+    if (code < 0) return "invalid argument";
+    if (code == QRDM_ERR_NONFINITE) return "matrix contains NaN or Inf";
+    if (code == QRDM_ERR_NOMEM) return "workspace allocation failed";
+    if (code == QRDM_ERR_UNSUPPORTED) return "size not supported by the kernels";
+    if (code >= QRDM_ERR_HIP) return hipGetErrorString((hipError_t)(code - QRDM_ERR_HIP));
+    return "unknown error";
+}
+
+void qrdm_release(void) {
+    if (g_ws.base) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_ws.base);
+    }
+    if (g_ws.host_snap) (void)hipHostFree(g_ws.host_snap);
+    for (auto e : g_ws.events) (void)hipEventDestroy(e);
+    g_ws = Workspace();
+}
+
+int qrdm_colnorms(const double *A, int64_t m, int64_t n, int64_t lda, double *out, void *stream) {
+    int rc = check_common(A, m, n, lda, nullptr);
+    if (rc) return rc;
+    if (n > 0 && !out) return -5;
+    if (n == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    Layout L = make_layout(m, n);
+    rc = ensure_workspace(L.total, 8);
+    if (rc) return rc;
+    QrdmCtl *ctl = (QrdmCtl *)(g_ws.base + L.ctl);
+    double *vn2 = (double *)(g_ws.base + L.vn2);
+    QrdmCtl c0 = initial_ctl();
+    HIP_TRY(hipMemcpyAsync(ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_colnorm(A, m, n, lda, out, vn2, ctl, s));
+    int32_t nf = 0;
+    HIP_TRY(hipMemcpyAsync(&nf, &ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return nf ? QRDM_ERR_NONFINITE : 0;
+}
+
+int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *pin, double *tau_house,
+                   int32_t *perm, int64_t *rank, qrdm_stats *stats, qrdm_block *log, int64_t log_cap,
+                   int64_t *nlog, void *stream) {
+    qrdm_params p;
+    if (pin) p = *pin; else qrdm_default_params(&p);
+    int rc = check_common(A, m, n, lda, &p);
+    if (rc) return rc;
+    const int64_t pmin = std::min(m, n);
+    if (pmin > 0 && !tau_house) return -6;
+    if (n > 0 && !perm) return -7;
+    if (!rank) return -8;
+    if (log && log_cap < 0) return -11;
+    if (n > 32768 || m > 65536) return QRDM_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (nlog) *nlog = 0;
+    if (pmin == 0) {
+        if (n > 0) {
+            std::vector<int32_t> id(n);
+            for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
+            HIP_TRY(hipMemcpyAsync(perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        *rank = 0;
+        return 0;
+    }
+    const int lag = log ? 0 : p.poll_lag;
+    Layout L = make_layout(m, n);
+    rc = ensure_workspace(L.total, lag + 2);
+    if (rc) return rc;
+    char *ws = g_ws.base;
+    QrdmArgs a;
+    a.A = A;
+    a.m = m;
+    a.n = n;
+    a.lda = lda;
+    a.tau = p.tau;
+    a.delta = p.delta;
+    a.kmax = p.kmax;
+    a.stop_rule = p.stop_rule;
+    // working precision of the trailing data: 2^-52 (FP64) or 2^-23 (FP32 updates)
+    const double eps_w = (p.precision == QRDM_PREC_MIXED) ? 1.1920928955078125e-07 : 2.220446049250313e-16;
+    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * eps_w;
+    a.fbeps = (double)n * eps_w;
+    a.tol3z = sqrt(eps_w);
+    a.vn1 = (double *)(ws + L.vn1);
+    a.vn2 = (double *)(ws + L.vn2);
+    a.perm = perm;
+    a.tau_house = tau_house;
+    a.ctl = (QrdmCtl *)(ws + L.ctl);
+    double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
+    double *Tm = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
+    float *Vw32 = (float *)(ws + L.vw32);
+    void *Zp = ws + L.zp, *Z = ws + L.z;
+    const int64_t ldv = m;
+
+    QrdmCtl c0 = initial_ctl();
+    HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
+    int32_t nf = 0;
+    HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nf) return QRDM_ERR_NONFINITE;
+    HIP_TRY(launch_init(a, s));
+
+    if (p.profile) {
+        if (prof_events(2) != 0) return QRDM_ERR_NOMEM;
+        HIP_TRY(hipEventRecord(g_prof_ev[0], s));
+    }
+    const int rows_per_wg = panel_rows_per_wg(std::min<int>(p.kmax, QK_KM));
+    int64_t ns_known = 0;
+    int64_t nrec = 0;
+    int64_t iter = 0;
+    bool finished = false;
+    const int ring = g_ws.ring;
+    const int64_t max_iter = pmin + 2;
+    while (!finished) {
+        const int64_t tb = m - ns_known, wb = n - ns_known;
+        HIP_TRY(launch_select(a, s));
+        HIP_TRY(launch_gram(a, Gp, tb, s));
+        HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
+        HIP_TRY(launch_dm_finish(a, G, nullptr, s));
+        HIP_TRY(launch_swap(a, s));
+        HIP_TRY(launch_panel(a, PB, Tm, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
+        hipEvent_t *ev = nullptr;
+        if (p.profile) {
+            if (prof_events(4 * (size_t)(iter + 1) + 2) != 0) return QRDM_ERR_NOMEM;
+            ev = g_prof_ev.data() + 2 + 4 * iter;
+        }
+        HIP_TRY(launch_trail(a, p.precision, Tm, Vw, Vw32, ldv, Zp, Z, tb, wb, kSplitRows, s, ev));
+        HIP_TRY(launch_downdate(a, wb, s));
+        Snapshot *hs = g_ws.host_snap + (iter % ring);
+        HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
+        if (iter >= lag) {
+            const int64_t k = iter - lag;
+            HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
+            const Snapshot sn = g_ws.host_snap[k % ring];
+            if (sn.ns > ns_known) ns_known = sn.ns;
+            if (log && !sn.done) {
+                if (nrec < log_cap) {
+                    qrdm_block b;
+                    b.ns = sn.ns;
+                    b.nL = sn.nL;
+                    b.ks = sn.ks;
+                    b.l = sn.l;
+                    b.fallback = sn.fallback;
+                    b.umax = 0.0;
+                    log[nrec] = b;
+                }
+                ++nrec;
+            }
+            if (sn.done) finished = true;
+        }
+        ++iter;
+        if (iter > max_iter + lag + 1) break;  // cannot happen: every block advances n_s
+    }
+    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    QrdmCtl cf;
+    HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
+    if (stats && p.profile) {
+        float ms = 0.f;
+        double g1 = 0.0, g2 = 0.0;
+        for (int64_t k = 0; k < iter; ++k) {
+            hipEvent_t *ev = g_prof_ev.data() + 2 + 4 * k;
+            if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) g1 += ms;
+            if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) g2 += ms;
+        }
+        stats->gemm1_ms = g1;
+        stats->gemm2_ms = g2;
+        stats->gemm_flop = cf.flop_gemm;
+        if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[1]) == hipSuccess) stats->total_ms = ms;
+    }
+    if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
+    *rank = cf.rank >= 0 ? cf.rank : cf.ns;
+    if (stats) {
+        stats->nblocks = cf.nblocks;
+        stats->nbreaks = cf.nbreaks;
+        stats->nfallback = cf.nfallback;
+        stats->nrecompute = cf.nrecompute;
+        stats->ncols_factored = cf.ns;
+    }
+    if (nlog) *nlog = nrec;
+    if (log && lag == 0) {
+        // umax of every logged block is not in the snapshot; leave 0
+    }
+    return 0;
+}
+
+int qrdm_factor(double *A, int64_t m, int64_t n, int64_t lda, double tau, double delta, int32_t kmax,
+                double *tau_house, int32_t *perm, int64_t *rank, void *stream) {
+    qrdm_params p;
+    qrdm_default_params(&p);
+    p.tau = tau;
+    p.delta = delta;
+    p.kmax = kmax;
+    return qrdm_factor_ex(A, m, n, lda, &p, tau_house, perm, rank, nullptr, nullptr, 0, nullptr, stream);
+}
+
+int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns, const double *vn1, double tau,
+                 double delta, int32_t kmax, int32_t *L, int32_t *nL, double *theta, int32_t *J, int32_t *ks,
+                 void *stream) {
+    qrdm_params p;
+    qrdm_default_params(&p);
+    p.tau = tau;
+    p.delta = delta;
+    p.kmax = kmax;
+    int rc = check_common(A, m, n, lda, &p);
+    if (rc) return rc;
+    if (ns < 0 || ns >= std::min(m, n)) return -5;
+    if (!vn1) return -6;
+    if (!L || !nL || !J || !ks) return -10;
+    if (n > 32768) return QRDM_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    Layout Ly = make_layout(m, n);
+    rc = ensure_workspace(Ly.total, 8);
+    if (rc) return rc;
+    char *ws = g_ws.base;
+    QrdmArgs a;
+    a.A = (double *)A;
+    a.m = m;
+    a.n = n;
+    a.lda = lda;
+    a.tau = tau;
+    a.delta = delta;
+    a.kmax = kmax;
+    a.stop_rule = QRDM_STOP_NONE;
+    a.eps1 = 0.0;
+    a.fbeps = (double)n * 2.220446049250313e-16;
+    a.tol3z = 1.4901161193847656e-08;
+    a.vn1 = (double *)(ws + Ly.vn1);
+    a.vn2 = (double *)(ws + Ly.vn2);
+    a.perm = (int32_t *)(ws + Ly.perm_dbg);
+    a.tau_house = nullptr;
+    a.ctl = (QrdmCtl *)(ws + Ly.ctl);
+    HIP_TRY(hipMemcpyAsync(a.vn1, vn1, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(a.vn2, vn1, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    std::vector<int32_t> id(n);
+    for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
+    HIP_TRY(hipMemcpyAsync(a.perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    QrdmCtl c0 = initial_ctl();
+    c0.ns = ns;
+    c0.rank = 0;        // stopping test already decided: not applied here
+    c0.nblocks = 1;     // keep amax as given
+    c0.amax = 2.2250738585072014e-308;  // fallback test never fires for a non-zero trailing block
+    HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    double *Gp = (double *)(ws + Ly.gp), *G = (double *)(ws + Ly.g), *th = (double *)(ws + Ly.theta);
+    HIP_TRY(launch_select(a, s));
+    HIP_TRY(launch_gram(a, Gp, m - ns, s));
+    HIP_TRY(launch_gram_reduce(a, Gp, G, m - ns, s));
+    HIP_TRY(launch_dm_finish(a, G, th, s));
+    QrdmCtl cf;
+    HIP_TRY(hipMemcpyAsync(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *nL = cf.nL;
+    *ks = cf.ks;
+    for (int i = 0; i < cf.nL; ++i) L[i] = cf.L[i];
+    for (int i = 0; i < cf.ks; ++i) J[i] = cf.J[i];
+    if (theta && cf.nL > 1) {
+        std::vector<double> h((size_t)cf.nL * cf.nL);
+        HIP_TRY(hipMemcpy(h.data(), th, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < h.size(); ++e) theta[e] = h[e];
+    } else if (theta && cf.nL == 1) {
+        theta[0] = 1.0;
+    }
+    return 0;
+}
+
+int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *pin, int32_t nb,
+                  double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats, void *stream);
+
+int qrp_factor(double *A, int64_t m, int64_t n, int64_t lda, double *tau_house, int32_t *perm, int64_t *rank,
+               void *stream) {
+    return qrp_factor_ex(A, m, n, lda, nullptr, 32, tau_house, perm, rank, nullptr, stream);
+}
+
+}  // extern "C"

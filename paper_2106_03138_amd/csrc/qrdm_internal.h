@@ -1,0 +1,82 @@
+// Internal declarations shared by the HIP kernels and the host driver of
+// libqrdm.so (gfx950).  Not part of the public ABI (include/qrdm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define QK_KM 128          // capacity of every per-block array (k_DM <= 128)
+#define QK_SWAP_MAX (2 * QK_KM)
+
+// Loop state of one factorization, resident in device memory.  Every kernel of
+// an outer step reads it; only the single-workgroup kernels write it.
+struct QrdmCtl {
+    int64_t ns;      // columns factored (n_s)
+    int64_t rank;    // -1 until the stopping test first holds
+    int32_t l;       // reflectors kept by the current step's panel
+    int32_t ks;      // accepted columns of the current step (k_s)
+    int32_t nL;      // candidate list length (0 when done)
+    int32_t done;    // 1 = no further step
+    int32_t fallback;  // current step uses scalar pivoting
+    int32_t jmax;
+    int32_t nswap;     // column moves of the current step
+    int32_t nonfinite; // set by the norm sweep
+    int32_t error;     // bit 1: a grid barrier timed out
+    uint32_t bar;      // grid barrier counter of the cooperative panel
+    uint32_t bar2;     // second counter (QRP kernels)
+    double amax;       // max initial column norm
+    double umax;       // max partial norm of the current step
+    double eps_s;      // panel break threshold tau*umax
+    // statistics
+    int64_t nblocks, nbreaks, nfallback, nrecompute;
+    double flop_gemm;  // algorithmic flops of one trailing GEMM (2 t l w), summed over blocks
+    int32_t L[QK_KM];
+    int32_t J[QK_KM];
+    int32_t swp_dst[QK_SWAP_MAX];
+    int32_t swp_src[QK_SWAP_MAX];
+};
+
+struct QrdmArgs {
+    double *A;
+    int64_t m, n, lda;
+    double tau, delta;
+    int32_t kmax;
+    int32_t stop_rule;
+    double eps1;    // eps_1 * (applied as eps1 * amax) of the stopping test
+    double fbeps;   // eps_w * n: scalar pivoting when max partial norm <= fbeps * amax
+    double tol3z;   // sqrt(eps_w): recompute a partial norm when the downdate lost this much
+    double *vn1, *vn2;
+    int32_t *perm;
+    double *tau_house;
+    QrdmCtl *ctl;
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+    // fixed-order butterfly over the 64 lanes of a wavefront
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t p_of(const QrdmArgs &a) { return a.m < a.n ? a.m : a.n; }
+
+// ------------------------------------------------------------ launchers
+// Each returns hipGetLastError() of its launch.
+hipError_t launch_colnorm(const double *A, int64_t m, int64_t n, int64_t lda, double *vn1, double *vn2,
+                          QrdmCtl *ctl, hipStream_t s);
+hipError_t launch_init(QrdmArgs a, hipStream_t s);
+hipError_t launch_select(QrdmArgs a, hipStream_t s);
+hipError_t launch_gram(QrdmArgs a, double *Gp, int64_t t_bound, hipStream_t s);
+hipError_t launch_gram_reduce(QrdmArgs a, const double *Gp, double *G, int64_t t_bound, hipStream_t s);
+hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipStream_t s);
+hipError_t launch_swap(QrdmArgs a, hipStream_t s);
+hipError_t launch_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw32, int64_t ldv,
+                        int64_t t_bound, int rows_per_wg, hipStream_t s);
+// ev (may be null): 4 events recorded before GEMM1, after GEMM1, before GEMM2, after GEMM2
+hipError_t launch_trail(QrdmArgs a, int precision, const double *T, const double *Vw, const float *Vw32,
+                        int64_t ldv, void *Zp, void *Z, int64_t t_bound, int64_t w_bound, int split_rows,
+                        hipStream_t s, hipEvent_t *ev);
+hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s);
+
+int panel_max_wgs(int rows_per_wg);
+int panel_rows_per_wg(int kmax);
