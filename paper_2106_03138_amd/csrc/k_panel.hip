@@ -1,7 +1,8 @@
 // Householder panel of one QRDM block with the early break (Algorithm 4 of
-// the paper, inner loop; threshold eps_s of eq. lenght_check) and the
-// compact-WY factor T (Section 3.2; forward column-wise form of Schreiber and
-// Van Loan), on gfx950.
+// the paper, inner loop; threshold eps_s of eq. lenght_check), on gfx950.  It
+// also records the inner products v_a^T v_i of the reflectors, from which the
+// trailing update applies the compact WY form (Section 3.2) without forming
+// its triangular factor.
 //
 // The k_s accepted columns (rows n_s..m-1) are split into row slabs, one per
 // workgroup, held in LDS for the whole panel.  Every panel column costs one
@@ -11,8 +12,7 @@
 // where x is the current column.  From the reduced vector every workgroup
 // derives, redundantly and identically, ||x|| (and the break decision), the
 // reflector (LAPACK larfg convention: beta = -sign(alpha)||x||), the products
-// v^T a_j of the in-panel update, and the inner products v_a^T v_i that build
-// column i of T.  Reductions are in fixed order, so the run is bit-reproducible
+// v^T a_j of the in-panel update, and the inner products v_a^T v_i.  Reductions are in fixed order, so the run is bit-reproducible
 // and every workgroup takes the same branch.
 //
 // The launch must be cooperative (all workgroups co-resident): the rounds are
@@ -29,9 +29,9 @@
 // increment.  The spin is bounded: on timeout the error flag is raised and the
 // kernel runs to completion (the host then reports an error).
 __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, int32_t *err) {
+    __builtin_amdgcn_s_waitcnt(0);  // every wave's published stores have completed
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int it = 0;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -55,7 +55,7 @@ __device__ __forceinline__ double ld_coherent(const double *p) {
 extern __shared__ double pn_lds[];
 
 __global__ void __launch_bounds__(PN_THREADS)
-k_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw32, int64_t ldv) {
+k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
@@ -184,17 +184,11 @@ k_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw32, int64_t ldv)
         }
         for (int jj = i + 1 + tid; jj < ks; jj += PN_THREADS) sW[jj] = ti * (sTop[jj] + sR[jj] / den);
         if (wg == 0) {
-            // column i of T: T_ii = tau_i, T[0:i, i] = -tau_i T[0:i,0:i] (V^T v_i)
-            // with v_a^T v_i = Top_a + Dall_a / den for a < i
-            if (tid < i) {
-                double s = 0.0;
-                for (int b = tid; b < i; ++b) s += T[tid * QK_KM + b] * (sTop[b] + sR[b] / den);
-                T[tid * QK_KM + i] = -ti * s;
-            }
-            if (tid == 0) {
-                T[i * QK_KM + i] = ti;
-                a.tau_house[c] = ti;
-            }
+            // inner products v_a^T v_i = Top_a + Dall_a / den (a < i) of the
+            // compact WY form; the trailing update uses them with tau instead of
+            // forming T explicitly
+            if (tid < i) VV[tid * QK_KM + i] = sTop[tid] + sR[tid] / den;
+            if (tid == 0) a.tau_house[c] = ti;
         }
         __syncthreads();
         // ---- apply H_i to the slab: rows below c, then row c
@@ -253,7 +247,7 @@ int panel_max_wgs(int rows_per_wg) {
     return prop.multiProcessorCount;
 }
 
-hipError_t launch_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw32, int64_t ldv,
+hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv,
                         int64_t t_bound, int rows_per_wg, hipStream_t s) {
     if (t_bound <= 0) return hipSuccess;
     int P = (int)((t_bound + rows_per_wg - 1) / rows_per_wg);
@@ -262,9 +256,10 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw
     const int lds = panel_lds_bytes(rows_per_wg, kk);
     static bool attr_set = false;
     if (!attr_set) {
-        hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void *)k_panel, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e != hipSuccess) return e;
         attr_set = true;
     }
-    void *args[] = {&a, &PB, &T, &Vw, &Vw32, &ldv};
+    void *args[] = {&a, &PB, &VV, &Vw, &Vw32, &ldv};
     return hipLaunchCooperativeKernel((const void *)k_panel, dim3(P), dim3(PN_THREADS), args, (unsigned)lds, s);
 }

@@ -1,0 +1,376 @@
+// QR with column pivoting (Algorithm 2 of the paper, QRP) in the blocked form
+// that LAPACK xgeqp3 uses (Section 3.1 cites it as QP3): one pivot per step,
+// with the trailing update deferred and accumulated as A_tr -= V F^T, so each
+// step costs one matrix-vector sweep of the trailing matrix (the BLAS-2 part
+// whose cost Section 5 identifies) and every nb steps one BLAS-3 update.
+// It is the classical baseline and the scalar-pivoting continuation of QRDM
+// once the partial norms reach the noise level (eq. column_norm_bound_DM).
+//
+// One step (column j = n_s, block [k0, k0 + nb), b = j - k0 reflectors done):
+//   k_qp_select  advance the step state; arg-max of the partial norms (lowest
+//                position on ties); stopping test; swap bookkeeping (vn1, vn2,
+//                perm, the F row of both columns).
+//   k_qp_column  per row slab: normalize the previous reflector; swap columns;
+//                x = A[j:m, j] - V F[j,:]^T (the deferred update of the pivot
+//                column); partial sums ||x_below||^2, x_j, V^T x.
+//   k_qp_gemv    per trailing column c (one wavefront): reflector scalars from
+//                the partials (LAPACK larfg convention); F[c, b] = tau v^T a_c
+//                corrected by the earlier reflectors of the block; the pivot
+//                row A[j, c] of R; the partial norm update of column c with the
+//                cancellation-safe recompute flag.
+//   k_qp_close   at block end: normalize the last reflector, stage V for the
+//                BLAS-3 update (then k_gemm2 mode 1), recompute flagged norms.
+#include <float.h>
+
+#include "qrdm_internal.h"
+
+#define QP_ROWS 256  // rows per workgroup of the pivot-column pass
+#define QP_NBMAX 64
+
+hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
+                            int64_t w_bound, hipStream_t s);
+
+// ------------------------------------------------------------ init / select
+__global__ void k_qp_init(QrdmArgs a, int nb) {
+    QrdmCtl *c = a.ctl;
+    if (!c->done) c->ns += c->l;  // finish the advance of a preceding QRDM step
+    c->qp_k0 = c->ns;
+    c->qp_b = 0;
+    c->qp_pend = 0;
+    c->qp_end = 0;
+    c->qp_stop = 0;
+    c->qp_flag = 0;
+    c->qp_nb = nb;
+    c->l = 0;
+}
+
+hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_qp_init, dim3(1), dim3(1), 0, s, a, nb);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ bool qp_better(double va, int ja, double vb, int jb) {
+    return va > vb || (va == vb && ja < jb);
+}
+
+__global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
+    QrdmCtl *ctl = a.ctl;
+    __shared__ double s_v[16];
+    __shared__ int s_j[16];
+    __shared__ int s_go;
+    if (ctl->done) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // advance from the previous step
+        if (ctl->qp_end) {
+            ctl->qp_k0 = ctl->qp_last + 1;
+            ctl->qp_b = 0;
+            ctl->qp_pend = 0;
+            ctl->qp_flag = 0;
+            ctl->qp_end = 0;
+            ctl->ns = ctl->qp_last + 1;
+        } else if (ctl->l == 1) {  // a reflector was made at column ns
+            ctl->qp_b += 1;
+            ctl->qp_pend = 1;
+            ctl->ns += 1;
+        }
+        ctl->l = 0;
+    }
+    __syncthreads();
+    const int64_t j = ctl->ns;
+    const int64_t p = p_of(a);
+    if (j >= p) {
+        if (tid == 0) {
+            ctl->done = 1;
+            if (ctl->rank < 0) ctl->rank = j;
+        }
+        return;
+    }
+    double bv = -1.0;
+    int bj = 0x7fffffff;
+    for (int64_t c = j + tid; c < a.n; c += 1024) {
+        const double v = a.vn1[c];
+        if (v > bv) { bv = v; bj = (int)c; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oj = __shfl_xor(bj, o, 64);
+        if (qp_better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
+    }
+    if ((tid & 63) == 0) { s_v[tid >> 6] = bv; s_j[tid >> 6] = bj; }
+    __syncthreads();
+    if (tid == 0) {
+        double uv = s_v[0];
+        int uj = s_j[0];
+        for (int i = 1; i < 16; ++i)
+            if (qp_better(s_v[i], s_j[i], uv, uj)) { uv = s_v[i]; uj = s_j[i]; }
+        double amax = ctl->amax;
+        if (ctl->nblocks == 0 && j == 0) { amax = uv; ctl->amax = amax; }
+        int go = 1;
+        if (amax == 0.0) {
+            ctl->rank = 0;
+            ctl->done = 1;
+            go = 0;
+        } else if (ctl->rank < 0) {
+            const double lhs = (a.stop_rule == 1) ? uv : sqrt((double)(a.n - j)) * uv;
+            if (lhs <= a.eps1 * amax) {
+                ctl->rank = j;
+                if (a.stop_rule != 2) {
+                    go = 0;
+                    if (ctl->qp_b > 0) {  // close the block so the trailing block is up to date
+                        ctl->qp_stop = 1;
+                    } else {
+                        ctl->done = 1;
+                    }
+                }
+            }
+        }
+        if (go) {
+            ctl->jmax = uj;
+            ctl->umax = uv;
+            ctl->nblocks += 1;
+            if (uj != j) {
+                double t1 = a.vn1[j]; a.vn1[j] = a.vn1[uj]; a.vn1[uj] = t1;
+                t1 = a.vn2[j]; a.vn2[j] = a.vn2[uj]; a.vn2[uj] = t1;
+                const int32_t pp = a.perm[j]; a.perm[j] = a.perm[uj]; a.perm[uj] = pp;
+            }
+        }
+        s_go = go && (uj != j);
+    }
+    __syncthreads();
+    // swap the F rows of columns j and jmax (F^T stored as Fz[b'][column])
+    if (s_go) {
+        const int uj = ctl->jmax;
+        const int b = ctl->qp_b;
+        for (int bb = tid; bb < b; bb += 1024) {
+            const double t1 = Fz[(int64_t)bb * a.n + j];
+            Fz[(int64_t)bb * a.n + j] = Fz[(int64_t)bb * a.n + uj];
+            Fz[(int64_t)bb * a.n + uj] = t1;
+        }
+    }
+}
+
+// ------------------------------------------------------------ pivot column
+__global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz, double *PB2) {
+    const QrdmCtl *ctl = a.ctl;
+    if (ctl->done || ctl->qp_stop) return;
+    const int64_t j = ctl->ns;
+    const int64_t k0 = ctl->qp_k0;
+    const int b = ctl->qp_b;
+    const int64_t jm = ctl->jmax;
+    const int64_t r0 = (int64_t)blockIdx.x * QP_ROWS;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ double sF[QP_NBMAX];
+    __shared__ double red[4][2 + 2 * QP_NBMAX];
+    for (int bb = tid; bb < b; bb += 256) sF[bb] = Fz[(int64_t)bb * a.n + j];
+    __syncthreads();
+    const int64_t r = r0 + tid;
+    // per row: normalize the pending reflector (column j-1), swap, update x_r
+    double x = 0.0;
+    if (r < a.m) {
+        if (ctl->qp_pend) {
+            const int64_t pc = j - 1;
+            if (r > pc) a.A[pc * a.lda + r] /= ctl->qp_den;
+            else if (r == pc) a.A[pc * a.lda + r] = ctl->qp_beta;
+        }
+        if (jm != j) {
+            const double t1 = a.A[j * a.lda + r];
+            a.A[j * a.lda + r] = a.A[jm * a.lda + r];
+            a.A[jm * a.lda + r] = t1;
+        }
+        if (r >= j) {
+            x = a.A[j * a.lda + r];
+            for (int bb = 0; bb < b; ++bb) x -= a.A[(k0 + bb) * a.lda + r] * sF[bb];
+            a.A[j * a.lda + r] = x;
+        }
+    }
+    // partial sums: [0] sum_{r>j} x^2, [1] x_j, [2+bb] sum_{r>j} v_bb[r] x_r, [2+b+bb] v_bb[j]
+    const bool below = (r < a.m) && (r > j);
+    const bool atj = (r < a.m) && (r == j);
+    double s0 = below ? x * x : 0.0;
+    double s1 = atj ? x : 0.0;
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
+    for (int bb = 0; bb < b; ++bb) {
+        const double vb = (below || atj) ? a.A[(k0 + bb) * a.lda + r] : 0.0;
+        double d = below ? vb * x : 0.0;
+        double tp = atj ? vb : 0.0;
+        d = wave_sum(d);
+        tp = wave_sum(tp);
+        if (lane == 0) { red[wv][2 + bb] = d; red[wv][2 + b + bb] = tp; }
+    }
+    __syncthreads();
+    const int nv = 2 + 2 * b;
+    for (int e = tid; e < nv; e += 256)
+        PB2[(int64_t)blockIdx.x * (2 + 2 * QP_NBMAX) + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+}
+
+// -------------------------------------------------------------------- GEMV
+__global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const double *PB2, int32_t *flag) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done || ctl->qp_stop) return;
+    const int64_t j = ctl->ns;
+    const int64_t k0 = ctl->qp_k0;
+    const int b = ctl->qp_b;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ double sv[2 + 2 * QP_NBMAX];
+    __shared__ double s_scal[4];
+    __shared__ double auxv[QP_NBMAX];
+    const int nv = 2 + 2 * b;
+    const int npart = (int)((a.m + QP_ROWS - 1) / QP_ROWS);
+    // fixed-order reduction of the pivot-column partials (every workgroup)
+    for (int e = tid; e < nv; e += 256) {
+        double acc = 0.0;
+        for (int w0 = 0; w0 < npart; w0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = (w0 + u < npart) ? PB2[(int64_t)(w0 + u) * (2 + 2 * QP_NBMAX) + e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        sv[e] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double sp = sv[0], alpha = sv[1];
+        const double nrm = sqrt(alpha * alpha + sp);
+        double beta, ti, den;
+        if (sp == 0.0) {
+            ti = 0.0;
+            beta = alpha;
+            den = 1.0;
+        } else {
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            ti = (beta - alpha) / beta;
+            den = alpha - beta;
+        }
+        s_scal[0] = beta;
+        s_scal[1] = ti;
+        s_scal[2] = den;
+        if (blockIdx.x == 0) {
+            a.tau_house[j] = ti;
+            ctl->qp_beta = beta;
+            ctl->qp_den = den;
+            ctl->l = 1;
+        }
+    }
+    __syncthreads();
+    const double ti = s_scal[1], den = s_scal[2];
+    for (int bb = tid; bb < b; bb += 256) auxv[bb] = sv[2 + b + bb] + sv[2 + bb] / den;  // V^T v
+    __syncthreads();
+    const int64_t c = j + 1 + (int64_t)blockIdx.x * 4 + wv;
+    if (c >= a.n) return;
+    const double *xc = a.A + j * a.lda;
+    const double *ac = a.A + c * a.lda;
+    double d = 0.0;
+    for (int64_t r = j + 1 + lane; r < a.m; r += 64) d += xc[r] * ac[r];
+    d = wave_sum(d);
+    if (lane == 0) {
+        // F[c, b] = tau v^T a_c - tau sum_{b'<b} F[c, b'] (V^T v)_{b'}
+        double f = ac[j] + d / den;
+        double corr = 0.0;
+        for (int bb = 0; bb < b; ++bb) corr += Fz[(int64_t)bb * a.n + c] * auxv[bb];
+        f = ti * f - ti * corr;
+        Fz[(int64_t)b * a.n + c] = f;
+        // pivot row of R: A[j, c] -= sum_{b' <= b} V[j, b'] F[c, b'], V[j, b] = 1
+        double rjc = ac[j] - f;
+        for (int bb = 0; bb < b; ++bb) rjc -= sv[2 + b + bb] * Fz[(int64_t)bb * a.n + c];
+        a.A[c * a.lda + j] = rjc;
+        // partial norm update with the new row (cancellation-safe rule)
+        const double v1 = a.vn1[c];
+        if (v1 != 0.0) {
+            double q = 1.0 - (rjc * rjc) / (v1 * v1);
+            if (q < 0.0) q = 0.0;
+            const double r12 = v1 / a.vn2[c];
+            const double q2 = q * (r12 * r12);
+            if (q2 <= a.tol3z) {
+                flag[c] = 1;
+                atomicOr(&ctl->qp_flag, 1);
+            } else {
+                a.vn1[c] = v1 * sqrt(q);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------- closing
+// Decides whether this step closes the block; if so normalizes the last
+// reflector and stages V rows below the block for the BLAS-3 update.
+__global__ void __launch_bounds__(256) k_qp_close_a(QrdmArgs a, double *Vw, int64_t ldv, int nb) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int64_t j = ctl->ns;
+    const int b = ctl->qp_b;
+    const int stop = ctl->qp_stop;
+    const int64_t p = p_of(a);
+    const bool end = stop || (b + 1 == nb) || (j + 1 == p) || ctl->qp_flag;
+    if (!end) return;
+    const int kb = stop ? b : b + 1;  // reflectors in the block
+    const int64_t k0 = ctl->qp_k0;
+    const int64_t last = k0 + kb - 1;
+    const double den = ctl->qp_den, beta = ctl->qp_beta;
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    // the last reflector is the pending one: column j (normal) or j - 1 (stop)
+    if (r < a.m) {
+        if (r > last) a.A[last * a.lda + r] /= den;
+        else if (r == last) a.A[last * a.lda + r] = beta;
+        if (r > last)
+            for (int bb = 0; bb < kb; ++bb) Vw[(int64_t)bb * ldv + (r - last - 1)] = a.A[(k0 + bb) * a.lda + r];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // single writer; the rest of this grid reads only the fields above
+        ctl->qp_kb = kb;
+        ctl->qp_last = last;
+    }
+}
+
+// second phase: publish the decision (after every workgroup of close_a read it)
+__global__ void k_qp_close_b(QrdmArgs a, int nb) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int64_t j = ctl->ns;
+    const int b = ctl->qp_b;
+    const int stop = ctl->qp_stop;
+    const int64_t p = p_of(a);
+    const bool end = stop || (b + 1 == nb) || (j + 1 == p) || ctl->qp_flag;
+    ctl->qp_end = end ? 1 : 0;
+}
+
+// after the BLAS-3 update: recompute the flagged partial norms (wave per column)
+__global__ void __launch_bounds__(256) k_qp_close_c(QrdmArgs a, int32_t *flag) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done || !ctl->qp_end) return;
+    const int64_t last = ctl->qp_last;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = last + 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c < a.n && flag[c]) {
+        const double *col = a.A + c * a.lda;
+        double t = 0.0;
+        for (int64_t r = last + 1 + lane; r < a.m; r += 64) t += col[r] * col[r];
+        t = wave_sum(t);
+        if (lane == 0) {
+            const double v = sqrt(t);
+            a.vn1[c] = v;
+            a.vn2[c] = v;
+            flag[c] = 0;
+            atomicAdd((unsigned long long *)&ctl->nrecompute, 1ull);
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->qp_stop) ctl->done = 1;
+}
+
+hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s) {
+    const unsigned g_rows = (unsigned)((a.m + QP_ROWS - 1) / QP_ROWS);
+    const unsigned g_cols = (unsigned)((w_bound + 3) / 4 + 1);
+    hipLaunchKernelGGL(k_qp_select, dim3(1), dim3(1024), 0, s, a, bf.Fz);
+    hipLaunchKernelGGL(k_qp_column, dim3(g_rows), dim3(256), 0, s, a, bf.Fz, bf.PB2);
+    hipLaunchKernelGGL(k_qp_gemv, dim3(g_cols), dim3(256), 0, s, a, bf.Fz, bf.PB2, bf.flag);
+    hipLaunchKernelGGL(k_qp_close_a, dim3(g_rows), dim3(256), 0, s, a, bf.Vw, bf.ldv, nb);
+    hipLaunchKernelGGL(k_qp_close_b, dim3(1), dim3(1), 0, s, a, nb);
+    hipError_t e = launch_gemm2_qp3(a, bf.Vw, bf.ldv, bf.Fz, t_bound, w_bound, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_qp_close_c, dim3(g_cols), dim3(256), 0, s, a, bf.flag);
+    return hipGetLastError();
+}

@@ -1,24 +1,29 @@
 // Block trailing update of QRDM (Algorithm 4 of the paper, the BLAS-3 step;
-// compact WY form of Section 3.2): with the l kept reflectors as
-// H_0...H_{l-1} = I - V T V^T,
-//     A_tr <- (I - V T V^T)^T A_tr = A_tr - V (T^T (V^T A_tr)),
-// A_tr = A[n_s:m, n_s+k_s:n].  Three kernels on gfx950 MFMA:
-//   k_gemm1   Zp[s] = V^T A_tr over row split s (split-K, K = t rows).
-//   k_zreduce Z = T^T sum_s Zp[s] (fixed order; FP64).
-//   k_gemm2   A_tr -= V Z (K = l), the update accumulated in registers and
-//             subtracted from A in one read-modify-write pass.
-// Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode uses FP32 MFMA
-// (16x16x4 f32) with FP32 accumulation for the two products while A stays
-// FP64 in memory and Z is reduced in FP64.
+// compact WY form of Section 3.2).  With the l kept reflectors written as
+// H_0...H_{l-1} = I - V T V^T (forward accumulation),
+//     A_tr <- (I - V T V^T)^T A_tr = A_tr - V Z,   Z = T^T (V^T A_tr),
+// A_tr = A[n_s:m, n_s+k_s:n].  T is not formed: since T^{-1} = diag(1/tau) +
+// strict_upper(V^T V), Z solves the lower recurrence
+//     Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b),   Y = V^T A_tr,
+// (Z_a = 0 when tau_a = 0, the identity reflector), with v_b^T v_a recorded by
+// the panel.  Two kernels on gfx950 MFMA:
+//   k_gemm1  Y = V^T A_tr, split over rows; the last workgroup of each
+//            256-column tile sums the partials and runs the recurrence -> Z;
+//   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once.
+// Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode runs both products
+// on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and the
+// recurrence runs in FP64.
 #include "qrdm_internal.h"
+
+#define QK_SPLIT_MAX 16  // row splits of the V^T A product
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-template <typename T> struct Mfma;
 // Operand layouts of both 16x16x4 instructions: A[i][k] in lane i + 16k, B[k][j]
 // in lane j + 16k.  Result layouts differ: register v of a lane holds
 // D[4v + lane/16][lane%16] for f64 and D[4(lane/16) + v][lane%16] for f32.
+template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     typedef dbl4 acc_t;
     static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
@@ -35,17 +40,27 @@ template <> struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ GEMM1
-#define G1_NT 128   // trailing columns per workgroup
+#define G1_NT 256   // trailing columns per workgroup (V reused across them)
 #define G1_KC 32    // rows staged per step
 #define G1_LD (G1_KC + 1)
 
-// Zp[s] = V^T A_tr over rows [s*split_rows, (s+1)*split_rows).  The next row
-// chunk is loaded into registers while the current one is multiplied out of
-// LDS, so the HBM latency overlaps the MFMA work.
+__device__ __forceinline__ void st_coh(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Split-K: workgroup (x, y, z) forms rows [64z, 64z+64) of the partial
+// Y_y = V^T A_tr over rows [y*krows, (y+1)*krows) of A_tr, for trailing columns
+// [256x, 256x+256), and publishes it with agent-coherent stores.  The last
+// workgroup of a column tile to arrive (tile counter) sums the partials in
+// split order and runs the recurrence for Z, 64 columns at a time.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, T *__restrict__ Zp, int split_rows, int64_t ldz) {
-    const QrdmCtl *ctl = a.ctl;
+k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restrict__ VV, double *Yp,
+        uint32_t *tile_cnt, T *__restrict__ Z, int64_t ldz, int krows) {
+    QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks, l = ctl->l;
@@ -53,13 +68,22 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, T *__restrict__ Zp, in
     const int64_t c0 = ns + ks;
     const int64_t w2 = a.n - c0;
     const int64_t jb = (int64_t)blockIdx.x * G1_NT;
-    const int64_t rb = (int64_t)blockIdx.y * split_rows;
-    if (l <= 0 || jb >= w2 || rb >= t) return;
-    const int64_t re = (rb + split_rows < t) ? rb + split_rows : t;
-    const int lt = (l + 15) >> 4;  // 16-row tiles of Z
-    const int lp = lt * 16;
-    __shared__ T Vs[QK_KM * G1_LD];
-    __shared__ T As[G1_NT * G1_LD];
+    if (l <= 0 || jb >= w2 || t <= 0) return;
+    const int nsplit = (int)((t + krows - 1) / krows);
+    const int lt = (l + 15) >> 4;
+    const int nz = (lt + 3) >> 2;
+    const int sp = blockIdx.y, zg = blockIdx.z;
+    if (sp >= nsplit || zg >= nz) return;
+    if (blockIdx.x == 0 && sp == 0 && zg == 0 && threadIdx.x == 0)
+        ctl->flop_gemm += 2.0 * (double)t * (double)l * (double)w2;
+    const int64_t rb = (int64_t)sp * krows;
+    const int64_t re = (rb + krows < t) ? rb + krows : t;
+    const int q0 = 64 * zg;                 // first reflector of this row group
+    const int ltz = (lt - 4 * zg) < 4 ? (lt - 4 * zg) : 4;
+    extern __shared__ double g1_lds[];
+    T *Vs = reinterpret_cast<T *>(g1_lds);  // [64][G1_LD]
+    T *As = Vs + 64 * G1_LD;                // [G1_NT][G1_LD]
+    __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     typedef typename Mfma<T>::acc_t acc_t;
     acc_t acc[16];
@@ -67,16 +91,20 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, T *__restrict__ Zp, in
     for (int u = 0; u < 16; ++u) acc[u] = acc_t{0, 0, 0, 0};
     const int ncols = (int)((w2 - jb) < G1_NT ? (w2 - jb) : G1_NT);
     const double *Abase = a.A + (c0 + jb) * a.lda + ns;
-    // element u*256 + tid of a chunk: column q = u*8 + tid/32, row r = tid%32
+    // staged element u*256 + tid: row r = tid % 32, column/reflector q = u*8 + tid/32
     const int rr = tid & 31, qq = tid >> 5;
-    T vreg[16], areg[16];
+    T vreg[8], areg[32];
     auto fetch = [&](int64_t rc) {
         const int64_t row = rc + rr;
         const bool rok = row < re;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = u * 8 + qq;
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + u * 8 + qq;
             vreg[u] = (rok && q < l) ? V[(int64_t)q * ldv + row] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int q = u * 8 + qq;
             areg[u] = (rok && q < ncols) ? (T)Abase[(int64_t)q * a.lda + row] : (T)0;
         }
     };
@@ -84,96 +112,101 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, T *__restrict__ Zp, in
     for (int64_t rc = rb; rc < re; rc += G1_KC) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int q = u * 8 + qq;
-            if (q < lp) Vs[q * G1_LD + rr] = vreg[u];
-            As[q * G1_LD + rr] = areg[u];
-        }
+        for (int u = 0; u < 8; ++u) Vs[(u * 8 + qq) * G1_LD + rr] = vreg[u];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) As[(u * 8 + qq) * G1_LD + rr] = areg[u];
         __syncthreads();
         if (rc + G1_KC < re) fetch(rc + G1_KC);
-        // wave wv owns trailing columns [32 wv, 32 wv + 32): 2 column tiles x lt row tiles
-#pragma unroll
+        // wave wv owns columns [64 wv, 64 wv + 64): 4 column tiles x ltz row tiles
+#pragma unroll 2
         for (int k = 0; k < G1_KC; k += 4) {
-            const T b0 = As[(wv * 32 + (lane & 15)) * G1_LD + k + (lane >> 4)];
-            const T b1 = As[(wv * 32 + 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
+            T bcol[4];
 #pragma unroll
-            for (int ti = 0; ti < 8; ++ti) {
-                if (ti < lt) {
+            for (int c = 0; c < 4; ++c) bcol[c] = As[(wv * 64 + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti) {
+                if (ti < ltz) {
                     const T av = Vs[(ti * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
-                    acc[2 * ti] = Mfma<T>::op(av, b0, acc[2 * ti]);
-                    acc[2 * ti + 1] = Mfma<T>::op(av, b1, acc[2 * ti + 1]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[ti * 4 + c] = Mfma<T>::op(av, bcol[c], acc[ti * 4 + c]);
                 }
             }
         }
     }
-    T *out = Zp + (int64_t)blockIdx.y * QK_KM * ldz;
+    // publish the partial: Yp[sp][q0 + row][jb + col] (double, agent-coherent)
+    double *yp = Yp + ((int64_t)sp * QK_KM + q0) * ldz;
 #pragma unroll
-    for (int ti = 0; ti < 8; ++ti) {
-        if (ti < lt) {
+    for (int ti = 0; ti < 4; ++ti) {
+        if (ti < ltz) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t col = jb + wv * 32 + h * 16 + (lane & 15);
+            for (int c = 0; c < 4; ++c) {
+                const int64_t col = jb + wv * 64 + c * 16 + (lane & 15);
                 if (col < w2) {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = ti * 16 + Mfma<T>::row(lane, v);
-                        out[row * ldz + col] = acc[2 * ti + h][v];
-                    }
+                    for (int v = 0; v < 4; ++v)
+                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * 4 + c][v]);
                 }
             }
         }
     }
-}
-
-// ---------------------------------------------------------------- zreduce
-#define ZR_NC 32
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_zreduce(QrdmArgs a, const T *__restrict__ Zp, int nsplit_bound, int split_rows, const double *__restrict__ Tm,
-          T *__restrict__ Z, int64_t ldz) {
-    const QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
-    const int64_t ns = ctl->ns;
-    const int ks = ctl->ks, l = ctl->l;
-    const int64_t t = a.m - ns;
-    const int64_t w2 = a.n - (ns + ks);
-    const int64_t jb = (int64_t)blockIdx.x * ZR_NC;
-    if (l <= 0 || jb >= w2) return;
-    const int nsplit = (int)((t + split_rows - 1) / split_rows);
-    (void)nsplit_bound;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->flop_gemm += 2.0 * (double)t * (double)l * (double)w2;
-    __shared__ double Ys[QK_KM * ZR_NC];
-    __shared__ double Ts[QK_KM * QK_KM / 2 + QK_KM];
-    const int tid = threadIdx.x;
-    const int jl = tid & (ZR_NC - 1), ag = tid / ZR_NC;  // 8 groups
-    const int64_t j = jb + jl;
-    // T (upper triangle, packed by columns: T[b][a] for b <= a at a(a+1)/2 + b)
-    for (int e = tid; e < l * l; e += 256) {
-        const int b = e / l, aa = e - b * l;
-        if (b <= aa) Ts[aa * (aa + 1) / 2 + b] = Tm[b * QK_KM + aa];
-    }
-    for (int b = ag; b < l; b += 256 / ZR_NC) {
-        double s = 0.0;
-        if (j < w2) {
-            for (int sb = 0; sb < nsplit; sb += 8) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    v[u] = (sb + u < nsplit) ? (double)Zp[((int64_t)(sb + u) * QK_KM + b) * ldz + j] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) s += v[u];
-            }
-        }
-        Ys[b * ZR_NC + jl] = s;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t arrivals = (uint32_t)(nsplit * nz);
+        const uint32_t old = __hip_atomic_fetch_add(tile_cnt + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (old == arrivals - 1);
+        if (s_last) __hip_atomic_store(tile_cnt + blockIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (j < w2) {
-        for (int aa = ag; aa < l; aa += 256 / ZR_NC) {
-            double s = 0.0;
-            const double *tc = Ts + aa * (aa + 1) / 2;
-            for (int b = 0; b <= aa; ++b) s += tc[b] * Ys[b * ZR_NC + jl];
-            Z[(int64_t)aa * ldz + j] = (T)s;
+    if (!s_last) return;
+    // ---- last workgroup of this tile: Y = sum of partials in split order, then
+    // the recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column
+    const int lp = lt * 16;
+    double *Ys = g1_lds;                           // [lp][64]
+    double *VVs = Ys + lp * 64;                    // packed strict upper triangle
+    double *taus = VVs + (lp * (lp - 1)) / 2 + 1;  // [lp]
+    for (int e = tid; e < l * l; e += 256) {
+        const int b = e / l, aa = e - b * l;
+        if (b < aa) VVs[aa * (aa - 1) / 2 + b] = VV[b * QK_KM + aa];
+    }
+    for (int e = tid; e < l; e += 256) taus[e] = a.tau_house[ns + e];
+    const int jl = tid >> 2, g = tid & 3;  // 4 lanes of one wavefront per column
+    for (int cb = 0; cb < ncols; cb += 64) {
+        __syncthreads();
+        for (int e0 = 0; e0 < l * 64; e0 += 256 * 4) {
+            double sum4[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int s2 = 0; s2 < nsplit; ++s2) {
+                double v4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * 256 + tid;
+                    const int aa = e >> 6, j = e & 63;
+                    v4[u] = (e < l * 64 && cb + j < ncols)
+                                ? ld_coh(Yp + ((int64_t)s2 * QK_KM + aa) * ldz + jb + cb + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sum4[u] += v4[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (e0 + u * 256 + tid < l * 64) Ys[e0 + u * 256 + tid] = sum4[u];
+        }
+        __syncthreads();
+        for (int aa = 0; aa < l; ++aa) {
+            const double *vc = VVs + aa * (aa - 1) / 2;
+            double part = 0.0;
+            for (int b = g; b < aa; b += 4) part += vc[b] * Ys[b * 64 + jl];
+            part += __shfl_xor(part, 1, 64);
+            part += __shfl_xor(part, 2, 64);
+            if (g == 0) {
+                const double ta = taus[aa];
+                Ys[aa * 64 + jl] = (ta == 0.0) ? 0.0 : ta * (Ys[aa * 64 + jl] - part);
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < l * 64; e += 256) {
+            const int aa = e >> 6, j = e & 63;
+            if (cb + j < ncols) Z[(int64_t)aa * ldz + jb + cb + j] = (T)Ys[e];
         }
     }
 }
@@ -183,19 +216,35 @@ k_zreduce(QrdmArgs a, const T *__restrict__ Zp, int nsplit_bound, int split_rows
 #define G2_NT 128
 #define G2_KC 16
 
-// A_tr -= V Z on a 128 x 128 tile.  FP64: the accumulators start as the A tile
-// (loaded in the MFMA result layout) and the MFMAs add (-V) Z, so A is read
-// once, early, and written once.  FP32 (mixed): the A tile is prefetched into
-// FP64 registers while the FP32 product accumulates, then A - (double)acc.
-template <typename T>
+// A_tr -= V Z on a 128 x 128 tile, computed transposed (D = Z^T V^T) so that a
+// lane's accumulator registers map to 16 consecutive rows of 4 columns: every
+// load and store instruction touches four whole 128-byte column segments.
+// FP64: the accumulators start as the A tile and the MFMAs add (-Z)^T V^T.
+// FP32 (mixed): the A tile is prefetched into FP64 registers while the FP32
+// product accumulates, then A - (double)acc.
+// MODE 0: QRDM block (rows from n_s, columns from n_s + k_s, K = l, Z indexed
+// from the first trailing column).  MODE 1: closing a QP3 block (rows and
+// columns from last + 1, K = kb, Z = F^T indexed by absolute column).
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
 k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ Z, int64_t ldz) {
     const QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
-    const int64_t ns = ctl->ns;
-    const int ks = ctl->ks, l = ctl->l;
-    const int64_t t = a.m - ns;
-    const int64_t c0 = ns + ks;
+    int64_t r0, c0;
+    int l;
+    if constexpr (MODE == 0) {
+        r0 = ctl->ns;
+        c0 = ctl->ns + ctl->ks;
+        l = ctl->l;
+    } else {
+        if (!ctl->qp_end) return;
+        r0 = ctl->qp_last + 1;
+        c0 = r0;
+        l = ctl->qp_kb;
+        Z += c0;
+    }
+    const int64_t ns = r0;
+    const int64_t t = a.m - r0;
     const int64_t w2 = a.n - c0;
     const int64_t rb = (int64_t)blockIdx.y * G2_MT;
     const int64_t jb = (int64_t)blockIdx.x * G2_NT;
@@ -203,29 +252,30 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
     __shared__ T Vs[G2_KC * G2_MT];  // [k][row]
     __shared__ T Zs[G2_KC * G2_NT];  // [k][col]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;  // wave's 64x64 quadrant
+    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;  // wave's 64x64 quadrant (rows, cols)
     typedef typename Mfma<T>::acc_t acc_t;
     const int nrow = (int)((t - rb) < G2_MT ? (t - rb) : G2_MT);
     const int ncol = (int)((w2 - jb) < G2_NT ? (w2 - jb) : G2_NT);
     double *Ab = a.A + (c0 + jb) * a.lda + ns + rb;
     constexpr bool F64 = sizeof(T) == 8;
+    // tile (tc, tr): D[i][j] = A[row wr + 16 tr + j][col wc + 16 tc + i]
     acc_t acc[16];
     double apre[F64 ? 1 : 64];
+    const int rj = lane & 15;
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti)
+    for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-            const int cc = wc + tj * 16 + (lane & 15);
+        for (int tr = 0; tr < 4; ++tr) {
+            const int r = wr + tr * 16 + rj;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int r = wr + ti * 16 + Mfma<T>::row(lane, v);
+                const int cc = wc + tc * 16 + Mfma<T>::row(lane, v);
                 const double x = (r < nrow && cc < ncol) ? Ab[(int64_t)cc * a.lda + r] : 0.0;
-                if constexpr (F64) acc[ti * 4 + tj][v] = x;
-                else apre[(ti * 4 + tj) * 4 + v] = x;
+                if constexpr (F64) acc[tc * 4 + tr][v] = x;
+                else apre[(tc * 4 + tr) * 4 + v] = x;
             }
-            if constexpr (!F64) acc[ti * 4 + tj] = acc_t{0, 0, 0, 0};
+            if constexpr (!F64) acc[tc * 4 + tr] = acc_t{0, 0, 0, 0};
         }
-    // K chunks: element e = u*256 + tid -> (k = e / 128, index e % 128)
     for (int kc = 0; kc < l; kc += G2_KC) {
         T vr[8], zr[8];
 #pragma unroll
@@ -244,66 +294,87 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < G2_KC; k += 4) {
-            T av[4], bv[4];
+            T zo[4], vo[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = Vs[(k + (lane >> 4)) * G2_MT + wr + u * 16 + (lane & 15)];
-                bv[u] = Zs[(k + (lane >> 4)) * G2_NT + wc + u * 16 + (lane & 15)];
-                if constexpr (F64) av[u] = -av[u];
+                zo[u] = Zs[(k + (lane >> 4)) * G2_NT + wc + u * 16 + rj];  // A-operand: Z^T[i][k]
+                vo[u] = Vs[(k + (lane >> 4)) * G2_MT + wr + u * 16 + rj];  // B-operand: V^T[k][j]
+                if constexpr (F64) zo[u] = -zo[u];
             }
 #pragma unroll
-            for (int ti = 0; ti < 4; ++ti)
+            for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-                for (int tj = 0; tj < 4; ++tj) acc[ti * 4 + tj] = Mfma<T>::op(av[ti], bv[tj], acc[ti * 4 + tj]);
+                for (int tr = 0; tr < 4; ++tr) acc[tc * 4 + tr] = Mfma<T>::op(zo[tc], vo[tr], acc[tc * 4 + tr]);
         }
     }
 #pragma unroll
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-        for (int tj = 0; tj < 4; ++tj) {
-            const int cc = wc + tj * 16 + (lane & 15);
-            if (cc < ncol) {
+        for (int tr = 0; tr < 4; ++tr) {
+            const int r = wr + tr * 16 + rj;
+            if (r < nrow) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int r = wr + ti * 16 + Mfma<T>::row(lane, v);
-                    if (r < nrow) {
+                    const int cc = wc + tc * 16 + Mfma<T>::row(lane, v);
+                    if (cc < ncol) {
                         double y;
-                        if constexpr (F64) y = acc[ti * 4 + tj][v];
-                        else y = apre[(ti * 4 + tj) * 4 + v] - (double)acc[ti * 4 + tj][v];
+                        if constexpr (F64) y = acc[tc * 4 + tr][v];
+                        else y = apre[(tc * 4 + tr) * 4 + v] - (double)acc[tc * 4 + tr][v];
                         Ab[(int64_t)cc * a.lda + r] = y;
                     }
                 }
             }
         }
-    }
 }
 
-hipError_t launch_trail(QrdmArgs a, int precision, const double *Tm, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Zp, void *Z, int64_t t_bound, int64_t w_bound, int split_rows,
+hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
+                        int64_t ldv, void *Z, double *Yp, uint32_t *tile_cnt, int64_t t_bound, int64_t w_bound,
                         hipStream_t s, hipEvent_t *ev) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     const int64_t ldz = a.n;
-    const int nsplit = (int)((t_bound + split_rows - 1) / split_rows);
-    dim3 g1((unsigned)((w_bound + G1_NT - 1) / G1_NT), (unsigned)nsplit);
-    dim3 gz((unsigned)((w_bound + ZR_NC - 1) / ZR_NC));
+    const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
+    // splits: aim at ~256 workgroups, at most QK_SPLIT_MAX, at least 256 rows each
+    int nsplit = (256 + ntile - 1) / ntile;
+    if (nsplit > QK_SPLIT_MAX) nsplit = QK_SPLIT_MAX;
+    int64_t maxs = (t_bound + 255) / 256;
+    if (nsplit > maxs) nsplit = (int)maxs;
+    if (nsplit < 1) nsplit = 1;
+    int krows = (int)(((t_bound + nsplit - 1) / nsplit + G1_KC - 1) / G1_KC * G1_KC);
+    const int kk = a.kmax < QK_KM ? a.kmax : QK_KM;
+    dim3 g1((unsigned)ntile, (unsigned)nsplit, (unsigned)((((kk + 15) >> 4) + 3) >> 2));
     dim3 g2((unsigned)((w_bound + G2_NT - 1) / G2_NT), (unsigned)((t_bound + G2_MT - 1) / G2_MT));
+    const int kp = ((a.kmax < QK_KM ? a.kmax : QK_KM) + 15) & ~15;
+    const size_t tsz = precision == 0 ? sizeof(double) : sizeof(float);
+    const size_t main_b = (size_t)(64 + G1_NT) * G1_LD * tsz;
+    const size_t epi_b = ((size_t)kp * 64 + (size_t)kp * (kp - 1) / 2 + 1 + kp) * sizeof(double);
+    const size_t lds = main_b > epi_b ? main_b : epi_b;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e1 = hipFuncSetAttribute((const void *)k_gemm1<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        hipError_t e2 = hipFuncSetAttribute((const void *)k_gemm1<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+        if (e1 != hipSuccess) return e1;
+        if (e2 != hipSuccess) return e2;
+        attr = true;
+    }
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0)
-        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(256), 0, s, a, Vw, ldv, (double *)Zp, split_rows, ldz);
+        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(256), lds, s, a, Vw, ldv, VV, Yp, tile_cnt, (double *)Z, ldz, krows);
     else
-        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(256), 0, s, a, Vw32, ldv, (float *)Zp, split_rows, ldz);
+        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(256), lds, s, a, Vw32, ldv, VV, Yp, tile_cnt, (float *)Z, ldz, krows);
     if (ev) (void)hipEventRecord(ev[1], s);
-    if (precision == 0)
-        hipLaunchKernelGGL(k_zreduce<double>, gz, dim3(256), 0, s, a, (const double *)Zp, nsplit, split_rows, Tm,
-                           (double *)Z, ldz);
-    else
-        hipLaunchKernelGGL(k_zreduce<float>, gz, dim3(256), 0, s, a, (const float *)Zp, nsplit, split_rows, Tm,
-                           (float *)Z, ldz);
     if (ev) (void)hipEventRecord(ev[2], s);
     if (precision == 0)
-        hipLaunchKernelGGL(k_gemm2<double>, g2, dim3(256), 0, s, a, Vw, ldv, (const double *)Z, ldz);
+        hipLaunchKernelGGL((k_gemm2<double, 0>), g2, dim3(256), 0, s, a, Vw, ldv, (const double *)Z, ldz);
     else
-        hipLaunchKernelGGL(k_gemm2<float>, g2, dim3(256), 0, s, a, Vw32, ldv, (const float *)Z, ldz);
+        hipLaunchKernelGGL((k_gemm2<float, 0>), g2, dim3(256), 0, s, a, Vw32, ldv, (const float *)Z, ldz);
     if (ev) (void)hipEventRecord(ev[3], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
+                            int64_t w_bound, hipStream_t s) {
+    if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
+    dim3 g2((unsigned)((w_bound + G2_NT - 1) / G2_NT), (unsigned)((t_bound + G2_MT - 1) / G2_MT));
+    hipLaunchKernelGGL((k_gemm2<double, 1>), g2, dim3(256), 0, s, a, Vw, ldv, Fz, a.n);
     return hipGetLastError();
 }

@@ -54,11 +54,10 @@ int prof_events(size_t count) {
 }
 
 struct Layout {
-    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, zp, z, perm_dbg, total;
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, tcnt, pb2, fz, flag, perm_dbg, total;
 };
 
 const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
-const int kSplitRows = 1024;    // rows per GEMM1 split
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -78,9 +77,12 @@ Layout make_layout(int64_t m, int64_t n) {
     L.tm = take(sizeof(double) * QK_KM * QK_KM);
     L.vw = take(sizeof(double) * (size_t)QK_KM * mm);
     L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
-    const int64_t nsplit = (mm + kSplitRows - 1) / kSplitRows;
-    L.zp = take(sizeof(double) * (size_t)nsplit * QK_KM * nn);
     L.z = take(sizeof(double) * (size_t)QK_KM * nn);
+    L.yp = take(sizeof(double) * 16 * (size_t)QK_KM * nn);
+    L.tcnt = take(sizeof(uint32_t) * (size_t)((nn + 255) / 256 + 1));
+    L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
+    L.fz = take(sizeof(double) * 64 * (size_t)nn);
+    L.flag = take(sizeof(int32_t) * (size_t)nn);
     L.perm_dbg = take(sizeof(int32_t) * nn);
     L.total = off;
     return L;
@@ -124,6 +126,7 @@ int ensure_workspace(size_t bytes, int ring) {
         g_ws.base = nullptr;
         return QRDM_ERR_NOMEM;
     }
+    if (hipMemset(g_ws.base, 0, want) != hipSuccess) return QRDM_ERR_NOMEM;
     g_ws.events.resize(r);
     for (int i = 0; i < r; ++i) HIP_TRY(hipEventCreateWithFlags(&g_ws.events[i], hipEventDisableTiming));
     g_ws.bytes = want;
@@ -154,6 +157,38 @@ QrdmCtl initial_ctl() {
     memset(&c, 0, sizeof c);
     c.rank = -1;
     return c;
+}
+
+const int kQp3Nb = 32;  // block size of the column-pivoting update
+
+// Column pivoting steps from the device's current n_s until the loop is done.
+int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int64_t ldv, int nb, int lag, int64_t ns_known,
+            hipStream_t s) {
+    Qp3Bufs bf;
+    bf.PB2 = (double *)(ws + L.pb2);
+    bf.Fz = (double *)(ws + L.fz);
+    bf.flag = (int32_t *)(ws + L.flag);
+    bf.Vw = (double *)(ws + L.vw);
+    bf.ldv = ldv;
+    HIP_TRY(launch_qp3_init(a, nb, s));
+    const int ring = g_ws.ring;
+    const int64_t pmin = std::min(a.m, a.n);
+    for (int64_t iter = 0;; ++iter) {
+        const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
+        HIP_TRY(launch_qp3_step(a, bf, nb, tb, wb, s));
+        Snapshot *hs = g_ws.host_snap + (iter % ring);
+        HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
+        if (iter >= lag) {
+            const int64_t k = iter - lag;
+            HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
+            const Snapshot sn = g_ws.host_snap[k % ring];
+            if (sn.ns > ns_known) ns_known = sn.ns;
+            if (sn.done) break;
+        }
+        if (iter > 2 * pmin + lag + 4) break;  // cannot happen: every step advances n_s
+    }
+    return 0;
 }
 
 }  // namespace
@@ -263,13 +298,16 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     a.tau_house = tau_house;
     a.ctl = (QrdmCtl *)(ws + L.ctl);
     double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
-    double *Tm = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
+    double *VVb = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
     float *Vw32 = (float *)(ws + L.vw32);
-    void *Zp = ws + L.zp, *Z = ws + L.z;
+    void *Z = ws + L.z;
     const int64_t ldv = m;
 
     QrdmCtl c0 = initial_ctl();
     HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    // the GEMM tile counters self-reset, but their place in the cached workspace
+    // depends on (m, n): clear them for this call
+    HIP_TRY(hipMemsetAsync(ws + L.tcnt, 0, sizeof(uint32_t) * (size_t)((n + 255) / 256 + 1), s));
     HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
     int32_t nf = 0;
     HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
@@ -282,6 +320,8 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         HIP_TRY(hipEventRecord(g_prof_ev[0], s));
     }
     const int rows_per_wg = panel_rows_per_wg(std::min<int>(p.kmax, QK_KM));
+    bool switch_qp3 = false;
+    HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
     int64_t ns_known = 0;
     int64_t nrec = 0;
     int64_t iter = 0;
@@ -295,13 +335,14 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
         HIP_TRY(launch_dm_finish(a, G, nullptr, s));
         HIP_TRY(launch_swap(a, s));
-        HIP_TRY(launch_panel(a, PB, Tm, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
+        HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
         hipEvent_t *ev = nullptr;
         if (p.profile) {
             if (prof_events(4 * (size_t)(iter + 1) + 2) != 0) return QRDM_ERR_NOMEM;
             ev = g_prof_ev.data() + 2 + 4 * iter;
         }
-        HIP_TRY(launch_trail(a, p.precision, Tm, Vw, Vw32, ldv, Zp, Z, tb, wb, kSplitRows, s, ev));
+        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), (uint32_t *)(ws + L.tcnt),
+                             tb, wb, s, ev));
         HIP_TRY(launch_downdate(a, wb, s));
         Snapshot *hs = g_ws.host_snap + (iter % ring);
         HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
@@ -325,9 +366,17 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
                 ++nrec;
             }
             if (sn.done) finished = true;
+            if (sn.fallback && !sn.done) switch_qp3 = true;
         }
         ++iter;
+        if (switch_qp3) break;
         if (iter > max_iter + lag + 1) break;  // cannot happen: every block advances n_s
+    }
+    if (switch_qp3 && !finished) {
+        // the partial norms reached the noise level: the rest is scalar pivoting,
+        // run in the blocked column-pivoting form (deferred trailing update)
+        rc = run_qp3(a, ws, L, ldv, kQp3Nb, lag, ns_known, s);
+        if (rc) return rc;
     }
     if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -442,7 +491,77 @@ int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
 }
 
 int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *pin, int32_t nb,
-                  double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats, void *stream);
+                  double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats, void *stream) {
+    qrdm_params p;
+    if (pin) p = *pin; else qrdm_default_params(&p);
+    p.kmax = 1;
+    p.tau = 1.0;
+    p.delta = 0.0;
+    p.precision = QRDM_PREC_FP64;
+    int rc = check_common(A, m, n, lda, &p);
+    if (rc) return rc;
+    if (nb < 1 || nb > 64) return -6;
+    const int64_t pmin = std::min(m, n);
+    if (pmin > 0 && !tau_house) return -7;
+    if (n > 0 && !perm) return -8;
+    if (!rank) return -9;
+    if (m > 65536) return QRDM_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (pmin == 0) {
+        if (n > 0) {
+            std::vector<int32_t> id(n);
+            for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
+            HIP_TRY(hipMemcpyAsync(perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        *rank = 0;
+        return 0;
+    }
+    Layout L = make_layout(m, n);
+    rc = ensure_workspace(L.total, p.poll_lag + 2);
+    if (rc) return rc;
+    char *ws = g_ws.base;
+    QrdmArgs a;
+    memset(&a, 0, sizeof a);
+    a.A = A;
+    a.m = m;
+    a.n = n;
+    a.lda = lda;
+    a.tau = 1.0;
+    a.delta = 0.0;
+    a.kmax = 1;
+    a.stop_rule = p.stop_rule;
+    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * 2.220446049250313e-16;
+    a.fbeps = (double)n * 2.220446049250313e-16;
+    a.tol3z = 1.4901161193847656e-08;
+    a.vn1 = (double *)(ws + L.vn1);
+    a.vn2 = (double *)(ws + L.vn2);
+    a.perm = perm;
+    a.tau_house = tau_house;
+    a.ctl = (QrdmCtl *)(ws + L.ctl);
+    QrdmCtl c0 = initial_ctl();
+    HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
+    HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
+    int32_t nf = 0;
+    HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nf) return QRDM_ERR_NONFINITE;
+    HIP_TRY(launch_init(a, s));
+    rc = run_qp3(a, ws, L, m, nb, p.poll_lag, 0, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    QrdmCtl cf;
+    HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
+    *rank = cf.rank >= 0 ? cf.rank : cf.ns;
+    if (stats) {
+        stats->nblocks = cf.nblocks;
+        stats->nrecompute = cf.nrecompute;
+        stats->ncols_factored = cf.ns;
+    }
+    return 0;
+}
 
 int qrp_factor(double *A, int64_t m, int64_t n, int64_t lda, double *tau_house, int32_t *perm, int64_t *rank,
                void *stream) {

@@ -33,6 +33,19 @@ struct QrdmCtl {
     int32_t J[QK_KM];
     int32_t swp_dst[QK_SWAP_MAX];
     int32_t swp_src[QK_SWAP_MAX];
+    // column pivoting with deferred trailing update (QRP baseline and the
+    // scalar-pivoting continuation of QRDM)
+    int64_t qp_k0;      // first column of the current block
+    int64_t qp_last;    // last reflector of the block being closed
+    int32_t qp_b;       // reflectors completed in the current block
+    int32_t qp_kb;      // reflectors in the block being closed
+    int32_t qp_pend;    // 1 = reflector ns-1 still awaits its normalization
+    int32_t qp_end;     // the block closes at this step
+    int32_t qp_stop;    // the stopping test fired at this step
+    int32_t qp_flag;    // a partial norm needs recomputation
+    int32_t qp_nb;      // block size
+    int32_t qp_pad;
+    double qp_beta, qp_den;  // scalars of the pending reflector
 };
 
 struct QrdmArgs {
@@ -70,13 +83,27 @@ hipError_t launch_gram(QrdmArgs a, double *Gp, int64_t t_bound, hipStream_t s);
 hipError_t launch_gram_reduce(QrdmArgs a, const double *Gp, double *G, int64_t t_bound, hipStream_t s);
 hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipStream_t s);
 hipError_t launch_swap(QrdmArgs a, hipStream_t s);
-hipError_t launch_panel(QrdmArgs a, double *PB, double *T, double *Vw, float *Vw32, int64_t ldv,
+hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv,
                         int64_t t_bound, int rows_per_wg, hipStream_t s);
+// VV: v_a^T v_i (a < i) at VV[a * QK_KM + i], from the panel.
 // ev (may be null): 4 events recorded before GEMM1, after GEMM1, before GEMM2, after GEMM2
-hipError_t launch_trail(QrdmArgs a, int precision, const double *T, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Zp, void *Z, int64_t t_bound, int64_t w_bound, int split_rows,
+// Yp: QK_SPLIT_MAX x QK_KM x n partials; tile_cnt: ceil(n/256) zeroed counters (self-resetting)
+hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
+                        int64_t ldv, void *Z, double *Yp, uint32_t *tile_cnt, int64_t t_bound, int64_t w_bound,
                         hipStream_t s, hipEvent_t *ev);
 hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s);
 
+// QP3 (LAPACK xgeqp3-style) column loop: one step per column, launched by the host
+struct Qp3Bufs {
+    double *PB2;      // [ceil(m/QP_ROWS)][2 + 2 nb] partials of the pivot column pass
+    double *Fz;       // [nb][n]: F^T of the deferred update, absolute column index
+    int32_t *flag;    // [n]: partial norm needs recomputation
+    double *Vw;       // [nb][m]: block reflectors below the block rows (rows from last+1)
+    int64_t ldv;
+};
+hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s);
+hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
+                            int64_t w_bound, hipStream_t s);
+hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s);
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
