@@ -191,12 +191,22 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
             if (tid == 0) a.tau_house[c] = ti;
         }
         __syncthreads();
-        // ---- apply H_i to the slab: rows below c, then row c
-        for (int r = rstart + wv; r < nrows; r += PN_WAVES) {
-            const double v = S[r * ksp + i] / den;
-            for (int jj = lane; jj < ks; jj += 64)
-                if (jj > i) S[r * ksp + jj] -= v * sW[jj];
-            if (lane == (i & 63)) S[r * ksp + i] = v;
+        // ---- apply H_i to the slab: rows below c, then row c.  v = x / (alpha - beta)
+        // is formed with one reciprocal per round, as LAPACK larfg scales by it.
+        {
+            const double rden = 1.0 / den;
+            const int j0 = lane, j1 = lane + 64;
+            const double w0 = (j0 > i && j0 < ks) ? sW[j0] : 0.0;
+            const double w1 = (j1 > i && j1 < ks) ? sW[j1] : 0.0;
+            const bool has1 = j1 < ks;
+            const bool own0 = (lane == i), own1 = (lane + 64 == i);
+#pragma unroll 4
+            for (int r = rstart + wv; r < nrows; r += PN_WAVES) {
+                double *row = S + r * ksp;
+                const double v = row[i] * rden;
+                if (j0 < ks) row[j0] = own0 ? v : row[j0] - v * w0;
+                if (has1) row[j1] = own1 ? v : row[j1] - v * w1;
+            }
         }
         if (cl >= 0 && wv == (cl % PN_WAVES)) {
             for (int jj = lane; jj < ks; jj += 64)

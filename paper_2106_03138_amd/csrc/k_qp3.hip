@@ -18,8 +18,9 @@
 //                corrected by the earlier reflectors of the block; the pivot
 //                row A[j, c] of R; the partial norm update of column c with the
 //                cancellation-safe recompute flag.
-//   k_qp_close   at block end: normalize the last reflector, stage V for the
-//                BLAS-3 update (then k_gemm2 mode 1), recompute flagged norms.
+//   k_gemm2      (mode 1) at block end, A_tr -= V F^T with V read in place.
+//   k_qp_close   at block end: recompute flagged norms; at the very end
+//                normalize the last reflector.
 #include <float.h>
 
 #include "qrdm_internal.h"
@@ -49,6 +50,18 @@ hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Does the step at column ns close the current block?  Evaluated identically by
+// every kernel after the GEMV pass (the fields it reads are final by then).
+__device__ __forceinline__ bool qp_closes(const QrdmCtl *c, int64_t p, int nb, int *kb, int64_t *last) {
+    const int b = c->qp_b;
+    const bool stop = c->qp_stop != 0;
+    const bool end = stop || (b + 1 == nb) || (c->ns + 1 == p) || c->qp_flag;
+    const int k = stop ? b : b + 1;  // reflectors in the block
+    *kb = k;
+    *last = c->qp_k0 + k - 1;
+    return end;
+}
+
 __device__ __forceinline__ bool qp_better(double va, int ja, double vb, int jb) {
     return va > vb || (va == vb && ja < jb);
 }
@@ -57,23 +70,23 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
     QrdmCtl *ctl = a.ctl;
     __shared__ double s_v[16];
     __shared__ int s_j[16];
-    __shared__ int s_go;
+    __shared__ int s_go, s_norm;
     if (ctl->done) return;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        // advance from the previous step
-        if (ctl->qp_end) {
-            ctl->qp_k0 = ctl->qp_last + 1;
+    if (tid == 0 && ctl->l == 1) {
+        // advance from the previous step, which made the reflector of column ns;
+        // that reflector stays pending (normalized by the next column pass)
+        int kb;
+        int64_t last;
+        if (qp_closes(ctl, p_of(a), ctl->qp_nb, &kb, &last)) {
+            ctl->qp_k0 = last + 1;
             ctl->qp_b = 0;
-            ctl->qp_pend = 0;
             ctl->qp_flag = 0;
-            ctl->qp_end = 0;
-            ctl->ns = ctl->qp_last + 1;
-        } else if (ctl->l == 1) {  // a reflector was made at column ns
+        } else {
             ctl->qp_b += 1;
-            ctl->qp_pend = 1;
-            ctl->ns += 1;
         }
+        ctl->qp_pend = 1;
+        ctl->ns += 1;
         ctl->l = 0;
     }
     __syncthreads();
@@ -101,6 +114,7 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
     if ((tid & 63) == 0) { s_v[tid >> 6] = bv; s_j[tid >> 6] = bj; }
     __syncthreads();
     if (tid == 0) {
+        s_norm = 0;
         double uv = s_v[0];
         int uj = s_j[0];
         for (int i = 1; i < 16; ++i)
@@ -122,6 +136,7 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
                         ctl->qp_stop = 1;
                     } else {
                         ctl->done = 1;
+                        s_norm = ctl->qp_pend;  // the previous block's last reflector
                     }
                 }
             }
@@ -139,6 +154,12 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
         s_go = go && (uj != j);
     }
     __syncthreads();
+    if (s_norm) {  // stopping right after a block end: normalize reflector j-1 in place
+        const double rden = 1.0 / ctl->qp_den;
+        for (int64_t r = j + tid; r < a.m; r += 1024) a.A[(j - 1) * a.lda + r] *= rden;
+        if (tid == 0) a.A[(j - 1) * a.lda + (j - 1)] = ctl->qp_beta;
+        return;
+    }
     // swap the F rows of columns j and jmax (F^T stored as Fz[b'][column])
     if (s_go) {
         const int uj = ctl->jmax;
@@ -171,7 +192,7 @@ __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz,
     if (r < a.m) {
         if (ctl->qp_pend) {
             const int64_t pc = j - 1;
-            if (r > pc) a.A[pc * a.lda + r] /= ctl->qp_den;
+            if (r > pc) a.A[pc * a.lda + r] *= 1.0 / ctl->qp_den;
             else if (r == pc) a.A[pc * a.lda + r] = ctl->qp_beta;
         }
         if (jm != j) {
@@ -296,53 +317,17 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
 }
 
 // ----------------------------------------------------------------- closing
-// Decides whether this step closes the block; if so normalizes the last
-// reflector and stages V rows below the block for the BLAS-3 update.
-__global__ void __launch_bounds__(256) k_qp_close_a(QrdmArgs a, double *Vw, int64_t ldv, int nb) {
+// After the block's BLAS-3 update (k_gemm2 mode 1, which reads V from A and
+// scales the pending reflector by 1/den): recompute the flagged partial norms
+// (wave per column) and, when the factorization ends here, normalize the last
+// reflector in place.
+__global__ void __launch_bounds__(256) k_qp_close(QrdmArgs a, int32_t *flag, int nb) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
-    const int64_t j = ctl->ns;
-    const int b = ctl->qp_b;
-    const int stop = ctl->qp_stop;
+    int kb;
+    int64_t last;
     const int64_t p = p_of(a);
-    const bool end = stop || (b + 1 == nb) || (j + 1 == p) || ctl->qp_flag;
-    if (!end) return;
-    const int kb = stop ? b : b + 1;  // reflectors in the block
-    const int64_t k0 = ctl->qp_k0;
-    const int64_t last = k0 + kb - 1;
-    const double den = ctl->qp_den, beta = ctl->qp_beta;
-    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    // the last reflector is the pending one: column j (normal) or j - 1 (stop)
-    if (r < a.m) {
-        if (r > last) a.A[last * a.lda + r] /= den;
-        else if (r == last) a.A[last * a.lda + r] = beta;
-        if (r > last)
-            for (int bb = 0; bb < kb; ++bb) Vw[(int64_t)bb * ldv + (r - last - 1)] = a.A[(k0 + bb) * a.lda + r];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // single writer; the rest of this grid reads only the fields above
-        ctl->qp_kb = kb;
-        ctl->qp_last = last;
-    }
-}
-
-// second phase: publish the decision (after every workgroup of close_a read it)
-__global__ void k_qp_close_b(QrdmArgs a, int nb) {
-    QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
-    const int64_t j = ctl->ns;
-    const int b = ctl->qp_b;
-    const int stop = ctl->qp_stop;
-    const int64_t p = p_of(a);
-    const bool end = stop || (b + 1 == nb) || (j + 1 == p) || ctl->qp_flag;
-    ctl->qp_end = end ? 1 : 0;
-}
-
-// after the BLAS-3 update: recompute the flagged partial norms (wave per column)
-__global__ void __launch_bounds__(256) k_qp_close_c(QrdmArgs a, int32_t *flag) {
-    QrdmCtl *ctl = a.ctl;
-    if (ctl->done || !ctl->qp_end) return;
-    const int64_t last = ctl->qp_last;
+    if (!qp_closes(ctl, p, nb, &kb, &last)) return;
     const int lane = threadIdx.x & 63;
     const int64_t c = last + 1 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (c < a.n && flag[c]) {
@@ -358,7 +343,15 @@ __global__ void __launch_bounds__(256) k_qp_close_c(QrdmArgs a, int32_t *flag) {
             atomicAdd((unsigned long long *)&ctl->nrecompute, 1ull);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->qp_stop) ctl->done = 1;
+    const bool final_step = ctl->qp_stop || last + 1 >= p;
+    if (final_step && kb > 0) {
+        const double rden = 1.0 / ctl->qp_den;
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t r = last + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.m; r += stride)
+            a.A[last * a.lda + r] *= rden;
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.A[last * a.lda + last] = ctl->qp_beta;
+    }
+    if (final_step && blockIdx.x == 0 && threadIdx.x == 0 && ctl->qp_stop) ctl->done = 1;
 }
 
 hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s) {
@@ -367,10 +360,8 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int6
     hipLaunchKernelGGL(k_qp_select, dim3(1), dim3(1024), 0, s, a, bf.Fz);
     hipLaunchKernelGGL(k_qp_column, dim3(g_rows), dim3(256), 0, s, a, bf.Fz, bf.PB2);
     hipLaunchKernelGGL(k_qp_gemv, dim3(g_cols), dim3(256), 0, s, a, bf.Fz, bf.PB2, bf.flag);
-    hipLaunchKernelGGL(k_qp_close_a, dim3(g_rows), dim3(256), 0, s, a, bf.Vw, bf.ldv, nb);
-    hipLaunchKernelGGL(k_qp_close_b, dim3(1), dim3(1), 0, s, a, nb);
-    hipError_t e = launch_gemm2_qp3(a, bf.Vw, bf.ldv, bf.Fz, t_bound, w_bound, s);
+    hipError_t e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_qp_close_c, dim3(g_cols), dim3(256), 0, s, a, bf.flag);
+    hipLaunchKernelGGL(k_qp_close, dim3(g_cols), dim3(256), 0, s, a, bf.flag, nb);
     return hipGetLastError();
 }

@@ -41,7 +41,8 @@ template <> struct Mfma<float> {
 
 // ------------------------------------------------------------------ GEMM1
 #define G1_NT 256   // trailing columns per workgroup (V reused across them)
-#define G1_KC 32    // rows staged per step
+#define G1_KC 16    // rows staged per step
+#define G1_TH 512   // threads: 8 wavefronts, 32 columns each
 #define G1_LD (G1_KC + 1)
 
 __device__ __forceinline__ void st_coh(double *p, double v) {
@@ -57,7 +58,7 @@ __device__ __forceinline__ double ld_coh(const double *p) {
 // workgroup of a column tile to arrive (tile counter) sums the partials in
 // split order and runs the recurrence for Z, 64 columns at a time.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(G1_TH)
 k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restrict__ VV, double *Yp,
         uint32_t *tile_cnt, T *__restrict__ Z, int64_t ldz, int krows) {
     QrdmCtl *ctl = a.ctl;
@@ -86,25 +87,25 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     typedef typename Mfma<T>::acc_t acc_t;
-    acc_t acc[16];
+    acc_t acc[8];  // 4 row tiles x 2 column tiles
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = acc_t{0, 0, 0, 0};
+    for (int u = 0; u < 8; ++u) acc[u] = acc_t{0, 0, 0, 0};
     const int ncols = (int)((w2 - jb) < G1_NT ? (w2 - jb) : G1_NT);
     const double *Abase = a.A + (c0 + jb) * a.lda + ns;
-    // staged element u*256 + tid: row r = tid % 32, column/reflector q = u*8 + tid/32
-    const int rr = tid & 31, qq = tid >> 5;
-    T vreg[8], areg[32];
+    // staged element u*512 + tid: row r = tid % 16, column/reflector q = u*32 + tid/16
+    const int rr = tid & 15, qq = tid >> 4;
+    T vreg[2], areg[8];
     auto fetch = [&](int64_t rc) {
         const int64_t row = rc + rr;
         const bool rok = row < re;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = q0 + u * 8 + qq;
+        for (int u = 0; u < 2; ++u) {
+            const int q = q0 + u * 32 + qq;
             vreg[u] = (rok && q < l) ? V[(int64_t)q * ldv + row] : (T)0;
         }
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int q = u * 8 + qq;
+        for (int u = 0; u < 8; ++u) {
+            const int q = u * 32 + qq;
             areg[u] = (rok && q < ncols) ? (T)Abase[(int64_t)q * a.lda + row] : (T)0;
         }
     };
@@ -112,23 +113,23 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     for (int64_t rc = rb; rc < re; rc += G1_KC) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 8; ++u) Vs[(u * 8 + qq) * G1_LD + rr] = vreg[u];
+        for (int u = 0; u < 2; ++u) Vs[(u * 32 + qq) * G1_LD + rr] = vreg[u];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) As[(u * 8 + qq) * G1_LD + rr] = areg[u];
+        for (int u = 0; u < 8; ++u) As[(u * 32 + qq) * G1_LD + rr] = areg[u];
         __syncthreads();
         if (rc + G1_KC < re) fetch(rc + G1_KC);
-        // wave wv owns columns [64 wv, 64 wv + 64): 4 column tiles x ltz row tiles
-#pragma unroll 2
-        for (int k = 0; k < G1_KC; k += 4) {
-            T bcol[4];
+        // wave wv owns columns [32 wv, 32 wv + 32): 2 column tiles x ltz row tiles
 #pragma unroll
-            for (int c = 0; c < 4; ++c) bcol[c] = As[(wv * 64 + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
+        for (int k = 0; k < G1_KC; k += 4) {
+            T bcol[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bcol[c] = As[(wv * 32 + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
 #pragma unroll
             for (int ti = 0; ti < 4; ++ti) {
                 if (ti < ltz) {
                     const T av = Vs[(ti * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[ti * 4 + c] = Mfma<T>::op(av, bcol[c], acc[ti * 4 + c]);
+                    for (int c = 0; c < 2; ++c) acc[ti * 2 + c] = Mfma<T>::op(av, bcol[c], acc[ti * 2 + c]);
                 }
             }
         }
@@ -139,12 +140,12 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     for (int ti = 0; ti < 4; ++ti) {
         if (ti < ltz) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int64_t col = jb + wv * 64 + c * 16 + (lane & 15);
+            for (int c = 0; c < 2; ++c) {
+                const int64_t col = jb + wv * 32 + c * 16 + (lane & 15);
                 if (col < w2) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * 4 + c][v]);
+                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * 2 + c][v]);
                 }
             }
         }
@@ -165,21 +166,21 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     double *Ys = g1_lds;                           // [lp][64]
     double *VVs = Ys + lp * 64;                    // packed strict upper triangle
     double *taus = VVs + (lp * (lp - 1)) / 2 + 1;  // [lp]
-    for (int e = tid; e < l * l; e += 256) {
+    for (int e = tid; e < l * l; e += G1_TH) {
         const int b = e / l, aa = e - b * l;
         if (b < aa) VVs[aa * (aa - 1) / 2 + b] = VV[b * QK_KM + aa];
     }
-    for (int e = tid; e < l; e += 256) taus[e] = a.tau_house[ns + e];
-    const int jl = tid >> 2, g = tid & 3;  // 4 lanes of one wavefront per column
+    for (int e = tid; e < l; e += G1_TH) taus[e] = a.tau_house[ns + e];
+    const int jl = tid >> 3, g = tid & 7;  // 8 lanes of one wavefront per column
     for (int cb = 0; cb < ncols; cb += 64) {
         __syncthreads();
-        for (int e0 = 0; e0 < l * 64; e0 += 256 * 4) {
+        for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 4) {
             double sum4[4] = {0.0, 0.0, 0.0, 0.0};
             for (int s2 = 0; s2 < nsplit; ++s2) {
                 double v4[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * 256 + tid;
+                    const int e = e0 + u * G1_TH + tid;
                     const int aa = e >> 6, j = e & 63;
                     v4[u] = (e < l * 64 && cb + j < ncols)
                                 ? ld_coh(Yp + ((int64_t)s2 * QK_KM + aa) * ldz + jb + cb + j) : 0.0;
@@ -189,22 +190,23 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (e0 + u * 256 + tid < l * 64) Ys[e0 + u * 256 + tid] = sum4[u];
+                if (e0 + u * G1_TH + tid < l * 64) Ys[e0 + u * G1_TH + tid] = sum4[u];
         }
         __syncthreads();
         for (int aa = 0; aa < l; ++aa) {
             const double *vc = VVs + aa * (aa - 1) / 2;
             double part = 0.0;
-            for (int b = g; b < aa; b += 4) part += vc[b] * Ys[b * 64 + jl];
+            for (int b = g; b < aa; b += 8) part += vc[b] * Ys[b * 64 + jl];
             part += __shfl_xor(part, 1, 64);
             part += __shfl_xor(part, 2, 64);
+            part += __shfl_xor(part, 4, 64);
             if (g == 0) {
                 const double ta = taus[aa];
                 Ys[aa * 64 + jl] = (ta == 0.0) ? 0.0 : ta * (Ys[aa * 64 + jl] - part);
             }
         }
         __syncthreads();
-        for (int e = tid; e < l * 64; e += 256) {
+        for (int e = tid; e < l * 64; e += G1_TH) {
             const int aa = e >> 6, j = e & 63;
             if (cb + j < ncols) Z[(int64_t)aa * ldz + jb + cb + j] = (T)Ys[e];
         }
@@ -226,22 +228,31 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
 // from the first trailing column).  MODE 1: closing a QP3 block (rows and
 // columns from last + 1, K = kb, Z = F^T indexed by absolute column).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ Z, int64_t ldz) {
     const QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     int64_t r0, c0;
     int l;
+    double rpend = 1.0;  // mode 1: the block's last reflector is stored unscaled
+    int64_t vk0 = 0;     // mode 1: first column of V in A
     if constexpr (MODE == 0) {
         r0 = ctl->ns;
         c0 = ctl->ns + ctl->ks;
         l = ctl->l;
     } else {
-        if (!ctl->qp_end) return;
-        r0 = ctl->qp_last + 1;
+        // QP3 block end: same predicate as the column-pivoting kernels
+        const int b = ctl->qp_b;
+        const bool stop = ctl->qp_stop != 0;
+        const int64_t pmin = a.m < a.n ? a.m : a.n;
+        if (!(stop || (b + 1 == ctl->qp_nb) || (ctl->ns + 1 == pmin) || ctl->qp_flag)) return;
+        l = stop ? b : b + 1;
+        const int64_t last = ctl->qp_k0 + l - 1;
+        r0 = last + 1;
         c0 = r0;
-        l = ctl->qp_kb;
         Z += c0;
+        rpend = 1.0 / ctl->qp_den;
+        vk0 = ctl->qp_k0;
     }
     const int64_t ns = r0;
     const int64_t t = a.m - r0;
@@ -252,65 +263,71 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
     __shared__ T Vs[G2_KC * G2_MT];  // [k][row]
     __shared__ T Zs[G2_KC * G2_NT];  // [k][col]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wr = (wv >> 1) * 64, wc = (wv & 1) * 64;  // wave's 64x64 quadrant (rows, cols)
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 64;  // wave's 32 x 64 block (rows, cols)
     typedef typename Mfma<T>::acc_t acc_t;
     const int nrow = (int)((t - rb) < G2_MT ? (t - rb) : G2_MT);
     const int ncol = (int)((w2 - jb) < G2_NT ? (w2 - jb) : G2_NT);
     double *Ab = a.A + (c0 + jb) * a.lda + ns + rb;
     constexpr bool F64 = sizeof(T) == 8;
     // tile (tc, tr): D[i][j] = A[row wr + 16 tr + j][col wc + 16 tc + i]
-    acc_t acc[16];
-    double apre[F64 ? 1 : 64];
+    acc_t acc[8];
+    double apre[F64 ? 1 : 32];
     const int rj = lane & 15;
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-        for (int tr = 0; tr < 4; ++tr) {
+        for (int tr = 0; tr < 2; ++tr) {
             const int r = wr + tr * 16 + rj;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int cc = wc + tc * 16 + Mfma<T>::row(lane, v);
                 const double x = (r < nrow && cc < ncol) ? Ab[(int64_t)cc * a.lda + r] : 0.0;
-                if constexpr (F64) acc[tc * 4 + tr][v] = x;
-                else apre[(tc * 4 + tr) * 4 + v] = x;
+                if constexpr (F64) acc[tc * 2 + tr][v] = x;
+                else apre[(tc * 2 + tr) * 4 + v] = x;
             }
-            if constexpr (!F64) acc[tc * 4 + tr] = acc_t{0, 0, 0, 0};
+            if constexpr (!F64) acc[tc * 2 + tr] = acc_t{0, 0, 0, 0};
         }
     for (int kc = 0; kc < l; kc += G2_KC) {
-        T vr[8], zr[8];
+        T vr[4], zr[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int e = u * 256 + tid, k = e >> 7, r = e & 127;
+        for (int u = 0; u < 4; ++u) {
+            const int e = u * 512 + tid, k = e >> 7, r = e & 127;
             const bool kok = kc + k < l;
-            vr[u] = (kok && r < nrow) ? V[(int64_t)(kc + k) * ldv + rb + r] : (T)0;
+            if constexpr (MODE == 0) {
+                vr[u] = (kok && r < nrow) ? V[(int64_t)(kc + k) * ldv + rb + r] : (T)0;
+            } else {
+                const double sc = (kc + k == l - 1) ? rpend : 1.0;
+                vr[u] = (kok && r < nrow) ? (T)(V[(vk0 + kc + k) * ldv + ns + rb + r] * sc) : (T)0;
+            }
             zr[u] = (kok && r < ncol) ? Z[(int64_t)(kc + k) * ldz + jb + r] : (T)0;
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            Vs[u * 256 + tid] = vr[u];
-            Zs[u * 256 + tid] = zr[u];
+        for (int u = 0; u < 4; ++u) {
+            Vs[u * 512 + tid] = vr[u];
+            Zs[u * 512 + tid] = zr[u];
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < G2_KC; k += 4) {
-            T zo[4], vo[4];
+            T zo[4], vo[2];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 zo[u] = Zs[(k + (lane >> 4)) * G2_NT + wc + u * 16 + rj];  // A-operand: Z^T[i][k]
-                vo[u] = Vs[(k + (lane >> 4)) * G2_MT + wr + u * 16 + rj];  // B-operand: V^T[k][j]
                 if constexpr (F64) zo[u] = -zo[u];
             }
 #pragma unroll
+            for (int u = 0; u < 2; ++u) vo[u] = Vs[(k + (lane >> 4)) * G2_MT + wr + u * 16 + rj];  // B: V^T[k][j]
+#pragma unroll
             for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-                for (int tr = 0; tr < 4; ++tr) acc[tc * 4 + tr] = Mfma<T>::op(zo[tc], vo[tr], acc[tc * 4 + tr]);
+                for (int tr = 0; tr < 2; ++tr) acc[tc * 2 + tr] = Mfma<T>::op(zo[tc], vo[tr], acc[tc * 2 + tr]);
         }
     }
 #pragma unroll
     for (int tc = 0; tc < 4; ++tc)
 #pragma unroll
-        for (int tr = 0; tr < 4; ++tr) {
+        for (int tr = 0; tr < 2; ++tr) {
             const int r = wr + tr * 16 + rj;
             if (r < nrow) {
 #pragma unroll
@@ -318,8 +335,8 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
                     const int cc = wc + tc * 16 + Mfma<T>::row(lane, v);
                     if (cc < ncol) {
                         double y;
-                        if constexpr (F64) y = acc[tc * 4 + tr][v];
-                        else y = apre[(tc * 4 + tr) * 4 + v] - (double)acc[tc * 4 + tr][v];
+                        if constexpr (F64) y = acc[tc * 2 + tr][v];
+                        else y = apre[(tc * 2 + tr) * 4 + v] - (double)acc[tc * 2 + tr][v];
                         Ab[(int64_t)cc * a.lda + r] = y;
                     }
                 }
@@ -358,15 +375,15 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     }
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0)
-        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(256), lds, s, a, Vw, ldv, VV, Yp, tile_cnt, (double *)Z, ldz, krows);
+        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), lds, s, a, Vw, ldv, VV, Yp, tile_cnt, (double *)Z, ldz, krows);
     else
-        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(256), lds, s, a, Vw32, ldv, VV, Yp, tile_cnt, (float *)Z, ldz, krows);
+        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), lds, s, a, Vw32, ldv, VV, Yp, tile_cnt, (float *)Z, ldz, krows);
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);
     if (precision == 0)
-        hipLaunchKernelGGL((k_gemm2<double, 0>), g2, dim3(256), 0, s, a, Vw, ldv, (const double *)Z, ldz);
+        hipLaunchKernelGGL((k_gemm2<double, 0>), g2, dim3(512), 0, s, a, Vw, ldv, (const double *)Z, ldz);
     else
-        hipLaunchKernelGGL((k_gemm2<float, 0>), g2, dim3(256), 0, s, a, Vw32, ldv, (const float *)Z, ldz);
+        hipLaunchKernelGGL((k_gemm2<float, 0>), g2, dim3(512), 0, s, a, Vw32, ldv, (const float *)Z, ldz);
     if (ev) (void)hipEventRecord(ev[3], s);
     return hipGetLastError();
 }
@@ -375,6 +392,6 @@ hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const dou
                             int64_t w_bound, hipStream_t s) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     dim3 g2((unsigned)((w_bound + G2_NT - 1) / G2_NT), (unsigned)((t_bound + G2_MT - 1) / G2_MT));
-    hipLaunchKernelGGL((k_gemm2<double, 1>), g2, dim3(256), 0, s, a, Vw, ldv, Fz, a.n);
+    hipLaunchKernelGGL((k_gemm2<double, 1>), g2, dim3(512), 0, s, a, Vw, ldv, Fz, a.n);
     return hipGetLastError();
 }

@@ -162,31 +162,33 @@ QrdmCtl initial_ctl() {
 const int kQp3Nb = 32;  // block size of the column-pivoting update
 
 // Column pivoting steps from the device's current n_s until the loop is done.
-int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int64_t ldv, int nb, int lag, int64_t ns_known,
-            hipStream_t s) {
+int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64_t ns_known, hipStream_t s) {
     Qp3Bufs bf;
     bf.PB2 = (double *)(ws + L.pb2);
     bf.Fz = (double *)(ws + L.fz);
     bf.flag = (int32_t *)(ws + L.flag);
-    bf.Vw = (double *)(ws + L.vw);
-    bf.ldv = ldv;
     HIP_TRY(launch_qp3_init(a, nb, s));
     const int ring = g_ws.ring;
     const int64_t pmin = std::min(a.m, a.n);
+    // snapshots every kStride steps; the host waits on the one `lag` snapshots back
+    const int kStride = 4;
+    int64_t nsnap = 0;
     for (int64_t iter = 0;; ++iter) {
         const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
         HIP_TRY(launch_qp3_step(a, bf, nb, tb, wb, s));
-        Snapshot *hs = g_ws.host_snap + (iter % ring);
+        if ((iter + 1) % kStride != 0) continue;
+        Snapshot *hs = g_ws.host_snap + (nsnap % ring);
         HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
-        if (iter >= lag) {
-            const int64_t k = iter - lag;
+        HIP_TRY(hipEventRecord(g_ws.events[nsnap % ring], s));
+        if (nsnap >= lag) {
+            const int64_t k = nsnap - lag;
             HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
             const Snapshot sn = g_ws.host_snap[k % ring];
             if (sn.ns > ns_known) ns_known = sn.ns;
             if (sn.done) break;
         }
-        if (iter > 2 * pmin + lag + 4) break;  // cannot happen: every step advances n_s
+        ++nsnap;
+        if (iter > 2 * pmin + kStride * (lag + 4)) break;  // cannot happen: every step advances n_s
     }
     return 0;
 }
@@ -375,7 +377,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     if (switch_qp3 && !finished) {
         // the partial norms reached the noise level: the rest is scalar pivoting,
         // run in the blocked column-pivoting form (deferred trailing update)
-        rc = run_qp3(a, ws, L, ldv, kQp3Nb, lag, ns_known, s);
+        rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s);
         if (rc) return rc;
     }
     if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
@@ -549,7 +551,7 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     HIP_TRY(hipStreamSynchronize(s));
     if (nf) return QRDM_ERR_NONFINITE;
     HIP_TRY(launch_init(a, s));
-    rc = run_qp3(a, ws, L, m, nb, p.poll_lag, 0, s);
+    rc = run_qp3(a, ws, L, nb, p.poll_lag, 0, s);
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;

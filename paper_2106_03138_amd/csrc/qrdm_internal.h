@@ -98,8 +98,6 @@ struct Qp3Bufs {
     double *PB2;      // [ceil(m/QP_ROWS)][2 + 2 nb] partials of the pivot column pass
     double *Fz;       // [nb][n]: F^T of the deferred update, absolute column index
     int32_t *flag;    // [n]: partial norm needs recomputation
-    double *Vw;       // [nb][m]: block reflectors below the block rows (rows from last+1)
-    int64_t ldv;
 };
 hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s);
 hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
