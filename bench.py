@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 
 
 def make_input(n, spectrum, seed, torch):
@@ -67,6 +68,62 @@ def flops_cols(m, n, r):
     return float(np.sum(4.0 * (m - s) * (n - s)))
 
 
+KERNEL_SOURCES = {"k_panel": "k_panel.hip", "k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip"}
+
+
+def source_sha(kernel):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2106_03138_amd", "csrc", KERNEL_SOURCES[kernel])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(kernel, workload_tag):
+    """HBM bytes per launch from the committed counter summary of this kernel and
+    workload (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or
+    None when there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_tag}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_sha(kernel):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(prof, prec, Q, workload_tag=None):
+    """Roofline of the kernel with the largest summed time.  The panel is
+    HBM-bound (arithmetic intensity k_s/8 flop/B is below the FP64 ridge of
+    78.6/8 = 9.8 flop/B); the two trailing GEMMs are MFMA-bound."""
+    times = {"k_panel": prof["panel_ms"], "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"]}
+    dom = max(times, key=times.get)
+    nlaunch = max(int(prof["npanel"]), 1)  # one panel and one launch of each GEMM per block
+    if dom == "k_panel":
+        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
+        work = prof["panel_bytes"]
+        achieved = work / (times[dom] * 1e-3) / 1e9
+    else:
+        bound, unit = "mfma", "TFLOP/s"
+        peak = PEAK_FP32_TFLOPS if prec == Q.PREC_MIXED else PEAK_FP64_TFLOPS
+        work = prof["gemm_flop"]
+        achieved = work / (times[dom] * 1e-3) / 1e12
+    traffic = measured_traffic(dom, workload_tag) if workload_tag else None
+    return {"bound": bound, "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5), "traffic": traffic,
+            "launches": nlaunch, "avg_launch_us": round(1e3 * times[dom] / nlaunch, 2),
+            "algorithmic_per_launch": work / nlaunch,
+            "phase_ms": {"dm_select": round(prof["dm_ms"], 3), "panel": round(prof["panel_ms"], 3),
+                         "gemm1": round(prof["gemm1_ms"], 3), "gemm2": round(prof["gemm2_ms"], 3),
+                         "downdate": round(prof["downdate_ms"], 3), "qp3_tail": round(prof["qp3_ms"], 3),
+                         "loop_total": round(prof["total_ms"], 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +136,12 @@ def main():
     ap.add_argument("--delta", type=float, default=0.9)
     ap.add_argument("--kmax", type=int, default=64)
     ap.add_argument("--qrp-runs", type=int, default=1)
-    ap.add_argument("--cpu-sample-cols", type=int, default=192)
+    ap.add_argument("--cpu-sample-cols", type=int, default=1536)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a plain elementwise copy of this many MiB (for counter calibration)")
+    ap.add_argument("--no-profile-run", action="store_true")
+    ap.add_argument("--input-cache", default="",
+                    help=".npy file holding the input: loaded if present, else written after generation")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -94,7 +156,21 @@ def main():
     torch.cuda.set_device(0)
     n = m = args.size
     prec = Q.PREC_MIXED if args.precision == "mixed" else Q.PREC_FP64
-    a0 = make_input(n, args.spectrum, args.seed, torch)
+    if args.copy_calibration_mb > 0:
+        # a plain copy kernel of known traffic: reads and writes N float64 once each
+        cnt = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(cnt, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.input_cache and os.path.exists(args.input_cache):
+        a0 = torch.from_numpy(np.load(args.input_cache)).cuda().t()  # stored as the (n, m) row-major A^T
+    else:
+        a0 = make_input(n, args.spectrum, args.seed, torch)
+        if args.input_cache:
+            np.save(args.input_cache, a0.t().contiguous().cpu().numpy())
     A = torch.empty_like(a0.t().contiguous()).t()
     tau_h = torch.empty(n, dtype=torch.float64, device="cuda")
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -116,13 +192,13 @@ def main():
     F = flops_full(m, n)
     value = F / (ms * 1e-3) / 1e12
 
-    # dominant kernel, timed with HIP events on the library's stream
-    prof = step(profile=True).stats
-    g1, g2, gf = prof["gemm1_ms"], prof["gemm2_ms"], prof["gemm_flop"]
-    dom = "k_gemm2" if g2 >= g1 else "k_gemm1"
-    dom_ms = max(g1, g2)
-    peak = PEAK_FP32_TFLOPS if prec == Q.PREC_MIXED else PEAK_FP64_TFLOPS
-    achieved = gf / (dom_ms * 1e-3) / 1e12 if dom_ms > 0 else 0.0
+    # per-phase times from HIP events on the library's stream; the dominant kernel
+    # is the single kernel with the largest summed time
+    tag = f"qrdm{m}_{args.spectrum}_{args.precision}"
+    roof = None
+    if not args.no_profile_run:
+        prof = step(profile=True).stats
+        roof = roofline(prof, prec, Q, tag)
     rank = outs[-1].rank
     st = outs[-1].stats
 
@@ -146,7 +222,7 @@ def main():
     if args.cpu_sample_cols > 0:
         import oracle
         host = np.asfortranarray(a0.t().contiguous().cpu().numpy().T)
-        cores = len(os.sched_getaffinity(0))
+        cores = oracle.threads()
         c0 = time.perf_counter()
         res = oracle.qrdm(host, tau=args.tau, delta=args.delta, kmax=args.kmax, stop_rule=oracle.STOP_NONE,
                           max_ns=args.cpu_sample_cols, log_cap=args.cpu_sample_cols + 2)
@@ -174,10 +250,7 @@ def main():
                                f"k_DM={args.kmax}, stop off (full), {args.precision}",
                    "m": m, "n": n, "flop": F, "rank_paper_rule": rank,
                    "blocks": st["nblocks"], "breaks": st["nbreaks"], "recomputes": st["nrecompute"]},
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "gemm1_ms": round(g1, 3), "gemm2_ms": round(g2, 3),
-                     "gemm_flop_per_kernel": gf, "loop_ms_profiled": round(prof["total_ms"], 3)},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "qrp": qrp,
     }

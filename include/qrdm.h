@@ -85,6 +85,14 @@ typedef struct {
     double gemm_flop;    /* algorithmic flops of ONE of the two GEMMs, summed over blocks:
                             sum 2 t l w (t rows, l reflectors, w trailing columns)         */
     double total_ms;     /* event time of the whole factorization loop                    */
+    double dm_ms;        /* DM selection per block: select, Gram, greedy, swaps            */
+    double panel_ms;     /* Householder panels with break                                  */
+    double downdate_ms;  /* partial-norm downdates and recomputes after each block         */
+    double qp3_ms;       /* the scalar-pivoting continuation (column pivoting steps)       */
+    double panel_flop;   /* algorithmic flops of the panels: per reflector i of a block,
+                            (t-i)(2 + 4(k_s-1-i))                                          */
+    double panel_bytes;  /* algorithmic bytes of the panels: 16 t k_s per block            */
+    int64_t npanel;      /* panel launches that factored a block (always filled)            */
 } qrdm_stats;
 
 /* One record per outer step, for tests and tracing. */

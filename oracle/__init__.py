@@ -123,3 +123,8 @@ def dm_step(a: np.ndarray, vn1: np.ndarray, ns: int, tau: float, delta: float, c
         raise RuntimeError(f"oracle_dm_step failed: {code}")
     k = nl.value
     return L[:k].copy(), th[: k * k].reshape(k, k).copy(), J[: ks.value].copy()
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())

@@ -51,6 +51,9 @@
  * Build: gcc -O2 -fPIC -shared -ffp-contract=off -fopenmp (see build_oracle.py).
  */
 #include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -529,3 +532,12 @@ int oracle_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t n
 }
 
 size_t oracle_block_size(void) { return sizeof(oracle_block); }
+
+/* Threads the OpenMP loops of the trailing update use (for reporting timings). */
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -24,7 +24,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("nblocks", ctypes.c_int64), ("nbreaks", ctypes.c_int64), ("nfallback", ctypes.c_int64),
                 ("nrecompute", ctypes.c_int64), ("ncols_factored", ctypes.c_int64),
                 ("gemm1_ms", ctypes.c_double), ("gemm2_ms", ctypes.c_double), ("gemm_flop", ctypes.c_double),
-                ("total_ms", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("dm_ms", ctypes.c_double), ("panel_ms", ctypes.c_double),
+                ("downdate_ms", ctypes.c_double), ("qp3_ms", ctypes.c_double), ("panel_flop", ctypes.c_double),
+                ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64)]
 
 
 class Block(ctypes.Structure):

@@ -232,6 +232,12 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
     if (wg == 0 && tid == 0) {
         ctl->l = l;
         if (l < ks) ctl->nbreaks += 1;
+        // reflector i: norm 2(t-i), apply to the ks-1-i panel columns to its right 4(t-i)(ks-1-i)
+        double f = 0.0;
+        for (int i = 0; i < l; ++i) f += (double)(t - i) * (2.0 + 4.0 * (double)(ks - 1 - i));
+        ctl->flop_panel += f;
+        ctl->bytes_panel += 16.0 * (double)t * (double)ks;
+        ctl->npanel += 1;
     }
 }
 

@@ -318,7 +318,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     HIP_TRY(launch_init(a, s));
 
     if (p.profile) {
-        if (prof_events(2) != 0) return QRDM_ERR_NOMEM;
+        if (prof_events(3) != 0) return QRDM_ERR_NOMEM;
         HIP_TRY(hipEventRecord(g_prof_ev[0], s));
     }
     const int rows_per_wg = panel_rows_per_wg(std::min<int>(p.kmax, QK_KM));
@@ -330,22 +330,30 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     bool finished = false;
     const int ring = g_ws.ring;
     const int64_t max_iter = pmin + 2;
+    // profile events per block: [0] select, [1] panel, [2] panel end, [3..6] the two
+    // GEMMs (start/end each), [7] downdate end; g_prof_ev[0..2] = loop start, QP3
+    // start, loop end
+    const int kEv = 8;
     while (!finished) {
         const int64_t tb = m - ns_known, wb = n - ns_known;
+        hipEvent_t *ev = nullptr;
+        if (p.profile) {
+            if (prof_events(kEv * (size_t)(iter + 1) + 3) != 0) return QRDM_ERR_NOMEM;
+            ev = g_prof_ev.data() + 3 + kEv * iter;
+            HIP_TRY(hipEventRecord(ev[0], s));
+        }
         HIP_TRY(launch_select(a, s));
         HIP_TRY(launch_gram(a, Gp, tb, s));
         HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
         HIP_TRY(launch_dm_finish(a, G, nullptr, s));
         HIP_TRY(launch_swap(a, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
-        hipEvent_t *ev = nullptr;
-        if (p.profile) {
-            if (prof_events(4 * (size_t)(iter + 1) + 2) != 0) return QRDM_ERR_NOMEM;
-            ev = g_prof_ev.data() + 2 + 4 * iter;
-        }
+        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
         HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), (uint32_t *)(ws + L.tcnt),
-                             tb, wb, s, ev));
+                             tb, wb, s, ev ? ev + 3 : nullptr));
         HIP_TRY(launch_downdate(a, wb, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[7], s));
         Snapshot *hs = g_ws.host_snap + (iter % ring);
         HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
@@ -374,28 +382,39 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (switch_qp3) break;
         if (iter > max_iter + lag + 1) break;  // cannot happen: every block advances n_s
     }
+    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
     if (switch_qp3 && !finished) {
         // the partial norms reached the noise level: the rest is scalar pivoting,
         // run in the blocked column-pivoting form (deferred trailing update)
         rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s);
         if (rc) return rc;
     }
-    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
+    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[2], s));
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;
     HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
     if (stats && p.profile) {
-        float ms = 0.f;
-        double g1 = 0.0, g2 = 0.0;
+        // intervals (e, e+1): 0 DM selection, 1 panel, 3 GEMM1 (with the fused
+        // recurrence), 5 GEMM2, 6 downdate; 2 and 4 are empty gaps
+        double t[kEv - 1] = {0};
         for (int64_t k = 0; k < iter; ++k) {
-            hipEvent_t *ev = g_prof_ev.data() + 2 + 4 * k;
-            if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) g1 += ms;
-            if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) g2 += ms;
+            hipEvent_t *ev = g_prof_ev.data() + 3 + kEv * k;
+            for (int e = 0; e + 1 < kEv; ++e) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) == hipSuccess) t[e] += ms;
+            }
         }
-        stats->gemm1_ms = g1;
-        stats->gemm2_ms = g2;
+        stats->dm_ms = t[0];
+        stats->panel_ms = t[1];
+        stats->gemm1_ms = t[3];
+        stats->gemm2_ms = t[5];
+        stats->downdate_ms = t[6];
         stats->gemm_flop = cf.flop_gemm;
-        if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[1]) == hipSuccess) stats->total_ms = ms;
+        stats->panel_flop = cf.flop_panel;
+        stats->panel_bytes = cf.bytes_panel;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof_ev[1], g_prof_ev[2]) == hipSuccess) stats->qp3_ms = ms;
+        if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[2]) == hipSuccess) stats->total_ms = ms;
     }
     if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     *rank = cf.rank >= 0 ? cf.rank : cf.ns;
@@ -405,6 +424,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         stats->nfallback = cf.nfallback;
         stats->nrecompute = cf.nrecompute;
         stats->ncols_factored = cf.ns;
+        stats->npanel = cf.npanel;
     }
     if (nlog) *nlog = nrec;
     if (log && lag == 0) {

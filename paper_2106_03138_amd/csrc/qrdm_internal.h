@@ -29,6 +29,9 @@ struct QrdmCtl {
     // statistics
     int64_t nblocks, nbreaks, nfallback, nrecompute;
     double flop_gemm;  // algorithmic flops of one trailing GEMM (2 t l w), summed over blocks
+    double flop_panel;   // algorithmic flops of the Householder panels, summed over blocks
+    double bytes_panel;  // algorithmic bytes of the panels (slab read + written: 16 t k_s)
+    int64_t npanel;      // panels that factored a block
     int32_t L[QK_KM];
     int32_t J[QK_KM];
     int32_t swp_dst[QK_SWAP_MAX];

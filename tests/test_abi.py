@@ -1,0 +1,110 @@
+"""The C ABI without a GPU: libqrdm.so loads, exports every function that
+include/qrdm.h declares, and the ctypes mirrors of the header's structs have
+the header's layout.  No compute call is made."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qrdm.h")
+LIB = os.path.join(ROOT, "paper_2106_03138_amd", "libqrdm.so")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("QRDM")))
+
+
+def _struct_sizes():
+    """sizeof/offsetof of the header's structs, from a host C compiler."""
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "qrdm.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(qrdm_params), sizeof(qrdm_stats), sizeof(qrdm_block));
+  printf("%zu %zu %zu\n", offsetof(qrdm_params, eps1_scale), offsetof(qrdm_params, profile),
+         offsetof(qrdm_stats, total_ms));
+  printf("%zu %zu\n", offsetof(qrdm_block, fallback), offsetof(qrdm_block, umax));
+  return 0;
+}
+"""
+    return src
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libqrdm.so not built (python -m paper_2106_03138_amd.build)")
+    import torch  # noqa: F401  (same HIP runtime as the library)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_expected_entry_points():
+    names = _declared_functions()
+    for want in ["qrdm_factor", "qrdm_factor_ex", "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
+                 "qrdm_dm_step", "qrdm_default_params", "qrdm_release", "qrdm_strerror"]:
+        assert want in names, names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    from paper_2106_03138_amd import _lib
+    assert sorted(_lib.SIGNATURES) == _declared_functions()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    from paper_2106_03138_amd import _lib
+    c = tmp_path / "sizes.c"
+    c.write_text(_struct_sizes())
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = [int(x) for x in out]
+    want = [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.Stats), ctypes.sizeof(_lib.Block),
+            _lib.Params.eps1_scale.offset, _lib.Params.profile.offset, _lib.Stats.total_ms.offset,
+            _lib.Block.fallback.offset, _lib.Block.umax.offset]
+    assert got == want
+
+
+def test_defaults_and_error_strings_without_a_device(lib):
+    from paper_2106_03138_amd import _lib
+    lib.qrdm_default_params.argtypes = [ctypes.POINTER(_lib.Params)]
+    p = _lib.Params()
+    lib.qrdm_default_params(ctypes.byref(p))
+    assert (p.tau, p.delta, p.kmax, p.stop_rule, p.precision) == (0.15, 0.9, 64, 0, 0)
+    lib.qrdm_strerror.restype = ctypes.c_char_p
+    lib.qrdm_strerror.argtypes = [ctypes.c_int]
+    for code in (0, 1, 2, 3, -1, 1001):
+        assert lib.qrdm_strerror(code)
+
+
+def test_invalid_arguments_are_rejected_before_any_launch(lib):
+    """Argument checks run on the host and return -i without touching the device."""
+    from paper_2106_03138_amd import _lib
+    f = lib.qrdm_factor_ex
+    f.restype, f.argtypes = _lib.SIGNATURES["qrdm_factor_ex"]
+    p = _lib.Params()
+    lib.qrdm_default_params(ctypes.byref(p))
+    rank = ctypes.c_int64(0)
+    nlog = ctypes.c_int64(0)
+    dummy = ctypes.c_void_p(16)
+    # m < 0
+    assert f(dummy, -1, 4, 4, ctypes.byref(p), dummy, dummy, ctypes.byref(rank), None, None, 0,
+             ctypes.byref(nlog), None) == -2
+    # lda < m
+    assert f(dummy, 8, 4, 4, ctypes.byref(p), dummy, dummy, ctypes.byref(rank), None, None, 0,
+             ctypes.byref(nlog), None) == -4
+    # kmax beyond the supported limit
+    p.kmax = 129
+    assert f(dummy, 8, 4, 8, ctypes.byref(p), dummy, dummy, ctypes.byref(rank), None, None, 0,
+             ctypes.byref(nlog), None) == -5
