@@ -164,6 +164,69 @@ void qrdm_release(void);
 /* Text for a return code (static storage). */
 const char *qrdm_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Batched QRDM: many independent small matrices, each factored exactly as
+ * qrdm_factor does (Algorithm 4 with Algorithm 1, FP64), by persistent
+ * kernels that hold one matrix per workgroup and take matrices from an atomic
+ * queue, longest first.  Matrices are grouped in size classes by m; each class
+ * runs its own launch variant (the autotuner's choice per class).
+ *
+ * Limits: 0 <= n <= QRDM_BATCH_NMAX, any m >= 0, lda >= max(1, m), and
+ * k_DM <= QRDM_BATCH_KMAX (larger per-matrix values are clamped to it).
+ * ------------------------------------------------------------------------ */
+#define QRDM_BATCH_NMAX 512
+#define QRDM_BATCH_KMAX 64
+#define QRDM_BATCH_CLASSES 4 /* size classes: m <= 64, <= 128, <= 256, > 256 */
+
+/* Per-matrix method parameters (device array, optional): tau, delta and k_DM
+ * as in qrdm_params; used by the learned parameter predictor. */
+typedef struct {
+    double tau;
+    double delta;
+    int32_t kmax;
+    int32_t pad;
+} qrdm_batch_params;
+
+/* Launch choice of one size class: variant 0 = 256 threads with 16 columns per
+ * wavefront in the trailing update, 1 = 256 threads with 32 columns, 2 = 512
+ * threads with 16 columns; wgs_per_cu = workgroups per compute unit (0 = the
+ * occupancy limit). */
+typedef struct {
+    int32_t variant;
+    int32_t wgs_per_cu;
+} qrdm_batch_tune;
+
+typedef struct qrdm_batch_plan qrdm_batch_plan;
+
+/* Plans a batch of `batch` matrices with HOST arrays m[batch], n[batch],
+ * lda[batch] and default parameters *p (tau, delta, kmax, stop_rule,
+ * eps1_scale; precision must be FP64).  tune[QRDM_BATCH_CLASSES] (host, may be
+ * NULL = built-in defaults).  Allocates the plan's device arrays (sizes, order,
+ * queue counters) on the current device.  Returns 0, -i for an invalid
+ * argument, QRDM_ERR_UNSUPPORTED if some n exceeds QRDM_BATCH_NMAX or
+ * p->kmax exceeds QRDM_BATCH_KMAX, or QRDM_ERR_HIP + error. */
+int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *lda, int32_t batch,
+                           const qrdm_params *p, const qrdm_batch_tune *tune, qrdm_batch_plan **plan);
+
+/* Factors every matrix of the plan in place.  A, tau_house, perm: DEVICE arrays
+ * of `batch` device pointers (matrix i is m[i] x n[i] with lda[i]; tau_house[i]
+ * holds min(m,n) entries, perm[i] n entries; same output layout as
+ * qrdm_factor).  rank, status: DEVICE arrays of `batch` entries; status 0 = ok,
+ * 1 = NaN/Inf in the matrix (nothing written, rank -1).  pm: DEVICE array of
+ * per-matrix parameters or NULL.  use_graph = 1 captures the launches in a
+ * hipGraph on the first call with these arguments (captured on a stream of
+ * the plan's own) and replays it on `stream` afterwards (the pointer arrays'
+ * contents may change between calls; new array addresses get a new capture,
+ * which happens automatically).
+ * Work is enqueued on `stream`; nothing is synchronized.  Calls with one plan
+ * must not overlap. */
+int qrdm_batch_factor(qrdm_batch_plan *plan, double *const *A, double *const *tau_house, int32_t *const *perm,
+                      int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int32_t use_graph,
+                      void *stream);
+
+/* Frees the plan, its device arrays and graphs (synchronizes the device). */
+void qrdm_batch_plan_destroy(qrdm_batch_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

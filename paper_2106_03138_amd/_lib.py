@@ -34,6 +34,18 @@ class Block(ctypes.Structure):
                 ("l", ctypes.c_int32), ("fallback", ctypes.c_int32), ("umax", ctypes.c_double)]
 
 
+class BatchParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("delta", ctypes.c_double), ("kmax", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class BatchTune(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32)]
+
+
+BATCH_NMAX, BATCH_KMAX, BATCH_CLASSES = 512, 64, 4
+
+
 class QrdmError(RuntimeError):
     def __init__(self, fn, code, msg):
         super().__init__(f"{fn} failed with code {code}: {msg}")
@@ -54,6 +66,10 @@ SIGNATURES = {
     "qrdm_dm_step": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _vp, _d, _d, _i32, _P(_i32), _P(_i32),
                                     _P(_d), _P(_i32), _P(_i32), _vp]),
     "qrdm_release": (None, []),
+    "qrdm_batch_plan_create": (ctypes.c_int, [_P(_i32), _P(_i32), _P(_i32), _i32, _P(Params), _P(BatchTune),
+                                              _P(_vp)]),
+    "qrdm_batch_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "qrdm_batch_plan_destroy": (None, [_vp]),
     "qrdm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

@@ -140,3 +140,117 @@ def dm_step(A, ns: int, vn1, tau: float, delta: float, kmax: int, stream=None):
     k = nL.value
     return (np.array(L[:k], dtype=np.int64), np.array(th[: k * k]).reshape(k, k),
             np.array(J[: ks.value], dtype=np.int64))
+
+
+# ---------------------------------------------------------------- batched
+def batch_size_class(m: int) -> int:
+    """Size class of a batched matrix (the classes of qrdm_batch_plan_create)."""
+    return 0 if m <= 64 else 1 if m <= 128 else 2 if m <= 256 else 3
+
+
+class Batch:
+    """Device storage for a batch of matrices: one packed float64 buffer (each
+    matrix column-major with lda = max(1, m)), packed tau_house and perm buffers,
+    rank and status arrays, and the device pointer arrays the C ABI takes."""
+
+    def __init__(self, shapes, device: str = "cuda"):
+        torch = _torch()
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.lda = [max(1, m) for m, _ in self.shapes]
+        sizes = [ld * n for ld, (_, n) in zip(self.lda, self.shapes)]
+        self.off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        psz = [min(m, n) for m, n in self.shapes]
+        self.toff = np.concatenate([[0], np.cumsum(psz)]).astype(np.int64)
+        self.poff = np.concatenate([[0], np.cumsum([n for _, n in self.shapes])]).astype(np.int64)
+        self.data = torch.zeros(max(int(self.off[-1]), 1), dtype=torch.float64, device=device)
+        self.tau = torch.zeros(max(int(self.toff[-1]), 1), dtype=torch.float64, device=device)
+        self.perm = torch.zeros(max(int(self.poff[-1]), 1), dtype=torch.int32, device=device)
+        b = len(self.shapes)
+        self.rank = torch.full((max(b, 1),), -2, dtype=torch.int64, device=device)
+        self.status = torch.full((max(b, 1),), -1, dtype=torch.int32, device=device)
+
+        def ptrs(t, offs, esize):
+            base = t.data_ptr()
+            return torch.tensor([base + esize * int(o) for o in offs[:-1]] or [0], dtype=torch.int64,
+                                device=device)
+        self.a_ptr = ptrs(self.data, self.off, 8)
+        self.t_ptr = ptrs(self.tau, self.toff, 8)
+        self.p_ptr = ptrs(self.perm, self.poff, 4)
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def load(self, mats):
+        """Copy host matrices (numpy, any order) into the device buffer."""
+        torch = _torch()
+        host = np.zeros(max(int(self.off[-1]), 1))
+        for i, a in enumerate(mats):
+            m, n = self.shapes[i]
+            a = np.asarray(a, dtype=np.float64)
+            assert a.shape == (m, n)
+            host[self.off[i]: self.off[i] + m * n] = a.reshape(-1, order="F")
+        self.data.copy_(torch.from_numpy(host))
+
+    def matrix(self, i):
+        m, n = self.shapes[i]
+        seg = self.data[int(self.off[i]): int(self.off[i]) + m * n].cpu().numpy()
+        return seg.reshape((m, n), order="F")
+
+    def tau_house(self, i):
+        return self.tau[int(self.toff[i]): int(self.toff[i + 1])].cpu().numpy()
+
+    def permutation(self, i):
+        return self.perm[int(self.poff[i]): int(self.poff[i + 1])].cpu().numpy().astype(np.int64)
+
+
+class BatchPlan:
+    """qrdm_batch_plan: size classes, longest-first order, launch variant per class."""
+
+    def __init__(self, batch: Batch, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
+                 stop_rule: int = _lib.STOP_PAPER, eps1_scale: float = 0.0, tune=None):
+        lib = _lib.load()
+        p = _params(tau, delta, kmax, stop_rule, _lib.PREC_FP64, 4, eps1_scale)
+        b = len(batch)
+        arr = lambda v: (ctypes.c_int32 * max(b, 1))(*v)  # noqa: E731
+        m = arr([s[0] for s in batch.shapes])
+        n = arr([s[1] for s in batch.shapes])
+        ld = arr(batch.lda)
+        tn = None
+        if tune is not None:
+            tn = (_lib.BatchTune * _lib.BATCH_CLASSES)(*[_lib.BatchTune(int(v), int(w)) for v, w in tune])
+        self._ptr = ctypes.c_void_p()
+        code = lib.qrdm_batch_plan_create(m, n, ld, b, ctypes.byref(p), tn, ctypes.byref(self._ptr))
+        _lib.check("qrdm_batch_plan_create", code)
+        self.batch = batch
+
+    def factor(self, params=None, use_graph: bool = False, stream=None):
+        """Factor every matrix of the batch in place (enqueued on the stream)."""
+        bt = self.batch
+        pm = ctypes.c_void_p(params.data_ptr()) if params is not None else None
+        code = _lib.load().qrdm_batch_factor(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                             ctypes.c_void_p(bt.t_ptr.data_ptr()),
+                                             ctypes.c_void_p(bt.p_ptr.data_ptr()),
+                                             ctypes.c_void_p(bt.rank.data_ptr()),
+                                             ctypes.c_void_p(bt.status.data_ptr()), pm, 1 if use_graph else 0,
+                                             _stream_ptr(stream))
+        _lib.check("qrdm_batch_factor", code)
+
+    def close(self):
+        if self._ptr:
+            _lib.load().qrdm_batch_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_params(tau, delta, kmax, device: str = "cuda"):
+    """Per-matrix (tau, delta, kmax) as the device array of qrdm_batch_params."""
+    torch = _torch()
+    b = len(tau)
+    raw = np.zeros(b, dtype=[("tau", "<f8"), ("delta", "<f8"), ("kmax", "<i4"), ("pad", "<i4")])
+    raw["tau"], raw["delta"], raw["kmax"] = tau, delta, kmax
+    return torch.from_numpy(raw.view(np.uint8).copy()).to(device)

@@ -31,6 +31,7 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(qrdm_params, eps1_scale), offsetof(qrdm_params, profile),
          offsetof(qrdm_stats, total_ms));
   printf("%zu %zu\n", offsetof(qrdm_block, fallback), offsetof(qrdm_block, umax));
+  printf("%zu %zu %zu\n", sizeof(qrdm_batch_params), offsetof(qrdm_batch_params, kmax), sizeof(qrdm_batch_tune));
   return 0;
 }
 """
@@ -72,7 +73,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     got = [int(x) for x in out]
     want = [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.Stats), ctypes.sizeof(_lib.Block),
             _lib.Params.eps1_scale.offset, _lib.Params.profile.offset, _lib.Stats.total_ms.offset,
-            _lib.Block.fallback.offset, _lib.Block.umax.offset]
+            _lib.Block.fallback.offset, _lib.Block.umax.offset,
+            ctypes.sizeof(_lib.BatchParams), _lib.BatchParams.kmax.offset, ctypes.sizeof(_lib.BatchTune)]
     assert got == want
 
 
@@ -108,3 +110,31 @@ def test_invalid_arguments_are_rejected_before_any_launch(lib):
     p.kmax = 129
     assert f(dummy, 8, 4, 8, ctypes.byref(p), dummy, dummy, ctypes.byref(rank), None, None, 0,
              ctypes.byref(nlog), None) == -5
+
+
+def test_batched_plan_rejects_bad_arguments_on_the_host(lib):
+    """Plan creation validates sizes and parameters before touching the device."""
+    from paper_2106_03138_amd import _lib
+    f = lib.qrdm_batch_plan_create
+    f.restype, f.argtypes = _lib.SIGNATURES["qrdm_batch_plan_create"]
+    p = _lib.Params()
+    lib.qrdm_default_params(ctypes.byref(p))
+    arr = lambda *v: (ctypes.c_int32 * len(v))(*v)  # noqa: E731
+    plan = ctypes.c_void_p()
+    # n beyond the batched limit
+    assert f(arr(600, 8), arr(600, 4), arr(600, 8), 2, ctypes.byref(p), None, ctypes.byref(plan)) == 3
+    # lda < m
+    assert f(arr(8), arr(4), arr(4), 1, ctypes.byref(p), None, ctypes.byref(plan)) == -3
+    # negative m, negative batch
+    assert f(arr(-1), arr(4), arr(4), 1, ctypes.byref(p), None, ctypes.byref(plan)) == -1
+    assert f(arr(8), arr(4), arr(8), -1, ctypes.byref(p), None, ctypes.byref(plan)) == -4
+    # k_DM beyond the batched limit; mixed precision is not offered for batches
+    p.kmax = 65
+    assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), None, ctypes.byref(plan)) == 3
+    p.kmax, p.precision = 64, 1
+    assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), None, ctypes.byref(plan)) == -5
+    # an unknown launch variant
+    p.precision = 0
+    tune = (_lib.BatchTune * 4)(*[_lib.BatchTune(7, 0)] * 4)
+    assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), tune, ctypes.byref(plan)) == -6
+    assert not plan.value

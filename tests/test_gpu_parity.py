@@ -13,10 +13,9 @@ import pytest
 import oracle
 from oracle import metrics as M
 from paper_2106_03138_amd import inputs as I
+from parity import EPS, ETA, compare as _compare
 
 pytestmark = pytest.mark.gpu
-EPS = np.finfo(np.float64).eps
-ETA = 1e-10
 
 
 def _gpu():
@@ -30,44 +29,6 @@ def _run_gpu(a, **kw):
     A = Q.device_matrix(a)
     out = Q.qrdm_factor(A, log=True, **kw)
     return Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out
-
-
-def _compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=True, full=False):
-    """full: the factorization ran to min(m, n) reflectors (stop rule NONE)."""
-    m, n = a.shape
-    k = ref.first_low_margin_block(ETA)
-    ns_cut = ref.blocks[k].ns if k < len(ref.blocks) else min(m, n)
-    real = [b for b in ref.blocks if b.l > 0]  # the oracle also logs the stopping step
-    # block sequence identical up to the first low-margin decision
-    if check_blocks:
-        for i in range(min(k, len(real))):
-            rb = real[i]
-            assert i < len(blocks), f"GPU log shorter than oracle at block {i}"
-            g = blocks[i]
-            assert (g[0], g[1], g[2], g[3]) == (rb.ns, rb.nL, rb.ks, rb.l), f"block {i}: gpu {g} oracle {(rb.ns, rb.nL, rb.ks, rb.l)}"
-    assert np.array_equal(perm[:ns_cut], ref.perm[:ns_cut])
-    if k == len(ref.blocks):
-        assert np.array_equal(perm, ref.perm)
-        assert rank == ref.rank
-    nref = min(m, n) if (full or rank >= min(m, n)) else rank
-    # backward error of the GPU factorization itself
-    assert M.residual(a, qr, tau, perm, nref) <= 1e-13
-    # R agrees normwise with the oracle's on the common prefix
-    na = np.linalg.norm(a, 2)
-    p = min(ns_cut, nref)
-    if p == 0:
-        return
-    # rows of R for the common prefix, columns aligned by original column index
-    rg = np.triu(qr[:p, :])[:, np.argsort(perm)]
-    ro = np.triu(ref.qr[:p, :])[:, np.argsort(ref.perm)]
-    dr = np.abs(rg - ro)
-    assert np.max(dr) <= tol_scale * n * EPS * na, np.max(dr)
-    # R diagonal: relative where large, absolute where small
-    d_g, d_o = np.abs(np.diag(qr)[:p]), np.abs(np.diag(ref.qr)[:p])
-    big = d_o >= 1e-3 * na
-    if np.any(big):
-        assert np.max(np.abs(d_g[big] - d_o[big]) / d_o[big]) <= 1e-12
-    assert np.max(np.abs(d_g - d_o)) <= tol_scale * n * EPS * na
 
 
 def test_colnorms():
