@@ -187,9 +187,11 @@ typedef struct {
     int32_t pad;
 } qrdm_batch_params;
 
-/* Launch choice of one size class: variant 0 = 256 threads with 16 columns per
- * wavefront in the trailing update, 1 = 256 threads with 32 columns, 2 = 512
- * threads with 16 columns; wgs_per_cu = workgroups per compute unit (0 = the
+/* Launch choice of one size class.  variant (256-thread workgroups): 0 = 16
+ * columns per wavefront in the trailing update, panel rows held in registers;
+ * 1 = the same with 32 columns; 2 = 16 columns, panel read from memory each
+ * step.  Every variant computes the same factorization (variant 2 sums in
+ * another order).  wgs_per_cu = workgroups per compute unit (0 = the
  * occupancy limit). */
 typedef struct {
     int32_t variant;

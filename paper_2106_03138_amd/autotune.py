@@ -6,9 +6,9 @@ choice as JSON per device.
     python -m paper_2106_03138_amd.autotune [--count 512] [--out PATH]
 
 The variants change only how the work is laid out (threads per workgroup,
-columns per wavefront in the trailing update, concurrency), never the
-factorization's decisions: variants 0 and 1 give bit-identical results and
-variant 2 differs by rounding only, so tuning cannot change what is computed.
+columns per wavefront in the trailing update, whether the panel rows sit in
+registers, concurrency), never the factorization's decisions: they differ in
+summation order only, so tuning cannot change what is computed beyond rounding.
 """
 from __future__ import annotations
 

@@ -29,6 +29,9 @@
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 #define QB_LD (QB_KM + 1)
+#ifndef QB_SW
+#define QB_SW 8  // columns of a register sub-panel
+#endif
 
 __device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -64,19 +67,22 @@ struct QbShared {
     double red[16];
     double rv[16];
     int rj[16];
+    double red16[16 * 16];
+    double prow[32], fin[32];  // pivot row and reduced sums of the register panel (two buffers)
     int L[QB_KM];
     int J[QB_KM];
     int swp[2 * QB_KM];
+    int swround[QB_KM];
     // scalars of the current step
     double umax, amax, eps_s, beta, tau_i, den;
     int64_t rank;
-    int ns, l, ks, nL, nsw, go, fb, idx, ncand;
+    int ns, l, ks, nL, nsw, nround, go, fb, idx, ncand;
 };
 
 // Gram G[i][j] = sum_r X_i[r] X_j[r] over r < t for i, j < nc, X given by col(r, i).
 // One 16x16 output tile per wavefront at a time, K in steps of 4 rows.
 template <int NT, class F>
-__device__ void qb_gram(const F &col, int nc, int t, double *G) {
+__device__ __forceinline__ void qb_gram(const F &col, int nc, int t, double *G) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nt = (nc + 15) >> 4;
@@ -113,7 +119,7 @@ __device__ void qb_gram(const F &col, int nc, int t, double *G) {
 // Trailing update of columns [c0, n) over rows [ns, m) with the l reflectors of
 // the block: A -= V (T^T (V^T A)).  Each wavefront owns WC column tiles of 16.
 template <int NT, int WC>
-__device__ void qb_trailing(double *A, int lda, int m, int n, int ns, int l, int c0, const double *G) {
+__device__ __forceinline__ void qb_trailing(double *A, int lda, int m, int n, int ns, int l, int c0, const double *G) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = lane & 15, kk = lane >> 4;
@@ -209,7 +215,244 @@ __device__ void qb_trailing(double *A, int lda, int m, int n, int ns, int l, int
     }
 }
 
-template <int NT, int WC>
+// T (forward, column-wise, Section 3.2) of the l reflectors stored in columns
+// [c0, c0 + l) from row c0 down, into the upper triangle of G: first V^T V on
+// MFMA into G, then T[a][i] = -tau_i sum_{b=a}^{i-1} T[a][b] (v_b^T v_i); row a
+// of T is private to thread a (v^T v is read from the lower triangle).
+template <int NT>
+__device__ __forceinline__ void qb_build_T(const double *A, int lda, int m, int c0, int l, const double *tau_h, double *G) {
+    const int tid = threadIdx.x;
+    if (l > 1) {
+        const double *Ab = A + c0;
+        auto vcol = [&](int r, int a) -> double {
+            if (r > a) return Ab[(int64_t)(c0 + a) * lda + r];
+            return r == a ? 1.0 : 0.0;
+        };
+        qb_gram<NT>(vcol, l, m - c0, G);
+        __syncthreads();
+        if (tid < l) {
+            const int a = tid;
+            G[a * QB_LD + a] = tau_h[c0 + a];
+            for (int i2 = a + 1; i2 < l; ++i2) {
+                double s = 0.0;
+                for (int b = a; b < i2; ++b) s += G[a * QB_LD + b] * G[i2 * QB_LD + b];
+                G[a * QB_LD + i2] = -tau_h[c0 + i2] * s;
+            }
+        }
+    } else if (l == 1 && tid == 0) {
+        G[0] = tau_h[c0];
+    }
+    __syncthreads();
+}
+
+// Sum of SW values (SW = 8 or 16) over the workgroup: a butterfly
+// reduce-scatter inside each wavefront (SW + 2 shuffles for 16, SW + 2 for 8),
+// then the wavefront partials in LDS.  fin[0..SW) holds the sums for every
+// thread on return.
+template <int NT, int SW>
+__device__ __forceinline__ void qb_reduce(const double (&v)[SW], double *red, double *fin) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double cur[SW];
+#pragma unroll
+    for (int k = 0; k < SW; ++k) cur[k] = v[k];
+    int idx = 0;
+    int width = SW;
+#pragma unroll
+    for (int o = 32; o >= 64 / SW; o >>= 1) {  // halve the values kept per lane
+        const bool hi = lane & o;
+        const int h = width >> 1;
+#pragma unroll
+        for (int k = 0; k < SW / 2; ++k) {
+            if (k < h) {
+                const double mine = hi ? cur[h + k] : cur[k], oth = hi ? cur[k] : cur[h + k];
+                cur[k] = mine + __shfl_xor(oth, o, 64);
+            }
+        }
+        idx = 2 * idx + (hi ? 1 : 0);
+        width = h;
+    }
+    double u1 = cur[0];
+#pragma unroll
+    for (int o = 32 / SW; o > 0; o >>= 1) u1 += __shfl_xor(u1, o, 64);
+    if ((lane & (64 / SW - 1)) == 0) red[w * SW + idx] = u1;
+    __syncthreads();
+    if (tid < SW) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) s += red[i * SW + tid];
+        fin[tid] = s;
+    }
+    __syncthreads();
+}
+
+// Householder panel with break (Algorithm 4, eq. lenght_check) for panel rows
+// [ns, m) held in registers, RPT rows per thread, in sub-panels of SW columns.
+// Each column takes one reduction of SW values (||x_below||^2 and x_below^T a_j
+// for the sub-panel's later columns); the pivot row is published in LDS.  After
+// a sub-panel its reflectors update the panel's later columns through a small
+// compact-WY product.  Returns l, the reflectors kept.
+template <int NT, int RPT, int SW>
+__device__ __forceinline__ int qb_panel_regs(double *A, int lda, int m, int ns, int ks, double eps_s, double *tau_h,
+                             QbShared &S) {
+    const int tid = threadIdx.x;
+    const int t = m - ns;
+    int l = ks;
+    for (int s0 = 0; s0 < ks; s0 += SW) {
+        const int nsub = ks - s0 < SW ? ks - s0 : SW;
+        double a[RPT][SW];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+#pragma unroll
+            for (int jj = 0; jj < SW; ++jj)
+                a[q][jj] = (r < t && jj < nsub) ? A[(int64_t)(ns + s0 + jj) * lda + ns + r] : 0.0;
+        }
+        int made = nsub;
+        bool brk = false;
+#pragma unroll
+        for (int ii = 0; ii < SW; ++ii) {
+            if (ii >= nsub || brk) continue;  // uniform; keeps the loop free of exits so it unrolls
+            const int pr = s0 + ii;  // pivot row (relative to ns) = panel column
+            double *prow = S.prow + (ii & 1) * 16;
+            double *fin = S.fin + (ii & 1) * 16;
+            double v[SW];
+#pragma unroll
+            for (int jj = 0; jj < SW; ++jj) v[jj] = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int r = tid + q * NT;
+                if (r > pr && r < t) {
+                    v[0] += a[q][ii] * a[q][ii];
+#pragma unroll
+                    for (int jj = ii + 1; jj < SW; ++jj) v[jj] += a[q][ii] * a[q][jj];
+                }
+                if (r == pr) {
+#pragma unroll
+                    for (int jj = 0; jj < SW; ++jj) prow[jj] = a[q][jj];
+                }
+            }
+            qb_reduce<NT, SW>(v, S.red16, fin);
+            const double sp = fin[0], alpha = prow[ii];
+            const double nrm = sqrt(alpha * alpha + sp);
+            if (pr >= 1 && nrm < eps_s) {  // nearly dependent column: end the block here
+                l = pr;
+                made = ii;
+                brk = true;
+                continue;
+            }
+            double beta, ti, den;
+            if (sp == 0.0) {
+                ti = 0.0;
+                beta = alpha;
+                den = 1.0;
+            } else {
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                ti = (beta - alpha) / beta;
+                den = alpha - beta;
+            }
+            double wj[SW];
+#pragma unroll
+            for (int jj = ii + 1; jj < SW; ++jj) wj[jj] = ti * (prow[jj] + fin[jj] / den);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int r = tid + q * NT;
+                if (r > pr && r < t) {
+                    const double vr = a[q][ii] / den;
+                    a[q][ii] = vr;
+#pragma unroll
+                    for (int jj = ii + 1; jj < SW; ++jj) a[q][jj] -= wj[jj] * vr;
+                } else if (r == pr) {
+                    a[q][ii] = beta;
+#pragma unroll
+                    for (int jj = ii + 1; jj < SW; ++jj) a[q][jj] -= wj[jj];
+                }
+            }
+            if (tid == 0) tau_h[ns + pr] = ti;
+        }
+        // write the sub-panel back (columns past a break are updated by the kept reflectors)
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int r = tid + q * NT;
+            if (r < t) {
+#pragma unroll
+                for (int jj = 0; jj < SW; ++jj)
+                    if (jj < nsub) A[(int64_t)(ns + s0 + jj) * lda + ns + r] = a[q][jj];
+            }
+        }
+        sync_global();
+        const int rest = s0 + nsub;
+        if (made > 0 && rest < ks) {
+            // the later panel columns take this sub-panel's reflectors
+            qb_build_T<NT>(A, lda, m, ns + s0, made, tau_h, S.G);
+            qb_trailing<NT, 1>(A, lda, m, ns + ks, ns + s0, made, ns + rest, S.G);
+            sync_global();
+        }
+        if (brk) break;
+    }
+    return l;
+}
+
+// The same panel for slabs taller than the registers hold: columns read from
+// global memory each step (a group of threads per later panel column).
+template <int NT>
+__device__ __forceinline__ int qb_panel_global(double *A, int lda, int m, int ns, int ks, double eps_s, double *tau_h,
+                               QbShared &S) {
+    const int tid = threadIdx.x;
+    int l = ks;
+    for (int i2 = 0; i2 < ks; ++i2) {
+        const int c = ns + i2;
+        double *xc = A + (int64_t)c * lda;
+        // alpha is read before the reduction's barriers: thread 0 overwrites it
+        // with beta further down
+        const double alpha = xc[c];
+        double part = 0.0;
+        for (int r = c + 1 + tid; r < m; r += NT) part += xc[r] * xc[r];
+        const double sp = block_sum<NT>(part, S.red);
+        const double nrm = sqrt(alpha * alpha + sp);
+        if (i2 >= 1 && nrm < eps_s) {
+            l = i2;
+            break;
+        }
+        double beta, ti, den;
+        if (sp == 0.0) {
+            ti = 0.0;
+            beta = alpha;
+            den = 1.0;
+        } else {
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            ti = (beta - alpha) / beta;
+            den = alpha - beta;
+        }
+        for (int r = c + 1 + tid; r < m; r += NT) xc[r] = xc[r] / den;
+        if (tid == 0) {
+            xc[c] = beta;
+            tau_h[c] = ti;
+        }
+        sync_global();
+        const int nj = ks - 1 - i2;
+        if (nj > 0) {
+            int g = 64;
+            while (g > 1 && g * nj > NT) g >>= 1;
+            const int gid = tid / g, lig = tid % g;
+            const bool act = gid < nj;
+            double d = 0.0;
+            double *yc = A + (int64_t)(c + 1 + (act ? gid : 0)) * lda;
+            if (act) {
+                for (int r = c + lig; r < m; r += g) d += (r == c ? 1.0 : xc[r]) * yc[r];
+            }
+            for (int o = g >> 1; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+            if (act) {
+                const double wj = ti * d;
+                for (int r = c + lig; r < m; r += g) yc[r] -= wj * (r == c ? 1.0 : xc[r]);
+            }
+        }
+        sync_global();
+    }
+    return l;
+}
+
+template <int NT, int WC, int PANEL>
 __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
     constexpr int NW = NT / 64;
     __shared__ QbShared S;
@@ -407,120 +650,80 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
             __syncthreads();
             const int ks = S.ks;
             // ------------------------------------------------- swap plan
+            // swap i brings accepted column J_i (tracked at its current
+            // position) to position ns + i; a swap runs one round after the
+            // latest earlier swap that touches one of its columns, so the swaps
+            // of one round are disjoint and run together
             if (wv == 0) {
                 int pos = lane < ks ? S.J[lane] : -1;  // current position of accepted column `lane`
-                int nsw = 0;
+                int nsw = 0, myd = -1, mys = -1, myr = 0;
                 for (int i2 = 0; i2 < ks; ++i2) {
                     const int qpos = __shfl(pos, i2, 64);
                     const int dst = ns + i2;
                     if (qpos != dst) {
-                        if (lane == 0) {
-                            S.swp[2 * nsw] = dst;
-                            S.swp[2 * nsw + 1] = qpos;
+                        int rr = 0;
+                        if (lane < nsw && (myd == dst || myd == qpos || mys == dst || mys == qpos)) rr = myr + 1;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) {
+                            const int orr = __shfl_xor(rr, o, 64);
+                            rr = orr > rr ? orr : rr;
+                        }
+                        if (lane == nsw) {
+                            myd = dst;
+                            mys = qpos;
+                            myr = rr;
                         }
                         ++nsw;
                         if (lane > i2 && pos == dst) pos = qpos;
                     }
                     if (lane == i2) pos = dst;
                 }
-                if (lane == 0) S.nsw = nsw;
+                int mr = lane < nsw ? myr : -1;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const int om = __shfl_xor(mr, o, 64);
+                    mr = om > mr ? om : mr;
+                }
+                if (lane < nsw) {
+                    S.swp[2 * lane] = myd;
+                    S.swp[2 * lane + 1] = mys;
+                    S.swround[lane] = myr;
+                }
+                if (lane == 0) {
+                    S.nsw = nsw;
+                    S.nround = mr + 1;
+                }
             }
             __syncthreads();
-            const int nsw = S.nsw;
-            for (int s2 = 0; s2 < nsw; ++s2) {
-                const int d = S.swp[2 * s2], sc = S.swp[2 * s2 + 1];
-                for (int r = tid; r < m; r += NT) {
-                    const double x = A[(int64_t)d * lda + r];
-                    A[(int64_t)d * lda + r] = A[(int64_t)sc * lda + r];
-                    A[(int64_t)sc * lda + r] = x;
+            {
+                const int nsw = S.nsw, nround = S.nround;
+                for (int rnd = 0; rnd < nround; ++rnd) {
+                    for (int s2 = 0; s2 < nsw; ++s2) {
+                        if (S.swround[s2] != rnd) continue;
+                        const int d = S.swp[2 * s2], sc = S.swp[2 * s2 + 1];
+                        for (int r = tid; r < m; r += NT) {
+                            const double x = A[(int64_t)d * lda + r];
+                            A[(int64_t)d * lda + r] = A[(int64_t)sc * lda + r];
+                            A[(int64_t)sc * lda + r] = x;
+                        }
+                        if (tid == 0) {
+                            double x = S.vn1[d]; S.vn1[d] = S.vn1[sc]; S.vn1[sc] = x;
+                            x = S.vn2[d]; S.vn2[d] = S.vn2[sc]; S.vn2[sc] = x;
+                            const int32_t pp = perm[d]; perm[d] = perm[sc]; perm[sc] = pp;
+                        }
+                    }
+                    sync_global();
                 }
-                if (tid == 0) {
-                    double x = S.vn1[d]; S.vn1[d] = S.vn1[sc]; S.vn1[sc] = x;
-                    x = S.vn2[d]; S.vn2[d] = S.vn2[sc]; S.vn2[sc] = x;
-                    const int32_t pp = perm[d]; perm[d] = perm[sc]; perm[sc] = pp;
-                }
-                sync_global();
             }
             // ------------------------------------------------- panel with break
             const double eps_s = S.eps_s;
-            int l = ks;
-            for (int i2 = 0; i2 < ks; ++i2) {
-                const int c = ns + i2;
-                double *xc = A + (int64_t)c * lda;
-                double part = 0.0;
-                for (int r = c + 1 + tid; r < m; r += NT) part += xc[r] * xc[r];
-                const double sp = block_sum<NT>(part, S.red);
-                const double alpha = xc[c];
-                const double nrm = sqrt(alpha * alpha + sp);
-                if (i2 >= 1 && nrm < eps_s) {  // nearly dependent column: end the block here
-                    l = i2;
-                    break;
-                }
-                double beta, ti, den;
-                if (sp == 0.0) {
-                    ti = 0.0;
-                    beta = alpha;
-                    den = 1.0;
-                } else {
-                    beta = (alpha >= 0.0) ? -nrm : nrm;
-                    ti = (beta - alpha) / beta;
-                    den = alpha - beta;
-                }
-                for (int r = c + 1 + tid; r < m; r += NT) xc[r] = xc[r] / den;
-                if (tid == 0) {
-                    xc[c] = beta;
-                    tau_h[c] = ti;
-                }
-                sync_global();
-                // dot and update of the remaining panel columns: a group of g
-                // threads per column, reduced with shuffles inside the group
-                const int nj = ks - 1 - i2;
-                if (nj > 0) {
-                    int g = 64;
-                    while (g > 1 && g * nj > NT) g >>= 1;
-                    const int gid = tid / g, lig = tid % g;
-                    const bool act = gid < nj;
-                    double d = 0.0;
-                    double *yc = A + (int64_t)(c + 1 + (act ? gid : 0)) * lda;
-                    if (act) {
-                        for (int r = c + lig; r < m; r += g) d += (r == c ? 1.0 : xc[r]) * yc[r];
-                    }
-                    for (int o = g >> 1; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-                    if (act) {
-                        const double wj = ti * d;
-                        for (int r = c + lig; r < m; r += g) yc[r] -= wj * (r == c ? 1.0 : xc[r]);
-                    }
-                }
-                sync_global();
-            }
-            if (tid == 0) S.l = l;
-            __syncthreads();
+            const int tpan = m - ns;
+            int l;
+            if (PANEL == 1 && tpan <= NT) l = qb_panel_regs<NT, 1, QB_SW>(A, lda, m, ns, ks, eps_s, tau_h, S);
+            else if (PANEL == 1 && tpan <= 2 * NT) l = qb_panel_regs<NT, 2, QB_SW>(A, lda, m, ns, ks, eps_s, tau_h, S);
+            else l = qb_panel_global<NT>(A, lda, m, ns, ks, eps_s, tau_h, S);
             // ------------------------------------------------- compact WY: T
-            if (l > 1) {
-                const double *Ab = A + ns;
-                const int t = m - ns;
-                auto vcol = [&](int r, int a) -> double {
-                    if (r > a) return Ab[(int64_t)(ns + a) * lda + r];
-                    return r == a ? 1.0 : 0.0;
-                };
-                qb_gram<NT>(vcol, l, t, S.G);  // V^T V (both triangles)
-                __syncthreads();
-                // T forward, column-wise: T[a][i] = -tau_i sum_{b=a}^{i-1} T[a][b] (v_b^T v_i);
-                // row a of T is private to thread a (upper triangle, v^T v read from the lower)
-                if (tid < l) {
-                    const int a = tid;
-                    S.G[a * QB_LD + a] = tau_h[ns + a];
-                    for (int i2 = a + 1; i2 < l; ++i2) {
-                        double s = 0.0;
-                        for (int b = a; b < i2; ++b) s += S.G[a * QB_LD + b] * S.G[i2 * QB_LD + b];
-                        S.G[a * QB_LD + i2] = -tau_h[ns + i2] * s;
-                    }
-                }
-                __syncthreads();
-            } else if (l == 1 && tid == 0) {
-                S.G[0] = tau_h[ns];
-            }
-            __syncthreads();
+            qb_build_T<NT>(A, lda, m, ns, l, tau_h, S.G);
             // ------------------------------------------------- trailing update
             if (l > 0 && ns + ks < n) qb_trailing<NT, WC>(A, lda, m, n, ns, l, ns + ks, S.G);
             sync_global();
@@ -562,27 +765,37 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
     }
 }
 
-int qb_variant_threads(int variant) { return variant == 2 ? 512 : 256; }
+// variant -> (threads, column tiles per wavefront in the trailing update, panel
+// kind).  512-thread workgroups are not offered: at that size the kernel has
+// half the registers per thread and spills.
+#define QB_VARIANT_LIST(X)  \
+    X(0, 256, 1, 1)         \
+    X(1, 256, 2, 1)         \
+    X(2, 256, 1, 0)
+
+int qb_variant_threads(int variant) {
+#define QB_NT(v, nt, wc, pn) if (variant == v) return nt;
+    QB_VARIANT_LIST(QB_NT)
+#undef QB_NT
+    return 0;
+}
 
 hipError_t launch_qrdm_batched(const QbArgs &q, int variant, int grid, hipStream_t s) {
     if (q.count <= 0 || grid <= 0) return hipSuccess;
-    switch (variant) {
-    case 0: hipLaunchKernelGGL((k_qrdm_batched<256, 1>), dim3(grid), dim3(256), 0, s, q); break;
-    case 1: hipLaunchKernelGGL((k_qrdm_batched<256, 2>), dim3(grid), dim3(256), 0, s, q); break;
-    case 2: hipLaunchKernelGGL((k_qrdm_batched<512, 1>), dim3(grid), dim3(512), 0, s, q); break;
-    default: return hipErrorInvalidValue;
+#define QB_LAUNCH(v, nt, wc, pn)                                                           \
+    if (variant == v) {                                                                    \
+        hipLaunchKernelGGL((k_qrdm_batched<nt, wc, pn>), dim3(grid), dim3(nt), 0, s, q); \
+        return hipGetLastError();                                                          \
     }
-    return hipGetLastError();
+    QB_VARIANT_LIST(QB_LAUNCH)
+#undef QB_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t qb_occupancy(int variant, int *wgs_per_cu) {
-    const void *f = nullptr;
-    int nt = qb_variant_threads(variant);
-    switch (variant) {
-    case 0: f = (const void *)k_qrdm_batched<256, 1>; break;
-    case 1: f = (const void *)k_qrdm_batched<256, 2>; break;
-    case 2: f = (const void *)k_qrdm_batched<512, 1>; break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, f, nt, 0);
+#define QB_OCC(v, nt, wc, pn) \
+    if (variant == v) return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, (const void *)k_qrdm_batched<nt, wc, pn>, nt, 0);
+    QB_VARIANT_LIST(QB_OCC)
+#undef QB_OCC
+    return hipErrorInvalidValue;
 }

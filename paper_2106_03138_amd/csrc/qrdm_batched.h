@@ -26,8 +26,9 @@ struct QbArgs {
     double eps1_scale;
 };
 
-// variant: 0 = 256 threads, 16 columns per wavefront in the trailing update;
-//          1 = 256 threads, 32 columns; 2 = 512 threads, 16 columns
+// variant: 0 = 256 threads, 16 columns per wavefront in the trailing update,
+//          panel rows in registers; 1 = 32 columns, registers; 2 = 16 columns,
+//          panel read from memory
 int qb_variant_threads(int variant);
 hipError_t launch_qrdm_batched(const QbArgs &q, int variant, int grid, hipStream_t s);
 hipError_t qb_occupancy(int variant, int *wgs_per_cu);

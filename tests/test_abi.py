@@ -135,6 +135,6 @@ def test_batched_plan_rejects_bad_arguments_on_the_host(lib):
     assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), None, ctypes.byref(plan)) == -5
     # an unknown launch variant
     p.precision = 0
-    tune = (_lib.BatchTune * 4)(*[_lib.BatchTune(7, 0)] * 4)
+    tune = (_lib.BatchTune * 4)(*[_lib.BatchTune(9, 0)] * 4)
     assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), tune, ctypes.byref(plan)) == -6
     assert not plan.value

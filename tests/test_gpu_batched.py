@@ -67,8 +67,12 @@ def _check_all(mats, b, tau, delta, kmax, stop_rule, per=None):
             assert np.array_equal(b.permutation(i), np.arange(n))
             assert not np.any(b.tau_house(i))
             continue
-        compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [], check_blocks=False,
-                full=(stop_rule == oracle.STOP_NONE))
+        try:
+            compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [], check_blocks=False,
+                    full=(stop_rule == oracle.STOP_NONE))
+        except AssertionError as e:
+            raise AssertionError(f"matrix {i} shape {a.shape} (tau {t}, delta {d}, kmax {k}, stop {stop_rule}): "
+                                 f"rank {rank[i]} vs oracle {ref.rank}; {e}") from e
 
 
 @pytest.mark.parametrize("stop_rule", [0, 1, 2])
@@ -87,8 +91,8 @@ def test_batched_other_parameters(tau, delta, kmax):
 
 def test_batched_variants():
     """Variants 0 and 1 differ only in how many column tiles a wavefront takes
-    in the trailing update, so they agree bit for bit; variant 2 (512 threads)
-    reduces in another order and is held to the oracle."""
+    in the trailing update, so they agree bit for bit; variant 2 (the panel read
+    from memory) reduces in another order and is held to the oracle."""
     mats = _small_batch(seed=7, count=16)
     outs = []
     for v in range(3):
@@ -96,7 +100,11 @@ def test_batched_variants():
         outs.append(b)
     assert np.array_equal(outs[0].data.cpu().numpy(), outs[1].data.cpu().numpy())
     assert np.array_equal(outs[0].perm.cpu().numpy(), outs[1].perm.cpu().numpy())
-    _check_all(mats, outs[2], 0.15, 0.9, 64, 0)
+    for v in (2,):
+        try:
+            _check_all(mats, outs[v], 0.15, 0.9, 64, 0)
+        except AssertionError as e:
+            raise AssertionError(f"variant {v}: {e}") from e
 
 
 def test_batched_graph_replay():
