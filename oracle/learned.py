@@ -163,7 +163,10 @@ def ice_sigma_min(r: np.ndarray) -> float:
     [v; gamma], x_{k+1} = [s x_k; c] with s^2 + c^2 = 1 gives
     ||x_{k+1}^T R_{k+1}||^2 = s^2 ||y_k||^2 + (s alpha + c gamma)^2, alpha = x_k^T v;
     (s, c) is the unit eigenvector of the smallest eigenvalue of
-    [[||y||^2 + alpha^2, alpha gamma], [alpha gamma, gamma^2]]."""
+    M = [[p, q], [q, r]] = [[||y||^2 + alpha^2, alpha gamma], [alpha gamma, gamma^2]].
+    det M = ||y||^2 gamma^2 exactly, so lambda_min = det M / lambda_max is formed
+    without cancellation (lambda_max = (p + r)/2 + sqrt(((p - r)/2)^2 + q^2));
+    the eigenvector is the larger of (-q, p - lambda_min) and (r - lambda_min, -q)."""
     r = np.asarray(r, dtype=np.float64)
     k = r.shape[0]
     if k == 0:
@@ -173,9 +176,16 @@ def ice_sigma_min(r: np.ndarray) -> float:
     for j in range(1, k):
         v, gamma = r[:j, j], r[j, j]
         alpha = float(x @ v)
-        m2 = np.array([[est * est + alpha * alpha, alpha * gamma], [alpha * gamma, gamma * gamma]])
-        w, vec = np.linalg.eigh(m2)
-        s, c = vec[0, 0], vec[1, 0]
+        p = est * est + alpha * alpha
+        q = alpha * gamma
+        rr = gamma * gamma
+        lmax = 0.5 * (p + rr) + np.hypot(0.5 * (p - rr), q)
+        lmin = (est * est) * rr / lmax if lmax > 0 else 0.0
+        v1 = np.array([-q, p - lmin])
+        v2 = np.array([rr - lmin, -q])
+        vec = v1 if np.hypot(*v1) >= np.hypot(*v2) else v2
+        nv = np.hypot(*vec)
+        s, c = (vec / nv) if nv > 0 else (1.0, 0.0)
         x = np.concatenate([s * x, [c]])
-        est = float(np.sqrt(max(w[0], 0.0)))
+        est = float(np.sqrt(lmin))
     return est
