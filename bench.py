@@ -165,6 +165,7 @@ def batched_leg(args, torch, Q):
         d = np.sort(np.abs(np.diag(seg)[:nr]))[::-1]
         worst = min(worst, float(np.min(d / sig[:nr])))
     plan.close()
+    learned = learned_leg(args, torch, Q, b, pristine, shapes, ms) if args.learned else None
     return {"metric": "batched QRDM matrices/s", "matrices": len(shapes), "ms": round(ms, 3),
             "matrices_per_s": round(len(shapes) / (ms * 1e-3), 1),
             "tflops": round(flop / (ms * 1e-3) / 1e12, 4), "flop": flop,
@@ -173,7 +174,78 @@ def batched_leg(args, torch, Q):
                          "frac": round(flop / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 5)},
             "tune": [list(t) for t in tune], "launch": "hipGraph replay",
             "quality": {"rank_equals_numerical_rank": exact, "max_rank_over": over,
-                        "min_d_over_sigma": round(worst, 4)}}
+                        "min_d_over_sigma": round(worst, 4)},
+            "learned": learned}
+
+
+def quality_of(b, shapes):
+    """Rank against the numerical rank fixed by construction, and the factor-10
+    band d_i / sigma_i on the first n_r diagonal entries (host, from R)."""
+    rank = b.rank.cpu().numpy()
+    host = b.data.cpu().numpy()
+    exact, over, worst, below = 0, 0, np.inf, 0
+    for i, (m, n, r) in enumerate(shapes):
+        sig = np.logspace(0.0, -14.0, r) if r > 1 else np.ones(1)
+        nr = int(np.sum(sig > np.finfo(np.float64).eps * n * sig[0]))
+        exact += int(rank[i] == nr)
+        over = max(over, int(rank[i]) - nr)
+        seg = host[int(b.off[i]): int(b.off[i]) + m * n].reshape((m, n), order="F")
+        d = np.sort(np.abs(np.diag(seg)[:nr]))[::-1]
+        w = float(np.min(d / sig[:nr]))
+        worst = min(worst, w)
+        below += int(w < 0.1)
+    return {"rank_equals_numerical_rank": exact, "max_rank_over": over, "min_d_over_sigma": round(worst, 4),
+            "matrices_below_factor_10": below}
+
+
+def learned_leg(args, torch, Q, b, pristine, shapes, default_ms):
+    """Per-matrix (tau, delta, k_DM) from the trained MLP: features, forward pass,
+    grid snap, factorization, online condition check and default re-runs of the
+    matrices that fail it, all timed together; compared with the default
+    parameters' graph replay on the same batch."""
+    from paper_2106_03138_amd import learned as Ld
+    model = Ld.Model.load()
+    if model is None:
+        return None
+    plan = Q.BatchPlan(b, tune=autotune_load())
+    # the default parameters, eager and timed the same way (wall clock with a sync)
+    eager = []
+    for _ in range(args.batched_reps):
+        b.data.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.factor()
+        torch.cuda.synchronize()
+        eager.append(1e3 * (time.perf_counter() - t0))
+    eager_ms = float(np.median(eager))
+    b.data.copy_(pristine)
+    Ld.predict_factor(b, plan, model, pristine)  # warm up
+    times, nfb = [], 0
+    for _ in range(args.batched_reps):
+        b.data.copy_(pristine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, nfb = Ld.predict_factor(b, plan, model, pristine)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0))
+    ms = float(np.median(times))
+    pm = Ld.predict_params(plan, model).cpu().numpy().view(
+        np.dtype([("tau", "<f8"), ("delta", "<f8"), ("kmax", "<i4"), ("pad", "<i4")]))
+    import collections
+    common = collections.Counter(zip(pm["tau"].round(3), pm["delta"].round(3), pm["kmax"])).most_common(3)
+    qual = quality_of(b, shapes)
+    plan.close()
+    return {"ms": round(ms, 3), "default_eager_ms": round(eager_ms, 3),
+            "gain_vs_default": round(eager_ms / ms, 4), "gain_vs_default_graph": round(default_ms / ms, 4),
+            "fallbacks": nfb,
+            "matrices_per_s": round(len(shapes) / (ms * 1e-3), 1), "quality": qual,
+            "most_common_params": [[float(t), float(d), int(k), c] for (t, d, k), c in common],
+            "timing": "wall clock around features + MLP + factorization + check + fallback (eager)"}
+
+
+def autotune_load():
+    from paper_2106_03138_amd import autotune
+    return autotune.load()
 
 
 def main():
@@ -194,6 +266,7 @@ def main():
     ap.add_argument("--no-profile-run", action="store_true")
     ap.add_argument("--batched-count", type=int, default=2048, help="0 skips the batched leg")
     ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--learned", type=int, default=1, help="1 = also time the learned-parameter path")
     ap.add_argument("--input-cache", default="",
                     help=".npy file holding the input: loaded if present, else written after generation")
     ap.add_argument("--seed", type=int, default=0)

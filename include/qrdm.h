@@ -215,7 +215,10 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
  * holds min(m,n) entries, perm[i] n entries; same output layout as
  * qrdm_factor).  rank, status: DEVICE arrays of `batch` entries; status 0 = ok,
  * 1 = NaN/Inf in the matrix (nothing written, rank -1).  pm: DEVICE array of
- * per-matrix parameters or NULL.  use_graph = 1 captures the launches in a
+ * per-matrix parameters or NULL.  info: DEVICE array of 4 * batch entries or
+ * NULL; per matrix: outer steps, steps whose panel stopped early (the length
+ * check of eq. lenght_check), scalar-pivoting steps, and GPU wall-clock ticks
+ * (100 MHz) the workgroup spent on it.  use_graph = 1 captures the launches in a
  * hipGraph on the first call with these arguments (captured on a stream of
  * the plan's own) and replays it on `stream` afterwards (the pointer arrays'
  * contents may change between calls; new array addresses get a new capture,
@@ -223,11 +226,68 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
  * Work is enqueued on `stream`; nothing is synchronized.  Calls with one plan
  * must not overlap. */
 int qrdm_batch_factor(qrdm_batch_plan *plan, double *const *A, double *const *tau_house, int32_t *const *perm,
-                      int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int32_t use_graph,
-                      void *stream);
+                      int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info,
+                      int32_t use_graph, void *stream);
 
 /* Frees the plan, its device arrays and graphs (synchronizes the device). */
 void qrdm_batch_plan_destroy(qrdm_batch_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Learned (tau, delta, k_DM) per matrix.  The paper chooses the parameters by
+ * a grid study and checks quality with the factor-10 rule on d_i / sigma_i
+ * (Section 5); here a multilayer perceptron 16 -> 64 -> 64 -> 3 (tanh, tanh,
+ * linear; FP32; 5443 parameters in the order W1[64][16], b1, W2[64][64], b2,
+ * W3[3][64], b3) maps per-matrix features to the grid
+ * tau in {0.05, 0.15, 0.3, 0.5, 0.7, 0.9}, delta in {0.5, 0.7, 0.9, 0.95},
+ * k_DM in {32, 64}, and an incremental condition estimate of R11 decides
+ * whether each prediction is kept.  All arrays are DEVICE arrays; work is
+ * enqueued on `stream` and nothing is synchronized.
+ * ------------------------------------------------------------------------ */
+#define QRDM_NFEAT 16
+#define QRDM_MLP_HIDDEN 64
+#define QRDM_MLP_OUT 3
+#define QRDM_MLP_NPARAM 5443
+#define QRDM_MLP_NDELTA 131 /* per-sample work of the gradient: 3 + 2 * 64 */
+
+/* features[16 * batch] (FP64) of the plan's matrices: [0..9) the order
+ * statistics floor(q (n-1)), q = 0.1..0.9, of log10(||a_j|| / max ||a_j||)
+ * (floored at -30); [9] log2 m; [10] log2 n; [11] n / m; over the columns
+ * floor(k n / s), k < s = min(64, n), with theta_ij = G_ij / sqrt(G_ii G_jj)
+ * (Algorithm 1's cosine; 0 if a column is zero): [12] mean |theta_ij|,
+ * [13] the order statistic floor(0.95 (P-1)) of the P = s(s-1)/2 values,
+ * [14] max, [15] fraction above 0.5.  A matrix that is empty or zero keeps
+ * zeros except [9..12). */
+int qrdm_batch_features(qrdm_batch_plan *plan, double *const *A, double *features, void *stream);
+
+/* Forward pass for `batch` samples: x = (features - norm[0..16)) * norm[16..32)
+ * (norm may be NULL: x = features); h1, h2 [batch * 64] (may be NULL when
+ * only y is wanted), y [batch * 3]. */
+int qrdm_mlp_forward(const float *params, const float *norm, const double *features, int32_t batch, float *h1,
+                     float *h2, float *y, void *stream);
+
+/* Gradient of L = 1/(2 batch) sum_b sum_o (y_bo - target_bo)^2 with respect
+ * to params, after qrdm_mlp_forward filled h1, h2, y: grad[5443];
+ * work[131 * batch] scratch; sqerr[batch] (may be NULL) the per-sample
+ * squared errors.  Each gradient entry is a fixed-order sum over samples. */
+int qrdm_mlp_gradient(const float *params, const float *norm, const double *features, const float *h1,
+                      const float *h2, const float *y, const float *target, int32_t batch, float *work, float *grad,
+                      float *sqerr, void *stream);
+
+/* Adam step t >= 1 (Kingma & Ba) on params with moments m, v (5443 each). */
+int qrdm_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream);
+
+/* MLP outputs y[3 * batch] -> per-matrix parameters: tau and delta are the
+ * nearest grid values to y0 and y1, k_DM = 64 if y2 >= 0.5 else 32. */
+int qrdm_mlp_to_params(const float *y, int32_t batch, qrdm_batch_params *out, void *stream);
+
+/* Online quality check after a factorization of the plan's matrices: with
+ * r = rank[i], an incremental condition estimate (Bischof) est of
+ * sigma_min(R11) (R11 = leading r x r of R); ok[i] = 1 iff
+ * est >= band * min_{j<r} |r_jj| (band = 0.1 for the factor-10 rule).
+ * est may be NULL. */
+int qrdm_batch_check(qrdm_batch_plan *plan, double *const *A, const int64_t *rank, double band, double *est,
+                     int32_t *ok, void *stream);
 
 #ifdef __cplusplus
 }

@@ -44,6 +44,7 @@ class BatchTune(ctypes.Structure):
 
 
 BATCH_NMAX, BATCH_KMAX, BATCH_CLASSES = 512, 64, 4
+NFEAT, MLP_HIDDEN, MLP_OUT, MLP_NPARAM, MLP_NDELTA = 16, 64, 3, 5443, 131
 
 
 class QrdmError(RuntimeError):
@@ -68,7 +69,14 @@ SIGNATURES = {
     "qrdm_release": (None, []),
     "qrdm_batch_plan_create": (ctypes.c_int, [_P(_i32), _P(_i32), _P(_i32), _i32, _P(Params), _P(BatchTune),
                                               _P(_vp)]),
-    "qrdm_batch_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "qrdm_batch_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "qrdm_batch_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "qrdm_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "qrdm_mlp_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "qrdm_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, _vp]),
+    "qrdm_mlp_to_params": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "qrdm_batch_check": (ctypes.c_int, [_vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "qrdm_batch_plan_destroy": (None, [_vp]),
     "qrdm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }

@@ -199,8 +199,32 @@ class Batch:
     def tau_house(self, i):
         return self.tau[int(self.toff[i]): int(self.toff[i + 1])].cpu().numpy()
 
+    def subset(self, idx):
+        """A batch over some of these matrices, sharing their storage (the
+        device pointer arrays are gathered; rank and status are new)."""
+        torch = _torch()
+        return _SubBatch(self, [int(i) for i in idx])
+
     def permutation(self, i):
         return self.perm[int(self.poff[i]): int(self.poff[i + 1])].cpu().numpy().astype(np.int64)
+
+
+class _SubBatch:
+    def __init__(self, parent, idx):
+        torch = _torch()
+        dev = parent.data.device
+        self.shapes = [parent.shapes[i] for i in idx]
+        self.lda = [parent.lda[i] for i in idx]
+        sel = torch.as_tensor(idx or [0], dtype=torch.int64, device=dev)
+        self.a_ptr = parent.a_ptr[sel].contiguous()
+        self.t_ptr = parent.t_ptr[sel].contiguous()
+        self.p_ptr = parent.p_ptr[sel].contiguous()
+        self.rank = torch.full((max(len(idx), 1),), -2, dtype=torch.int64, device=dev)
+        self.status = torch.full((max(len(idx), 1),), -1, dtype=torch.int32, device=dev)
+        self.data = parent.data
+
+    def __len__(self):
+        return len(self.shapes)
 
 
 class BatchPlan:
@@ -223,17 +247,45 @@ class BatchPlan:
         _lib.check("qrdm_batch_plan_create", code)
         self.batch = batch
 
-    def factor(self, params=None, use_graph: bool = False, stream=None):
-        """Factor every matrix of the batch in place (enqueued on the stream)."""
+    def factor(self, params=None, use_graph: bool = False, stream=None, info=None):
+        """Factor every matrix of the batch in place (enqueued on the stream).
+        info: optional int64 device tensor of 4 * batch entries (outer steps,
+        early-stopped panels, scalar-pivoting steps, clock ticks per matrix)."""
         bt = self.batch
         pm = ctypes.c_void_p(params.data_ptr()) if params is not None else None
+        inf = ctypes.c_void_p(info.data_ptr()) if info is not None else None
         code = _lib.load().qrdm_batch_factor(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
                                              ctypes.c_void_p(bt.t_ptr.data_ptr()),
                                              ctypes.c_void_p(bt.p_ptr.data_ptr()),
                                              ctypes.c_void_p(bt.rank.data_ptr()),
-                                             ctypes.c_void_p(bt.status.data_ptr()), pm, 1 if use_graph else 0,
+                                             ctypes.c_void_p(bt.status.data_ptr()), pm, inf, 1 if use_graph else 0,
                                              _stream_ptr(stream))
         _lib.check("qrdm_batch_factor", code)
+
+    def features(self, out=None, stream=None):
+        """Per-matrix features (float64 device tensor [batch, 16])."""
+        torch = _torch()
+        bt = self.batch
+        if out is None:
+            out = torch.zeros((max(len(bt), 1), _lib.NFEAT), dtype=torch.float64, device=bt.data.device)
+        code = _lib.load().qrdm_batch_features(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        _lib.check("qrdm_batch_features", code)
+        return out[: len(bt)]
+
+    def check(self, band: float = 0.1, stream=None):
+        """Online quality check of the current factorization: (ok int32, est float64)."""
+        torch = _torch()
+        bt = self.batch
+        dev = bt.data.device
+        ok = torch.zeros(max(len(bt), 1), dtype=torch.int32, device=dev)
+        est = torch.zeros(max(len(bt), 1), dtype=torch.float64, device=dev)
+        code = _lib.load().qrdm_batch_check(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                            ctypes.c_void_p(bt.rank.data_ptr()), float(band),
+                                            ctypes.c_void_p(est.data_ptr()), ctypes.c_void_p(ok.data_ptr()),
+                                            _stream_ptr(stream))
+        _lib.check("qrdm_batch_check", code)
+        return ok[: len(bt)], est[: len(bt)]
 
     def close(self):
         if self._ptr:
@@ -254,3 +306,57 @@ def batch_params(tau, delta, kmax, device: str = "cuda"):
     raw = np.zeros(b, dtype=[("tau", "<f8"), ("delta", "<f8"), ("kmax", "<i4"), ("pad", "<i4")])
     raw["tau"], raw["delta"], raw["kmax"] = tau, delta, kmax
     return torch.from_numpy(raw.view(np.uint8).copy()).to(device)
+
+
+# ---------------------------------------------------------------- MLP
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def mlp_forward(params, features, norm=None, h1=None, h2=None, stream=None):
+    """y [B, 3] (float32 device) for features [B, 16] (float64 device)."""
+    torch = _torch()
+    b = features.shape[0]
+    dev = features.device
+    y = torch.empty((max(b, 1), _lib.MLP_OUT), dtype=torch.float32, device=dev)
+    code = _lib.load().qrdm_mlp_forward(_vp(params), _vp(norm), _vp(features.contiguous()), b, _vp(h1), _vp(h2),
+                                        _vp(y), _stream_ptr(stream))
+    _lib.check("qrdm_mlp_forward", code)
+    return y[:b]
+
+
+def mlp_gradient(params, features, target, norm=None, stream=None):
+    """(grad [5443], y [B, 3], sqerr [B]) of the squared loss, all float32 device."""
+    torch = _torch()
+    b = features.shape[0]
+    dev = features.device
+    feats = features.contiguous()
+    h1 = torch.empty((b, _lib.MLP_HIDDEN), dtype=torch.float32, device=dev)
+    h2 = torch.empty_like(h1)
+    y = torch.empty((b, _lib.MLP_OUT), dtype=torch.float32, device=dev)
+    lib = _lib.load()
+    code = lib.qrdm_mlp_forward(_vp(params), _vp(norm), _vp(feats), b, _vp(h1), _vp(h2), _vp(y), _stream_ptr(stream))
+    _lib.check("qrdm_mlp_forward", code)
+    work = torch.empty(b * _lib.MLP_NDELTA, dtype=torch.float32, device=dev)
+    grad = torch.empty(_lib.MLP_NPARAM, dtype=torch.float32, device=dev)
+    sq = torch.empty(b, dtype=torch.float32, device=dev)
+    code = lib.qrdm_mlp_gradient(_vp(params), _vp(norm), _vp(feats), _vp(h1), _vp(h2), _vp(y),
+                                 _vp(target.contiguous()), b, _vp(work), _vp(grad), _vp(sq), _stream_ptr(stream))
+    _lib.check("qrdm_mlp_gradient", code)
+    return grad, y, sq
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    code = _lib.load().qrdm_mlp_adam(_vp(params), _vp(grad), _vp(m), _vp(v), int(t), float(lr), float(beta1),
+                                     float(beta2), float(eps), _stream_ptr(stream))
+    _lib.check("qrdm_mlp_adam", code)
+
+
+def mlp_to_params(y, stream=None):
+    """MLP outputs [B, 3] -> device array of qrdm_batch_params (24 bytes each)."""
+    torch = _torch()
+    b = y.shape[0]
+    out = torch.zeros(max(b, 1) * 24, dtype=torch.uint8, device=y.device)
+    code = _lib.load().qrdm_mlp_to_params(_vp(y.contiguous()), b, _vp(out), _stream_ptr(stream))
+    _lib.check("qrdm_mlp_to_params", code)
+    return out

@@ -76,7 +76,8 @@ struct QbShared {
     // scalars of the current step
     double umax, amax, eps_s, beta, tau_i, den;
     int64_t rank;
-    int ns, l, ks, nL, nsw, nround, go, fb, idx, ncand;
+    int ns, l, ks, nL, nsw, nround, go, fb, idx, ncand, nstep, nbreak, nfb;
+    int64_t t0;
 };
 
 // Gram G[i][j] = sum_r X_i[r] X_j[r] over r < t for i, j < nc, X given by col(r, i).
@@ -531,6 +532,10 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
             if (tid == 0) {
                 q.rank[mi] = -1;
                 q.status[mi] = 1;
+                if (q.info) {
+                    int64_t *inf = q.info + 4 * (int64_t)mi;
+                    inf[0] = inf[1] = inf[2] = inf[3] = 0;
+                }
             }
             __syncthreads();
             continue;
@@ -541,6 +546,8 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
             S.ns = 0;
             S.rank = -1;
             S.fb = 0;
+            S.nstep = S.nbreak = S.nfb = 0;
+            S.t0 = wall_clock64();
         }
         sync_global();
         const double amax = S.amax;
@@ -746,12 +753,24 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
                     S.vn1[j] = v1 * sqrt(qq);
                 }
             }
-            if (tid == 0) S.ns = ns + l;
+            if (tid == 0) {
+                S.ns = ns + l;
+                S.nstep += 1;
+                S.nbreak += l < ks ? 1 : 0;
+                S.nfb += S.fb;
+            }
             __syncthreads();
         }
         if (tid == 0) {
             q.rank[mi] = S.rank >= 0 ? S.rank : (amax > 0.0 ? S.ns : 0);
             q.status[mi] = 0;
+            if (q.info) {
+                int64_t *inf = q.info + 4 * (int64_t)mi;
+                inf[0] = S.nstep;
+                inf[1] = S.nbreak;
+                inf[2] = S.nfb;
+                inf[3] = wall_clock64() - S.t0;
+            }
         }
         sync_global();
     }

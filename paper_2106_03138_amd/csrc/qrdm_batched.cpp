@@ -23,7 +23,8 @@ struct qrdm_batch_plan {
     int32_t *d_m = nullptr, *d_n = nullptr, *d_lda = nullptr, *d_order = nullptr;
     uint32_t *d_counters = nullptr;  // 2 per class
     hipStream_t cap_stream = nullptr;  // captures run here (the legacy default stream cannot be captured)
-    std::map<std::tuple<const void *, const void *, const void *, const void *, const void *, const void *>,
+    std::map<std::tuple<const void *, const void *, const void *, const void *, const void *, const void *,
+                        const void *>,
              hipGraphExec_t>
         graphs;
 };
@@ -48,7 +49,7 @@ double flops(int64_t m, int64_t n) {
 const qrdm_batch_tune kDefaultTune[QRDM_BATCH_CLASSES] = {{0, 0}, {0, 0}, {1, 0}, {1, 0}};
 
 hipError_t enqueue(qrdm_batch_plan *pl, double *const *A, double *const *tau_house, int32_t *const *perm,
-                   int64_t *rank, int32_t *status, const qrdm_batch_params *pm, hipStream_t s) {
+                   int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info, hipStream_t s) {
     for (int c = 0; c < QRDM_BATCH_CLASSES; ++c) {
         if (pl->count[c] == 0) continue;
         QbArgs q;
@@ -61,6 +62,7 @@ hipError_t enqueue(qrdm_batch_plan *pl, double *const *A, double *const *tau_hou
         q.rank = rank;
         q.status = status;
         q.pm = pm;
+        q.info = info;
         q.order = pl->d_order + pl->offset[c];
         q.count = pl->count[c];
         q.counters = pl->d_counters + 2 * c;
@@ -153,11 +155,11 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
 }
 
 int qrdm_batch_factor(qrdm_batch_plan *pl, double *const *A, double *const *tau_house, int32_t *const *perm,
-                      int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int32_t use_graph,
+                      int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info, int32_t use_graph,
                       void *stream) {
     if (!pl) return -1;
     if (pl->batch > 0 && (!A || !tau_house || !perm || !rank || !status)) return -2;
-    if (use_graph < 0 || use_graph > 1) return -8;
+    if (use_graph < 0 || use_graph > 1) return -9;
     if (pl->batch == 0) return QRDM_OK;
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -165,11 +167,11 @@ int qrdm_batch_factor(qrdm_batch_plan *pl, double *const *A, double *const *tau_
     if (dev != pl->device) return -1;
     hipStream_t s = (hipStream_t)stream;
     if (!use_graph) {
-        e = enqueue(pl, A, tau_house, perm, rank, status, pm, s);
+        e = enqueue(pl, A, tau_house, perm, rank, status, pm, info, s);
         return e == hipSuccess ? QRDM_OK : QRDM_ERR_HIP + (int)e;
     }
     auto key = std::make_tuple((const void *)A, (const void *)tau_house, (const void *)perm, (const void *)rank,
-                               (const void *)status, (const void *)pm);
+                               (const void *)status, (const void *)pm, (const void *)info);
     auto it = pl->graphs.find(key);
     if (it == pl->graphs.end()) {
         if (!pl->cap_stream) {
@@ -180,7 +182,7 @@ int qrdm_batch_factor(qrdm_batch_plan *pl, double *const *A, double *const *tau_
         hipGraphExec_t ge = nullptr;
         e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return QRDM_ERR_HIP + (int)e;
-        hipError_t el = enqueue(pl, A, tau_house, perm, rank, status, pm, pl->cap_stream);
+        hipError_t el = enqueue(pl, A, tau_house, perm, rank, status, pm, info, pl->cap_stream);
         e = hipStreamEndCapture(pl->cap_stream, &g);
         if (el != hipSuccess) e = el;
         if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
@@ -190,6 +192,17 @@ int qrdm_batch_factor(qrdm_batch_plan *pl, double *const *A, double *const *tau_
     }
     e = hipGraphLaunch(it->second, s);
     return e == hipSuccess ? QRDM_OK : QRDM_ERR_HIP + (int)e;
+}
+
+int qb_plan_sizes(const qrdm_batch_plan *pl, int32_t *batch, const int32_t **m, const int32_t **n,
+                  const int32_t **lda, int *device) {
+    if (!pl) return -1;
+    *batch = pl->batch;
+    *m = pl->d_m;
+    *n = pl->d_n;
+    *lda = pl->d_lda;
+    *device = pl->device;
+    return 0;
 }
 
 void qrdm_batch_plan_destroy(qrdm_batch_plan *pl) {

@@ -17,6 +17,7 @@ struct QbArgs {
     int32_t *const *perm;
     int64_t *rank;
     int32_t *status;
+    int64_t *info;  // [4 per matrix]: outer steps, panel breaks, scalar-pivoting steps, clock ticks; or null
     const qrdm_batch_params *pm;  // per-matrix (tau, delta, kmax) or null
     const int32_t *order;
     int32_t count;
@@ -32,3 +33,7 @@ struct QbArgs {
 int qb_variant_threads(int variant);
 hipError_t launch_qrdm_batched(const QbArgs &q, int variant, int grid, hipStream_t s);
 hipError_t qb_occupancy(int variant, int *wgs_per_cu);
+
+// device copies of the plan's sizes (for the learned-predictor kernels)
+extern "C" int qb_plan_sizes(const qrdm_batch_plan *pl, int32_t *batch, const int32_t **m, const int32_t **n,
+                             const int32_t **lda, int *device);

@@ -141,3 +141,60 @@ def batch(count: int = 2048, seed: int = 0, mmin: int = 32, mmax: int = 512, nmi
     seqs = np.random.SeedSequence(seed).spawn(count)
     mats = [batch_matrix(m, n, r, s) for (m, n, r), s in zip(shapes, seqs)]
     return mats, shapes
+
+
+# ---------------------------------------------------------------- learned predictor
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Initial MLP parameters (16 -> 64 -> 64 -> 3, the flat layout W1, b1, W2,
+    b2, W3, b3): Glorot-uniform weights, zero biases; float64."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((64, 16), (64, 64), (3, 64)):
+        lim = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
+
+
+def spectrum(kind: str, n: int, r: int, rng: np.random.Generator) -> np.ndarray:
+    """Singular values (length min(m, n) = n here) of the training families:
+    geom   10^(-14 (j-1)/(r-1)) for j <= r, zero beyond (the uneven batch's law);
+    stairs 10^-floor(j / step), step = max(r // 6, 1), for j <= r, zero beyond;
+    flat   1 for j <= r, 1e-15 beyond (a clean gap);
+    split  two clusters, 1 and 10^-u (u ~ U[2, 10]), half each, zero beyond r."""
+    s = np.zeros(n)
+    j = np.arange(r)
+    if kind == "geom":
+        s[:r] = np.logspace(0.0, -14.0, r) if r > 1 else 1.0
+    elif kind == "stairs":
+        step = max(r // 6, 1)
+        s[:r] = 10.0 ** (-np.floor(j / step))
+    elif kind == "flat":
+        s[:r] = 1.0
+        s[r:] = 1e-15
+    elif kind == "split":
+        s[:r] = np.where(j < (r + 1) // 2, 1.0, 10.0 ** (-rng.uniform(2.0, 10.0)))
+    else:
+        raise ValueError(kind)
+    return s
+
+
+def training_batch(count: int = 4096, seed: int = 11, mmin: int = 32, mmax: int = 512, nmin: int = 16):
+    """Matrices for the predictor's labels: the uneven batch's shapes with the
+    four spectrum families above.  Returns (mats, shapes (m, n, r), sigmas, kinds)."""
+    rng = np.random.default_rng(seed)
+    kinds = ("geom", "stairs", "flat", "split")
+    mats, shapes, sigmas, kk = [], [], [], []
+    for i in range(count):
+        m = int(rng.integers(mmin, mmax + 1))
+        n = int(rng.integers(nmin, m + 1))
+        r = int(rng.integers((n + 3) // 4, n + 1))
+        kind = kinds[i % 4]
+        s = spectrum(kind, n, r, rng)
+        u = haar_cols(m, n, rng)
+        v = haar_cols(n, n, rng)
+        mats.append(np.asfortranarray((u * s[None, :]) @ v.T))
+        shapes.append((m, n, r))
+        sigmas.append(np.sort(s)[::-1])
+        kk.append(kind)
+    return mats, shapes, sigmas, kk
