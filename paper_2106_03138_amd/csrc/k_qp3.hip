@@ -173,6 +173,25 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
 }
 
 // ------------------------------------------------------------ pivot column
+#define QP_NB_REG 32  // earlier reflectors of the block held in registers per row
+
+// Sum of 32 values over a wavefront by butterfly reduce-scatter (32 shuffles):
+// on return lane L holds the sum of value (L >> 1) when L is even.
+__device__ __forceinline__ double qp_reduce_scatter32(const double (&v)[QP_NB_REG], int lane) {
+    double c16[16], c8[8], c4[4], c2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c16[k] = (b5 ? v[16 + k] : v[k]) + __shfl_xor(b5 ? v[k] : v[16 + k], 32, 64);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c8[k] = (b4 ? c16[8 + k] : c16[k]) + __shfl_xor(b4 ? c16[k] : c16[8 + k], 16, 64);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c4[k] = (b3 ? c8[4 + k] : c8[k]) + __shfl_xor(b3 ? c8[k] : c8[4 + k], 8, 64);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) c2[k] = (b2 ? c4[2 + k] : c4[k]) + __shfl_xor(b2 ? c4[k] : c4[2 + k], 4, 64);
+    const double c1 = (b1 ? c2[1] : c2[0]) + __shfl_xor(b1 ? c2[0] : c2[1], 2, 64);
+    return c1 + __shfl_xor(c1, 1, 64);
+}
+
 __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz, double *PB2) {
     const QrdmCtl *ctl = a.ctl;
     if (ctl->done || ctl->qp_stop) return;
@@ -184,11 +203,15 @@ __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz,
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ double sF[QP_NBMAX];
     __shared__ double red[4][2 + 2 * QP_NBMAX];
-    for (int bb = tid; bb < b; bb += 256) sF[bb] = Fz[(int64_t)bb * a.n + j];
+    __shared__ double stp[QP_NBMAX];  // V[j][bb], written by the thread that holds row j
+    for (int bb = tid; bb < QP_NBMAX; bb += 256) {
+        sF[bb] = bb < b ? Fz[(int64_t)bb * a.n + j] : 0.0;
+        stp[bb] = 0.0;
+    }
     __syncthreads();
     const int64_t r = r0 + tid;
+    const bool live = (r < a.m) && (r >= j);
     // per row: normalize the pending reflector (column j-1), swap, update x_r
-    double x = 0.0;
     if (r < a.m) {
         if (ctl->qp_pend) {
             const int64_t pc = j - 1;
@@ -200,32 +223,54 @@ __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz,
             a.A[j * a.lda + r] = a.A[jm * a.lda + r];
             a.A[jm * a.lda + r] = t1;
         }
-        if (r >= j) {
+    }
+    const bool below = live && (r > j);
+    const bool atj = live && (r == j);
+    double x = 0.0;
+    if (b <= QP_NB_REG) {
+        // the row's entries of the block's reflectors, loaded once (all loads issued together)
+        double vr[QP_NB_REG];
+#pragma unroll
+        for (int u = 0; u < QP_NB_REG; ++u) vr[u] = (live && u < b) ? a.A[(k0 + u) * a.lda + r] : 0.0;
+        if (live) {
+            x = a.A[j * a.lda + r];
+#pragma unroll
+            for (int u = 0; u < QP_NB_REG; ++u) x -= vr[u] * sF[u];
+            a.A[j * a.lda + r] = x;
+        }
+        if (atj) {
+#pragma unroll
+            for (int u = 0; u < QP_NB_REG; ++u)
+                if (u < b) stp[u] = vr[u];
+        }
+        double pv[QP_NB_REG];
+#pragma unroll
+        for (int u = 0; u < QP_NB_REG; ++u) pv[u] = below ? vr[u] * x : 0.0;
+        const double d = qp_reduce_scatter32(pv, lane);
+        if ((lane & 1) == 0 && (lane >> 1) < b) red[wv][2 + (lane >> 1)] = d;
+    } else {
+        if (live) {
             x = a.A[j * a.lda + r];
             for (int bb = 0; bb < b; ++bb) x -= a.A[(k0 + bb) * a.lda + r] * sF[bb];
             a.A[j * a.lda + r] = x;
         }
+        for (int bb = 0; bb < b; ++bb) {
+            const double vb = (below || atj) ? a.A[(k0 + bb) * a.lda + r] : 0.0;
+            const double d = wave_sum(below ? vb * x : 0.0);
+            if (lane == 0) red[wv][2 + bb] = d;
+            if (atj) stp[bb] = vb;
+        }
     }
-    // partial sums: [0] sum_{r>j} x^2, [1] x_j, [2+bb] sum_{r>j} v_bb[r] x_r, [2+b+bb] v_bb[j]
-    const bool below = (r < a.m) && (r > j);
-    const bool atj = (r < a.m) && (r == j);
-    double s0 = below ? x * x : 0.0;
-    double s1 = atj ? x : 0.0;
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
+    // [0] sum_{r>j} x^2, [1] x_j, [2+bb] sum_{r>j} v_bb[r] x_r, [2+b+bb] v_bb[j]
+    const double s0 = wave_sum(below ? x * x : 0.0);
+    const double s1 = wave_sum(atj ? x : 0.0);
     if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
-    for (int bb = 0; bb < b; ++bb) {
-        const double vb = (below || atj) ? a.A[(k0 + bb) * a.lda + r] : 0.0;
-        double d = below ? vb * x : 0.0;
-        double tp = atj ? vb : 0.0;
-        d = wave_sum(d);
-        tp = wave_sum(tp);
-        if (lane == 0) { red[wv][2 + bb] = d; red[wv][2 + b + bb] = tp; }
-    }
     __syncthreads();
     const int nv = 2 + 2 * b;
-    for (int e = tid; e < nv; e += 256)
-        PB2[(int64_t)blockIdx.x * (2 + 2 * QP_NBMAX) + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    for (int e = tid; e < nv; e += 256) {
+        const double v = e < 2 + b ? red[0][e] + red[1][e] + red[2][e] + red[3][e] : stp[e - 2 - b];
+        PB2[(int64_t)blockIdx.x * (2 + 2 * QP_NBMAX) + e] = v;
+    }
 }
 
 // -------------------------------------------------------------------- GEMV
@@ -285,19 +330,27 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
     if (c >= a.n) return;
     const double *xc = a.A + j * a.lda;
     const double *ac = a.A + c * a.lda;
-    double d = 0.0;
-    for (int64_t r = j + 1 + lane; r < a.m; r += 64) d += xc[r] * ac[r];
-    d = wave_sum(d);
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // four chains keep four loads in flight
+    int64_t r = j + 1 + lane;
+    for (; r + 192 < a.m; r += 256) {
+        d0 += xc[r] * ac[r];
+        d1 += xc[r + 64] * ac[r + 64];
+        d2 += xc[r + 128] * ac[r + 128];
+        d3 += xc[r + 192] * ac[r + 192];
+    }
+    for (; r < a.m; r += 64) d0 += xc[r] * ac[r];
+    const double d = wave_sum((d0 + d1) + (d2 + d3));
+    // the F row of column c, one earlier reflector per lane (b <= 64)
+    const double fz = lane < b ? Fz[(int64_t)lane * a.n + c] : 0.0;
+    const double corr = wave_sum(lane < b ? fz * auxv[lane] : 0.0);
+    const double rcor = wave_sum(lane < b ? fz * sv[2 + b + lane] : 0.0);
     if (lane == 0) {
         // F[c, b] = tau v^T a_c - tau sum_{b'<b} F[c, b'] (V^T v)_{b'}
         double f = ac[j] + d / den;
-        double corr = 0.0;
-        for (int bb = 0; bb < b; ++bb) corr += Fz[(int64_t)bb * a.n + c] * auxv[bb];
         f = ti * f - ti * corr;
         Fz[(int64_t)b * a.n + c] = f;
         // pivot row of R: A[j, c] -= sum_{b' <= b} V[j, b'] F[c, b'], V[j, b] = 1
-        double rjc = ac[j] - f;
-        for (int bb = 0; bb < b; ++bb) rjc -= sv[2 + b + bb] * Fz[(int64_t)bb * a.n + c];
+        const double rjc = ac[j] - f - rcor;
         a.A[c * a.lda + j] = rjc;
         // partial norm update with the new row (cancellation-safe rule)
         const double v1 = a.vn1[c];
