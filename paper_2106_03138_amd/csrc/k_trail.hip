@@ -40,9 +40,20 @@ template <> struct Mfma<float> {
 };
 
 // ------------------------------------------------------------------ GEMM1
-#define G1_NT 256   // trailing columns per workgroup (V reused across them)
-#define G1_KC 16    // rows staged per step
-#define G1_TH 512   // threads: 8 wavefronts, 32 columns each
+#ifndef G1_NT
+#define G1_NT 256   // trailing columns per workgroup (V reused across them): 128 or 256
+#endif
+#ifndef G1_TARGET_WGS
+#define G1_TARGET_WGS 256  // split count aims at this many workgroups
+#endif
+#ifndef G1_KC
+#define G1_KC 32    // rows staged per step: 16 or 32
+#endif
+#define G1_TH 512   // threads: 8 wavefronts, G1_NT / 8 columns each
+#define G1_CT (G1_NT / 128)  // 16-column tiles per wavefront
+#define G1_CPP (G1_TH / G1_KC)          // columns staged per pass (one thread per row of a column)
+#define G1_AU (G1_NT / G1_CPP)          // staged A elements per thread per step
+#define G1_VU (64 / G1_CPP)             // staged V elements per thread per step
 #define G1_LD (G1_KC + 1)
 
 __device__ __forceinline__ void st_coh(double *p, double v) {
@@ -87,25 +98,25 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     typedef typename Mfma<T>::acc_t acc_t;
-    acc_t acc[8];  // 4 row tiles x 2 column tiles
+    acc_t acc[4 * G1_CT];  // 4 row tiles x G1_CT column tiles
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = acc_t{0, 0, 0, 0};
+    for (int u = 0; u < 4 * G1_CT; ++u) acc[u] = acc_t{0, 0, 0, 0};
     const int ncols = (int)((w2 - jb) < G1_NT ? (w2 - jb) : G1_NT);
     const double *Abase = a.A + (c0 + jb) * a.lda + ns;
-    // staged element u*512 + tid: row r = tid % 16, column/reflector q = u*32 + tid/16
-    const int rr = tid & 15, qq = tid >> 4;
-    T vreg[2], areg[8];
+    // staged element u*512 + tid: row r = tid % G1_KC, column/reflector q = u*G1_CPP + tid/G1_KC
+    const int rr = tid % G1_KC, qq = tid / G1_KC;
+    T vreg[G1_VU], areg[G1_AU];
     auto fetch = [&](int64_t rc) {
         const int64_t row = rc + rr;
         const bool rok = row < re;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int q = q0 + u * 32 + qq;
+        for (int u = 0; u < G1_VU; ++u) {
+            const int q = q0 + u * G1_CPP + qq;
             vreg[u] = (rok && q < l) ? V[(int64_t)q * ldv + row] : (T)0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int q = u * 32 + qq;
+        for (int u = 0; u < G1_AU; ++u) {
+            const int q = u * G1_CPP + qq;
             areg[u] = (rok && q < ncols) ? (T)Abase[(int64_t)q * a.lda + row] : (T)0;
         }
     };
@@ -113,23 +124,25 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     for (int64_t rc = rb; rc < re; rc += G1_KC) {
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 2; ++u) Vs[(u * 32 + qq) * G1_LD + rr] = vreg[u];
+        for (int u = 0; u < G1_VU; ++u) Vs[(u * G1_CPP + qq) * G1_LD + rr] = vreg[u];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) As[(u * 32 + qq) * G1_LD + rr] = areg[u];
+        for (int u = 0; u < G1_AU; ++u) As[(u * G1_CPP + qq) * G1_LD + rr] = areg[u];
         __syncthreads();
         if (rc + G1_KC < re) fetch(rc + G1_KC);
-        // wave wv owns columns [32 wv, 32 wv + 32): 2 column tiles x ltz row tiles
+        // wave wv owns columns [16 G1_CT wv, 16 G1_CT (wv + 1)): G1_CT column tiles x ltz row tiles
 #pragma unroll
         for (int k = 0; k < G1_KC; k += 4) {
-            T bcol[2];
+            T bcol[G1_CT];
 #pragma unroll
-            for (int c = 0; c < 2; ++c) bcol[c] = As[(wv * 32 + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
+            for (int c = 0; c < G1_CT; ++c)
+                bcol[c] = As[(wv * 16 * G1_CT + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
 #pragma unroll
             for (int ti = 0; ti < 4; ++ti) {
                 if (ti < ltz) {
                     const T av = Vs[(ti * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) acc[ti * 2 + c] = Mfma<T>::op(av, bcol[c], acc[ti * 2 + c]);
+                    for (int c = 0; c < G1_CT; ++c)
+                        acc[ti * G1_CT + c] = Mfma<T>::op(av, bcol[c], acc[ti * G1_CT + c]);
                 }
             }
         }
@@ -140,12 +153,12 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     for (int ti = 0; ti < 4; ++ti) {
         if (ti < ltz) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int64_t col = jb + wv * 32 + c * 16 + (lane & 15);
+            for (int c = 0; c < G1_CT; ++c) {
+                const int64_t col = jb + wv * 16 * G1_CT + c * 16 + (lane & 15);
                 if (col < w2) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * 2 + c][v]);
+                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * G1_CT + c][v]);
                 }
             }
         }
@@ -174,23 +187,23 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     const int jl = tid >> 3, g = tid & 7;  // 8 lanes of one wavefront per column
     for (int cb = 0; cb < ncols; cb += 64) {
         __syncthreads();
-        for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 4) {
-            double sum4[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int s2 = 0; s2 < nsplit; ++s2) {
-                double v4[4];
+        // every split's partial of an element is loaded before any is summed
+        // (QK_SPLIT_MAX loads in flight per element), then summed in split order
+        for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 2) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * G1_TH + tid;
-                    const int aa = e >> 6, j = e & 63;
-                    v4[u] = (e < l * 64 && cb + j < ncols)
-                                ? ld_coh(Yp + ((int64_t)s2 * QK_KM + aa) * ldz + jb + cb + j) : 0.0;
-                }
+            for (int u = 0; u < 2; ++u) {
+                const int e = e0 + u * G1_TH + tid;
+                const int aa = e >> 6, j = e & 63;
+                const bool ok = e < l * 64 && cb + j < ncols;
+                double v[QK_SPLIT_MAX];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) sum4[u] += v4[u];
+                for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2)
+                    v[s2] = (ok && s2 < nsplit) ? ld_coh(Yp + ((int64_t)s2 * QK_KM + aa) * ldz + jb + cb + j) : 0.0;
+                double sum = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
+                if (e < l * 64) Ys[e] = sum;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (e0 + u * G1_TH + tid < l * 64) Ys[e0 + u * G1_TH + tid] = sum4[u];
         }
         __syncthreads();
         for (int aa = 0; aa < l; ++aa) {
@@ -350,8 +363,8 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     const int64_t ldz = a.n;
     const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
-    // splits: aim at ~256 workgroups, at most QK_SPLIT_MAX, at least 256 rows each
-    int nsplit = (256 + ntile - 1) / ntile;
+    // splits: aim at ~G1_TARGET_WGS workgroups, at most QK_SPLIT_MAX, at least 256 rows each
+    int nsplit = (G1_TARGET_WGS + ntile - 1) / ntile;
     if (nsplit > QK_SPLIT_MAX) nsplit = QK_SPLIT_MAX;
     int64_t maxs = (t_bound + 255) / 256;
     if (nsplit > maxs) nsplit = (int)maxs;

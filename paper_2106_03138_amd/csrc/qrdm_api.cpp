@@ -79,7 +79,7 @@ Layout make_layout(int64_t m, int64_t n) {
     L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
     L.z = take(sizeof(double) * (size_t)QK_KM * nn);
     L.yp = take(sizeof(double) * 16 * (size_t)QK_KM * nn);
-    L.tcnt = take(sizeof(uint32_t) * (size_t)((nn + 255) / 256 + 1));
+    L.tcnt = take(sizeof(uint32_t) * (size_t)((nn + 63) / 64 + 1));  // one counter per column tile (tiles >= 64 columns)
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
     L.fz = take(sizeof(double) * 64 * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
@@ -309,7 +309,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
     // the GEMM tile counters self-reset, but their place in the cached workspace
     // depends on (m, n): clear them for this call
-    HIP_TRY(hipMemsetAsync(ws + L.tcnt, 0, sizeof(uint32_t) * (size_t)((n + 255) / 256 + 1), s));
+    HIP_TRY(hipMemsetAsync(ws + L.tcnt, 0, sizeof(uint32_t) * (size_t)((n + 63) / 64 + 1), s));
     HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
     int32_t nf = 0;
     HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
