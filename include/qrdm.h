@@ -158,6 +158,45 @@ int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
                  double tau, double delta, int32_t kmax, int32_t *L, int32_t *nL, double *theta,
                  int32_t *J, int32_t *ks, void *stream);
 
+/*
+ * Least squares on top of a factorization: the basic solution of
+ * min_x ||A_in x - b|| (Section 1: column pivoting singles out the solution
+ * with `rank` nonzeros).  With r = min(rank, min(m,n)), y = Q_r^T b where
+ * Q_r = H_0 ... H_{r-1} (the first r reflectors), R11 x1 = y[0:r) (R11 the
+ * leading r x r block of R), x[perm[j]] = x1[j] for j < r and 0 for j >= r.
+ *   A, tau_house, perm  [in] the output of qrdm_factor* / qrp_factor* (A and
+ *              lda as passed to it); perm must be a permutation of 0..n-1
+ *              (entries outside [0, n) are skipped).
+ *   rank       [in, host] the rank to solve with (normally the factorization's);
+ *              rank < 0: X and resid are set to NaN, B is unchanged.
+ *   B          [in/out] m x nrhs, ldb >= max(1,m): on return rows [0, r) hold x1
+ *              (the solution in pivoted order) and rows [r, m) hold y[r:m)
+ *              (as LAPACK xgels leaves them).
+ *   X          [out] n x nrhs, ldx >= max(1,n): the basic solution.
+ *   resid      [out] nrhs doubles or NULL: ||y[r:m)|| = ||A_in x - b|| per column
+ *              (exact in exact arithmetic, since x vanishes on the columns of R12, R22).
+ * If some r_ii = 0 with i < r the solution holds Inf/NaN (no test is made).
+ * One workgroup per 4 right-hand sides; nothing is synchronized.
+ */
+int qrdm_lstsq(const double *A, int64_t m, int64_t n, int64_t lda, const double *tau_house, const int32_t *perm,
+               int64_t rank, double *B, int64_t ldb, int64_t nrhs, double *X, int64_t ldx, double *resid,
+               void *stream);
+
+/*
+ * Post-hoc rank truncation (Section 5: where the stopping criterion
+ * overestimates the numerical rank, the diagonal of R still shows the gap of
+ * the singular values, and R can be truncated afterwards).  With
+ * eps_1 = eps1_scale * 2^-52 (eps1_scale <= 0 selects n, the choice of eq.
+ * (practical stopping criterion_choice1)), *rank_out = the first i < r with
+ * |r_ii| <= eps_1 |r_00| (a NaN entry counts as small), or r if there is none,
+ * where r = min(rank, m, n); rank <= 0 is passed through.  The result is a
+ * prefix, so R11 stays the leading block that qrdm_lstsq solves with.
+ *   A          [in] the output of a factorization (only the diagonal is read).
+ *   rank_out   [out] one int64 in DEVICE memory (not synchronized).
+ */
+int qrdm_truncate_rank(const double *A, int64_t m, int64_t n, int64_t lda, int64_t rank, double eps1_scale,
+                       int64_t *rank_out, void *stream);
+
 /* Frees the workspace cached for the current device. */
 void qrdm_release(void);
 
@@ -231,6 +270,23 @@ int qrdm_batch_factor(qrdm_batch_plan *plan, double *const *A, double *const *ta
 
 /* Frees the plan, its device arrays and graphs (synchronizes the device). */
 void qrdm_batch_plan_destroy(qrdm_batch_plan *plan);
+
+/* Least squares for every matrix of the plan after qrdm_batch_factor: per
+ * matrix i exactly what qrdm_lstsq computes, with rank[i] (DEVICE array, the
+ * factorization's output; < 0 gives NaN solutions).  A, tau_house, perm as
+ * passed to qrdm_batch_factor; B, X: DEVICE arrays of `batch` device pointers,
+ * B[i] m[i] x nrhs with leading dimension max(1, m[i]) (in/out as in
+ * qrdm_lstsq), X[i] n[i] x nrhs with leading dimension max(1, n[i]).
+ * resid: DEVICE array of batch * nrhs doubles (matrix i at i * nrhs) or NULL.
+ * One workgroup per matrix and 4 right-hand sides; nothing is synchronized. */
+int qrdm_batch_lstsq(qrdm_batch_plan *plan, double *const *A, double *const *tau_house, int32_t *const *perm,
+                     const int64_t *rank, double *const *B, double *const *X, int32_t nrhs, double *resid,
+                     void *stream);
+
+/* qrdm_truncate_rank for every matrix of the plan: rank_in, rank_out DEVICE
+ * arrays of `batch` entries (they may be the same array). */
+int qrdm_batch_truncate_rank(qrdm_batch_plan *plan, double *const *A, const int64_t *rank_in, double eps1_scale,
+                             int64_t *rank_out, void *stream);
 
 /* ------------------------------------------------------------------------
  * Learned (tau, delta, k_DM) per matrix.  The paper chooses the parameters by

@@ -13,12 +13,13 @@ Python-side API (torch tensors are used for device memory and streams only):
 from __future__ import annotations
 
 from ._lib import (PREC_FP64, PREC_MIXED, STOP_MAXNORM, STOP_NONE, STOP_PAPER, QrdmError, load)
-from .api import (Batch, BatchPlan, Factorization, batch_params, batch_size_class, colnorms, device_matrix, dm_step,
-                  host_matrix, mlp_adam, mlp_forward, mlp_gradient, mlp_to_params, qrdm_factor, qrp_factor)
+from .api import (Batch, BatchPlan, BatchRHS, Factorization, batch_params, batch_size_class, colnorms, device_matrix, dm_step,
+                  host_matrix, lstsq, truncate_rank, mlp_adam, mlp_forward, mlp_gradient, mlp_to_params, qrdm_factor,
+                  qrp_factor)
 
 __all__ = [
     "PREC_FP64", "PREC_MIXED", "STOP_MAXNORM", "STOP_NONE", "STOP_PAPER", "QrdmError", "load",
-    "Factorization", "colnorms", "device_matrix", "dm_step", "host_matrix", "qrdm_factor", "qrp_factor",
+    "Factorization", "colnorms", "lstsq", "truncate_rank", "BatchRHS", "device_matrix", "dm_step", "host_matrix", "qrdm_factor", "qrp_factor",
     "Batch", "BatchPlan", "batch_params", "batch_size_class", "mlp_adam", "mlp_forward", "mlp_gradient",
     "mlp_to_params",
 ]

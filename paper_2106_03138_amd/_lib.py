@@ -66,6 +66,8 @@ SIGNATURES = {
     "qrdm_colnorms": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),
     "qrdm_dm_step": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _vp, _d, _d, _i32, _P(_i32), _P(_i32),
                                     _P(_d), _P(_i32), _P(_i32), _vp]),
+    "qrdm_lstsq": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _vp]),
+    "qrdm_truncate_rank": (ctypes.c_int, [_vp, _i64, _i64, _i64, _i64, _d, _vp, _vp]),
     "qrdm_release": (None, []),
     "qrdm_batch_plan_create": (ctypes.c_int, [_P(_i32), _P(_i32), _P(_i32), _i32, _P(Params), _P(BatchTune),
                                               _P(_vp)]),
@@ -78,6 +80,8 @@ SIGNATURES = {
     "qrdm_mlp_to_params": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "qrdm_batch_check": (ctypes.c_int, [_vp, _vp, _vp, _d, _vp, _vp, _vp]),
     "qrdm_batch_plan_destroy": (None, [_vp]),
+    "qrdm_batch_lstsq": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "qrdm_batch_truncate_rank": (ctypes.c_int, [_vp, _vp, _vp, _d, _vp, _vp]),
     "qrdm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 

@@ -115,6 +115,44 @@ def qrp_factor(A, stop_rule: int = _lib.STOP_PAPER, nb: int = 32, poll_lag: int 
     return Factorization(tau_house[: min(m, n)], perm[:n], rank.value, stats, [])
 
 
+def lstsq(A, fac: Factorization, B, rank: int | None = None, stream=None):
+    """Basic least-squares solution from a factorization of A (qrdm_lstsq).
+    B (m x nrhs column-major float64 device tensor, or a vector of length m) is
+    overwritten as qrdm_lstsq describes.  Returns (X [n x nrhs] or [n], resid)."""
+    torch = _torch()
+    m, n, lda = _check_matrix(A)
+    vec = B.dim() == 1
+    Bm = B.view(-1, 1) if vec else B
+    if Bm.dtype != torch.float64 or not Bm.is_cuda or Bm.shape[0] != m:
+        raise ValueError("B must be a float64 GPU tensor with m rows")
+    nrhs = Bm.shape[1]
+    if m > 1 and nrhs > 0 and Bm.stride(0) != 1:
+        raise ValueError("B must be column-major (stride(0) == 1)")
+    ldb = max(Bm.stride(1) if nrhs > 1 else m, m, 1)
+    X = torch.empty((max(nrhs, 1), max(n, 1)), dtype=torch.float64, device=A.device).t()
+    resid = torch.empty(max(nrhs, 1), dtype=torch.float64, device=A.device)
+    r = fac.rank if rank is None else int(rank)
+    code = _lib.load().qrdm_lstsq(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.c_void_p(fac.tau_house.data_ptr()),
+                                  ctypes.c_void_p(fac.perm.data_ptr()), r, ctypes.c_void_p(Bm.data_ptr()), ldb, nrhs,
+                                  ctypes.c_void_p(X.data_ptr()), max(n, 1), ctypes.c_void_p(resid.data_ptr()),
+                                  _stream_ptr(stream))
+    _lib.check("qrdm_lstsq", code)
+    X = X[:n, :nrhs]
+    return (X[:, 0] if vec else X), resid[:nrhs]
+
+
+def truncate_rank(A, rank: int, eps1_scale: float = 0.0, stream=None) -> int:
+    """Post-hoc truncated rank from the diagonal of a factored A (qrdm_truncate_rank);
+    synchronizes the stream to return a host integer."""
+    torch = _torch()
+    m, n, lda = _check_matrix(A)
+    out = torch.empty(1, dtype=torch.int64, device=A.device)
+    code = _lib.load().qrdm_truncate_rank(ctypes.c_void_p(A.data_ptr()), m, n, lda, int(rank), float(eps1_scale),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _lib.check("qrdm_truncate_rank", code)
+    return int(out.item())
+
+
 def colnorms(A, stream=None):
     torch = _torch()
     m, n, lda = _check_matrix(A)
@@ -227,6 +265,55 @@ class _SubBatch:
         return len(self.shapes)
 
 
+class BatchRHS:
+    """Right-hand sides and solutions of a batch: packed float64 buffers with
+    B[i] m_i x nrhs (leading dimension max(1, m_i)) and X[i] n_i x nrhs
+    (leading dimension max(1, n_i)), the device pointer arrays, and resid."""
+
+    def __init__(self, batch, nrhs: int):
+        torch = _torch()
+        dev = batch.data.device
+        self.shapes = list(batch.shapes)
+        self.nrhs = int(nrhs)
+        bsz = [max(1, m) * self.nrhs for m, _ in self.shapes]
+        xsz = [max(1, n) * self.nrhs for _, n in self.shapes]
+        self.boff = np.concatenate([[0], np.cumsum(bsz)]).astype(np.int64)
+        self.xoff = np.concatenate([[0], np.cumsum(xsz)]).astype(np.int64)
+        self.b = torch.zeros(max(int(self.boff[-1]), 1), dtype=torch.float64, device=dev)
+        self.x = torch.zeros(max(int(self.xoff[-1]), 1), dtype=torch.float64, device=dev)
+        self.resid = torch.zeros(max(len(self.shapes) * self.nrhs, 1), dtype=torch.float64, device=dev)
+        mk = lambda t, offs: torch.tensor([t.data_ptr() + 8 * int(o) for o in offs[:-1]] or [0],  # noqa: E731
+                                          dtype=torch.int64, device=dev)
+        self.b_ptr = mk(self.b, self.boff)
+        self.x_ptr = mk(self.x, self.xoff)
+
+    def load(self, rhs):
+        """Host right-hand sides: per matrix an (m,) or (m, nrhs) array."""
+        torch = _torch()
+        host = np.zeros(max(int(self.boff[-1]), 1))
+        for i, b in enumerate(rhs):
+            m = self.shapes[i][0]
+            if m == 0:
+                continue
+            b = np.asarray(b, dtype=np.float64).reshape(m, -1)
+            assert b.shape[1] == self.nrhs
+            host[self.boff[i]: self.boff[i] + m * self.nrhs] = b.reshape(-1, order="F")
+        self.b.copy_(torch.from_numpy(host))
+
+    def rhs(self, i):
+        m = self.shapes[i][0]
+        seg = self.b[int(self.boff[i]): int(self.boff[i]) + m * self.nrhs].cpu().numpy()
+        return seg.reshape((m, self.nrhs), order="F")
+
+    def solution(self, i):
+        n = self.shapes[i][1]
+        seg = self.x[int(self.xoff[i]): int(self.xoff[i]) + n * self.nrhs].cpu().numpy()
+        return seg.reshape((n, self.nrhs), order="F")
+
+    def residual(self, i):
+        return self.resid[i * self.nrhs: (i + 1) * self.nrhs].cpu().numpy()
+
+
 class BatchPlan:
     """qrdm_batch_plan: size classes, longest-first order, launch variant per class."""
 
@@ -261,6 +348,28 @@ class BatchPlan:
                                              ctypes.c_void_p(bt.status.data_ptr()), pm, inf, 1 if use_graph else 0,
                                              _stream_ptr(stream))
         _lib.check("qrdm_batch_factor", code)
+
+    def lstsq(self, rhs: BatchRHS, stream=None):
+        """Basic least-squares solutions of the factored batch (qrdm_batch_lstsq)."""
+        bt = self.batch
+        code = _lib.load().qrdm_batch_lstsq(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                            ctypes.c_void_p(bt.t_ptr.data_ptr()), ctypes.c_void_p(bt.p_ptr.data_ptr()),
+                                            ctypes.c_void_p(bt.rank.data_ptr()), ctypes.c_void_p(rhs.b_ptr.data_ptr()),
+                                            ctypes.c_void_p(rhs.x_ptr.data_ptr()), rhs.nrhs,
+                                            ctypes.c_void_p(rhs.resid.data_ptr()), _stream_ptr(stream))
+        _lib.check("qrdm_batch_lstsq", code)
+
+    def truncate_rank(self, eps1_scale: float = 0.0, out=None, stream=None):
+        """Post-hoc truncated ranks (int64 device tensor) of the factored batch."""
+        torch = _torch()
+        bt = self.batch
+        if out is None:
+            out = torch.empty(max(len(bt), 1), dtype=torch.int64, device=bt.data.device)
+        code = _lib.load().qrdm_batch_truncate_rank(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                                    ctypes.c_void_p(bt.rank.data_ptr()), float(eps1_scale),
+                                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        _lib.check("qrdm_batch_truncate_rank", code)
+        return out[: len(bt)]
 
     def features(self, out=None, stream=None):
         """Per-matrix features (float64 device tensor [batch, 16])."""

@@ -278,7 +278,6 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
     QrdmCtl *ctl = a.ctl;
     if (ctl->done || ctl->qp_stop) return;
     const int64_t j = ctl->ns;
-    const int64_t k0 = ctl->qp_k0;
     const int b = ctl->qp_b;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     __shared__ double sv[2 + 2 * QP_NBMAX];

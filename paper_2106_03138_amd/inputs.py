@@ -198,3 +198,21 @@ def training_batch(count: int = 4096, seed: int = 11, mmin: int = 32, mmax: int 
         sigmas.append(np.sort(s)[::-1])
         kk.append(kind)
     return mats, shapes, sigmas, kk
+
+
+def lstsq_factors(m: int, n: int, r: int, seed):
+    """Synthetic output of a pivoted QR for the least-squares solve, in the
+    LAPACK layout: reflector entries N(0, 1/m) below the diagonal, scalars
+    uniform in [0.5, 1], an upper triangle with diagonal entries of random sign
+    and magnitude in [1, 2] and other entries N(0, 1/r), and a random
+    permutation.  Any such arrays define Q_r and R11.  Returns (qr, tau, perm)."""
+    rng = np.random.default_rng(seed)
+    p = min(m, n)
+    qr = np.asfortranarray(rng.standard_normal((m, n)) / np.sqrt(max(m, 1)))
+    up = np.triu(rng.standard_normal((m, n)) / np.sqrt(max(r, 1)), 1)
+    qr = np.where(np.triu(np.ones((m, n), dtype=bool), 1), up, qr)
+    d = rng.uniform(1.0, 2.0, p) * rng.choice([-1.0, 1.0], p)
+    qr[np.arange(p), np.arange(p)] = d
+    tau = rng.uniform(0.5, 1.0, p)
+    perm = rng.permutation(n).astype(np.int32)
+    return np.asfortranarray(qr), tau, perm
