@@ -26,14 +26,14 @@ class OracleBlock(ctypes.Structure):
         ("jmax", ctypes.c_int32), ("umax", ctypes.c_double), ("eps_s", ctypes.c_double),
         ("m_order", ctypes.c_double), ("m_thr", ctypes.c_double), ("m_cos", ctypes.c_double),
         ("m_break", ctypes.c_double), ("m_stop", ctypes.c_double), ("m_fb", ctypes.c_double),
-        ("m_recomp", ctypes.c_double),
+        ("m_recomp", ctypes.c_double), ("gamma", ctypes.c_double), ("sigma_bound", ctypes.c_double),
     ]
 
 
 class OracleParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("delta", ctypes.c_double), ("kmax", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("eps1_scale", ctypes.c_double),
-                ("max_ns", ctypes.c_int64)]
+                ("max_ns", ctypes.c_int64), ("certified", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def lib():
@@ -82,7 +82,7 @@ class Result:
 
 def qrdm(a: np.ndarray, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
          stop_rule: int = STOP_PAPER, eps1_scale: float = 0.0, max_ns: int = -1,
-         log_cap: int | None = None) -> Result:
+         log_cap: int | None = None, certified: bool = False) -> Result:
     """Oracle QRDM2 (Algorithm 4) on a copy of a (m x n float64)."""
     a = np.array(a, dtype=np.float64, order="F", copy=True)
     m, n = a.shape
@@ -93,7 +93,7 @@ def qrdm(a: np.ndarray, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
     cap = log_cap if log_cap is not None else max(n, 1) + 2
     blocks = (OracleBlock * cap)()
     nb = ctypes.c_int64(0)
-    prm = OracleParams(tau, delta, kmax, stop_rule, eps1_scale, max_ns)
+    prm = OracleParams(tau, delta, kmax, stop_rule, eps1_scale, max_ns, 1 if certified else 0, 0)
     code = lib().oracle_qrdm(_dp(a), m, n, max(m, 1), ctypes.byref(prm), _dp(tau_h),
                              perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(rank),
                              blocks, cap, ctypes.byref(nb))

@@ -88,6 +88,10 @@ typedef struct {
     double m_stop;     /* stop test (while rank undecided)                 */
     double m_fb;       /* fallback test                                    */
     double m_recomp;   /* DBu08 recompute decisions                        */
+    double gamma;      /* Lemma 1: min_i (1 - sum_{j != i} |theta_ij|) over J */
+    double sigma_bound;/* Lemma 1: sqrt(gamma + tau_J^2 - 1) max_J ||c_j||,
+                          tau_J = min_J ||c_j|| / max_J ||c_j||; 0 when
+                          gamma <= 1 - tau_J^2 (the lemma does not apply)   */
 } oracle_block;
 
 typedef struct {
@@ -96,6 +100,8 @@ typedef struct {
     int32_t stop_rule;
     double eps1_scale; /* eps_1 = eps1_scale * eps; <= 0 means n */
     int64_t max_ns;    /* stop after ns >= max_ns (bounded runs); <0 = off */
+    int32_t certified; /* 1 = delta <= tau^2 / (|L| - 1) per block, eq. (delta_max) */
+    int32_t pad;
 } oracle_params;
 
 static double sq(double x) { return x * x; }
@@ -140,7 +146,7 @@ static int cand_cmp(const void *pa, const void *pb) {
  * Margins of the decisions are written into rec when it is not NULL.
  */
 static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
-                      const double *vn1, double tau, double delta, int64_t cap,
+                      const double *vn1, double tau, double delta, int64_t cap, int certified,
                       int64_t *L, int *nL, double *theta, int64_t *J, int *ks,
                       oracle_block *rec, cand_t *work, double *G, double nu) {
     int64_t t = m - ns;
@@ -182,6 +188,12 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
             if (theta) theta[a * nl + b] = th;
         }
     }
+    /* eq. (delta_max): with delta <= tau^2 / (k_max - 1), k_max the candidate
+     * count, every accepted block meets the hypotheses of Lemma 1 */
+    if (certified && nl > 1) {
+        double dmax = tau * tau / (double)(nl - 1);
+        if (dmax < delta) delta = dmax;
+    }
     /* steps 5-7: greedy acceptance |theta_ij| < delta for all j in J (R6) */
     J[0] = L[0];
     int k = 1;
@@ -214,6 +226,30 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
         if (ok) J[k++] = L[a];
     }
     *ks = k;
+    /* Lemma 1 on C = [A]_{ns:m, J}: gamma of the cosine matrix of J and the
+     * lower bound of sigma_min(C), with tau_J the actual norm ratio inside J */
+    double cmax = 0.0, cmin = INFINITY, gam = INFINITY;
+    for (int a = 0; a < k; ++a) {
+        int64_t ai = 0;
+        while (L[ai] != J[a]) ++ai;
+        double da = sqrt(G[ai * nl + ai]);
+        cmax = fmax(cmax, da);
+        cmin = fmin(cmin, da);
+        double rs = 0.0;
+        for (int b = 0; b < k; ++b) {
+            if (b == a) continue;
+            int64_t bi = 0;
+            while (L[bi] != J[b]) ++bi;
+            rs += fabs(G[ai * nl + bi] / (da * sqrt(G[bi * nl + bi])));
+        }
+        gam = fmin(gam, 1.0 - rs);
+    }
+    double tj = cmax > 0.0 ? cmin / cmax : 0.0;
+    double slack = gam + tj * tj - 1.0;
+    if (rec) {
+        rec->gamma = gam;
+        rec->sigma_bound = slack > 0.0 ? sqrt(slack) * cmax : 0.0;
+    }
     if (rec) {
         rec->ncand = (int32_t)nc;
         rec->nL = (int32_t)nl;
@@ -351,8 +387,12 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
                 if (j != jmax && vn1[j] > second) second = vn1[j];
             rec.m_order = (second >= 0.0) ? noise_margin(second, umax, nu) : INFINITY;
             rec.ncand = 1; rec.nL = 1; rec.jmax = (int32_t)jmax; rec.umax = umax;
+            /* a single column: gamma = 1 and sigma_min(C) = ||c|| (Lemma 1, k = 1) */
+            rec.gamma = 1.0;
+            rec.sigma_bound = norm2(A + jmax * lda + ns, m - ns);
         } else {
-            dm_select(A, m, n, lda, ns, vn1, prm->tau, prm->delta, cap, L, &nl, NULL, J, &ks, &rec, work, G, nu);
+            dm_select(A, m, n, lda, ns, vn1, prm->tau, prm->delta, cap, prm->certified, L, &nl, NULL, J, &ks, &rec,
+                      work, G, nu);
         }
         /* eq. (lenght_check): eps_s = tau * max u (R12) */
         double eps_s = prm->tau * umax;
@@ -523,7 +563,7 @@ int oracle_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t n
     double *G = malloc(sizeof(double) * (size_t)(cap * cap));
     if (!work || !G) { free(work); free(G); return O_ERR_NOMEM; }
     int nl = 0, k = 0;
-    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, L, &nl, theta, J, &k, NULL, work, G, 0.0);
+    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, 0, L, &nl, theta, J, &k, NULL, work, G, 0.0);
     *nL = nl;
     *ks = k;
     free(work);
