@@ -71,6 +71,9 @@ typedef struct {
                            (0 = synchronize every block; default 4)                       */
     int32_t profile;    /* 1 = time the trailing GEMMs with HIP events on `stream`
                            (results in qrdm_stats; adds event overhead); default 0        */
+    int32_t certified;  /* 1 = certified DM: per block, delta is lowered to
+                           tau^2 / (|L| - 1) (eq. delta_max, |L| the candidate count), so
+                           every block meets the hypotheses of Lemma 1; default 0         */
 } qrdm_params;
 
 typedef struct {
@@ -103,6 +106,14 @@ typedef struct {
     int32_t l;        /* reflectors kept after the break   */
     int32_t fallback; /* 1 = scalar pivoting step          */
     double umax;      /* max partial norm at selection     */
+    /* Lemma 1 on C = the k_s accepted columns [A]_{ns:m, J} at this step, from
+     * their Gram matrix: gamma = min_i (1 - sum_{j != i} |theta_ij|) and
+     * sigma_bound = sqrt(gamma + tau_J^2 - 1) max_J ||c_j|| with
+     * tau_J = min_J ||c_j|| / max_J ||c_j|| (0 when gamma <= 1 - tau_J^2: the
+     * lemma does not apply).  sigma_min(C) >= sigma_bound; with certified = 1 the
+     * bound is positive.  A one-column step records gamma = 1, sigma_bound = ||c||. */
+    double gamma;
+    double sigma_bound;
 } qrdm_block;
 
 /* Fills *p with the paper's defaults: tau = 0.15, delta = 0.9 (Section 5) and
@@ -241,7 +252,9 @@ typedef struct qrdm_batch_plan qrdm_batch_plan;
 
 /* Plans a batch of `batch` matrices with HOST arrays m[batch], n[batch],
  * lda[batch] and default parameters *p (tau, delta, kmax, stop_rule,
- * eps1_scale; precision must be FP64).  tune[QRDM_BATCH_CLASSES] (host, may be
+ * eps1_scale, certified; precision must be FP64).  The batched path keeps
+ * no per-step log: in certified mode every block meets Lemma 1 by
+ * construction, and the bound itself is reported by qrdm_factor_ex only.  tune[QRDM_BATCH_CLASSES] (host, may be
  * NULL = built-in defaults).  Allocates the plan's device arrays (sizes, order,
  * queue counters) on the current device.  Returns 0, -i for an invalid
  * argument, QRDM_ERR_UNSUPPORTED if some n exceeds QRDM_BATCH_NMAX or

@@ -17,7 +17,8 @@ ERR_NONFINITE, ERR_NOMEM, ERR_UNSUPPORTED, ERR_HIP = 1, 2, 3, 1000
 class Params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("delta", ctypes.c_double), ("kmax", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("eps1_scale", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("poll_lag", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("poll_lag", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("certified", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -31,7 +32,8 @@ class Stats(ctypes.Structure):
 
 class Block(ctypes.Structure):
     _fields_ = [("ns", ctypes.c_int64), ("nL", ctypes.c_int32), ("ks", ctypes.c_int32),
-                ("l", ctypes.c_int32), ("fallback", ctypes.c_int32), ("umax", ctypes.c_double)]
+                ("l", ctypes.c_int32), ("fallback", ctypes.c_int32), ("umax", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("sigma_bound", ctypes.c_double)]
 
 
 class BatchParams(ctypes.Structure):

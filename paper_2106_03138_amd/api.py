@@ -58,24 +58,26 @@ class Factorization:
     blocks: list = field(default_factory=list)
 
 
-def _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profile=False):
+def _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profile=False, certified=False):
     p = _lib.Params()
     _lib.load().qrdm_default_params(ctypes.byref(p))
     p.tau, p.delta, p.kmax = float(tau), float(delta), int(kmax)
     p.stop_rule, p.precision, p.poll_lag = int(stop_rule), int(precision), int(poll_lag)
     p.eps1_scale = float(eps1_scale)
     p.profile = 1 if profile else 0
+    p.certified = 1 if certified else 0
     return p
 
 
 def qrdm_factor(A, tau: float = 0.15, delta: float = 0.9, kmax: int = 64, stop_rule: int = _lib.STOP_PAPER,
                 precision: int = _lib.PREC_FP64, poll_lag: int = 4, eps1_scale: float = 0.0,
                 log: bool = False, profile: bool = False, stream=None, tau_house=None,
-                perm=None) -> Factorization:
-    """QRDM (Algorithm 4 with Algorithm 1) of A in place."""
+                perm=None, certified: bool = False) -> Factorization:
+    """QRDM (Algorithm 4 with Algorithm 1) of A in place.  With log=True,
+    blocks holds (ns, nL, ks, l, fallback, gamma, sigma_bound) per step."""
     torch = _torch()
     m, n, lda = _check_matrix(A)
-    p = _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profile)
+    p = _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profile, certified)
     if tau_house is None:
         tau_house = torch.empty(max(min(m, n), 1), dtype=torch.float64, device=A.device)
     if perm is None:
@@ -91,7 +93,8 @@ def qrdm_factor(A, tau: float = 0.15, delta: float = 0.9, kmax: int = 64, stop_r
         blocks if log else None, cap, ctypes.byref(nlog), _stream_ptr(stream))
     _lib.check("qrdm_factor_ex", code)
     stats = {k: getattr(st, k) for k, _ in _lib.Stats._fields_}
-    bl = [(b.ns, b.nL, b.ks, b.l, b.fallback) for b in list(blocks)[: min(nlog.value, cap)]] if log else []
+    bl = [(b.ns, b.nL, b.ks, b.l, b.fallback, b.gamma, b.sigma_bound)
+          for b in list(blocks)[: min(nlog.value, cap)]] if log else []
     return Factorization(tau_house[: min(m, n)], perm[:n], rank.value, stats, bl)
 
 
@@ -318,9 +321,9 @@ class BatchPlan:
     """qrdm_batch_plan: size classes, longest-first order, launch variant per class."""
 
     def __init__(self, batch: Batch, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
-                 stop_rule: int = _lib.STOP_PAPER, eps1_scale: float = 0.0, tune=None):
+                 stop_rule: int = _lib.STOP_PAPER, eps1_scale: float = 0.0, tune=None, certified: bool = False):
         lib = _lib.load()
-        p = _params(tau, delta, kmax, stop_rule, _lib.PREC_FP64, 4, eps1_scale)
+        p = _params(tau, delta, kmax, stop_rule, _lib.PREC_FP64, 4, eps1_scale, certified=certified)
         b = len(batch)
         arr = lambda v: (ctypes.c_int32 * max(b, 1))(*v)  # noqa: E731
         m = arr([s[0] for s in batch.shapes])

@@ -625,6 +625,8 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
                 qb_gram<NT>(ccol, nL, t, S.G);
                 __syncthreads();
                 if (wv == 0) {
+                    // certified mode: delta <= tau^2 / (k_max - 1), eq. (delta_max)
+                    const double dl = q.certified ? fmin(delta, tau * tau / (double)(nL - 1)) : delta;
                     // lane j keeps whether candidate j is accepted; Theta_ij = G_ij / (d_i d_j)
                     const double dj = lane < nL ? sqrt(S.G[lane * QB_LD + lane]) : 0.0;
                     bool acc = lane == 0;
@@ -634,7 +636,7 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
                         bool bad = false;
                         if (acc && lane < i2) {
                             const double th = S.G[i2 * QB_LD + lane] / (di * dj);
-                            bad = !(fabs(th) < delta);
+                            bad = !(fabs(th) < dl);
                         }
                         const bool rej = __any(bad);
                         if (!rej) {

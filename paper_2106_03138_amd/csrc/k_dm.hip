@@ -402,6 +402,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     __shared__ double sd[QK_KM];
     __shared__ double sG[QK_KM * QK_KM];
     __shared__ int sJ[QK_KM];
+    __shared__ int sAi[QK_KM];  // candidate index (row of G) of each accepted column
     __shared__ int sjslot[QK_KM];
     __shared__ int soutpos[QK_KM];
     __shared__ int s_ks;
@@ -432,6 +433,9 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
                 theta_out[e] = G[i * QK_KM + j] / (sd[i] * sd[j]);
             }
         }
+        // eq. (delta_max): delta <= tau^2 / (k_max - 1), k_max the candidate
+        // count, puts every accepted block under the hypotheses of Lemma 1
+        const double delta = a.certified ? fmin(a.delta, a.tau * a.tau / (double)(nL - 1)) : a.delta;
         if (tid < 64) {
             // greedy acceptance in candidate order, one wavefront; lane owns
             // candidates lane and lane+64
@@ -441,11 +445,11 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
                 bool bad = false;
                 if (lane < i && acc0) {
                     double th = fabs(G[i * QK_KM + lane] / (di * sd[lane]));
-                    bad = !(th < a.delta);
+                    bad = !(th < delta);
                 }
                 if (lane + 64 < i && acc1) {
                     double th = fabs(G[i * QK_KM + lane + 64] / (di * sd[lane + 64]));
-                    bad = bad || !(th < a.delta);
+                    bad = bad || !(th < delta);
                 }
                 const bool any_bad = __any(bad);
                 const bool ok = !any_bad && (di > 0.0);
@@ -457,15 +461,65 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             // compact accepted candidates in order
             unsigned long long b0 = __ballot(acc0), b1 = __ballot(acc1);
             int c0 = __popcll(b0);
-            if (acc0) sJ[__popcll(b0 & ((1ull << lane) - 1))] = ctl->L[lane];
-            if (acc1) sJ[c0 + __popcll(b1 & ((1ull << lane) - 1))] = ctl->L[lane + 64];
+            if (acc0) {
+                const int o = __popcll(b0 & ((1ull << lane) - 1));
+                sJ[o] = ctl->L[lane];
+                sAi[o] = lane;
+            }
+            if (acc1) {
+                const int o = c0 + __popcll(b1 & ((1ull << lane) - 1));
+                sJ[o] = ctl->L[lane + 64];
+                sAi[o] = lane + 64;
+            }
             if (lane == 0) s_ks = c0 + __popcll(b1);
         }
     } else {
-        if (tid == 0) { sJ[0] = ctl->L[0]; s_ks = 1; }
+        if (tid == 0) { sJ[0] = ctl->L[0]; sAi[0] = 0; s_ks = 1; }
     }
     __syncthreads();
     const int ks = s_ks;
+    // ---- Lemma 1 on the accepted columns (second wavefront, beside the swap
+    // bookkeeping of the first): gamma = min_i (1 - sum_{j != i} |theta_ij|)
+    // over J, tau_J = min_J ||c_j|| / max_J ||c_j||, bound sqrt(gamma + tau_J^2 - 1)
+    // max_J ||c_j|| (row sums in the order of J)
+    if (tid >= 64 && tid < 128) {
+        double cmax = 0.0, cmin = INFINITY, gmin = INFINITY;
+        if (nL > 1) {
+            for (int i = lane; i < ks; i += 64) {
+                const int ai = sAi[i];
+                const double da = sd[ai];
+                cmax = fmax(cmax, da);
+                cmin = fmin(cmin, da);
+                double rs = 0.0;
+                for (int j = 0; j < ks; ++j) {
+                    if (j == i) continue;
+                    const int bj = sAi[j];
+                    rs += fabs(G[ai * QK_KM + bj] / (da * sd[bj]));
+                }
+                gmin = fmin(gmin, 1.0 - rs);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+                cmin = fmin(cmin, __shfl_xor(cmin, o, 64));
+                gmin = fmin(gmin, __shfl_xor(gmin, o, 64));
+            }
+        } else {
+            // one column: gamma = 1 and sigma_min = its norm over rows ns..m-1
+            const double *col = a.A + (int64_t)ctl->L[0] * a.lda + ns;
+            double s = 0.0;
+            for (int64_t r = lane; r < a.m - ns; r += 64) s += col[r] * col[r];
+            s = wave_sum(s);
+            cmax = cmin = sqrt(s);
+            gmin = 1.0;
+        }
+        if (lane == 0) {
+            const double tj = cmax > 0.0 ? cmin / cmax : 0.0;
+            const double slack = gmin + tj * tj - 1.0;
+            ctl->gamma = gmin;
+            ctl->sigma_bound = slack > 0.0 ? sqrt(slack) * cmax : 0.0;
+        }
+    }
     // ---- transpositions: for i = 0..ks-1 swap position ns+i with the current
     // position of column J_i.  Slots: 0..ks-1 = positions ns..ns+ks-1, then the
     // accepted columns outside that range in list order.

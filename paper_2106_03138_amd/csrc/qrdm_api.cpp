@@ -29,7 +29,12 @@ struct Snapshot {  // first bytes of QrdmCtl copied back for polling
     int64_t ns;
     int64_t rank;
     int32_t l, ks, nL, done, fallback, jmax;
+    double gamma, sigma_bound;
 };
+static_assert(offsetof(Snapshot, jmax) == offsetof(QrdmCtl, jmax) &&
+                  offsetof(Snapshot, gamma) == offsetof(QrdmCtl, gamma) &&
+                  offsetof(Snapshot, sigma_bound) == offsetof(QrdmCtl, sigma_bound),
+              "the polled snapshot is a prefix of the control block");
 
 struct Workspace {
     int device = -1;
@@ -147,6 +152,7 @@ int check_common(const double *A, int64_t m, int64_t n, int64_t lda, const qrdm_
         if (p->precision < 0 || p->precision > 1) return -5;
         if (p->poll_lag < 0) return -5;
         if (p->profile < 0 || p->profile > 1) return -5;
+        if (p->certified < 0 || p->certified > 1) return -5;
     }
     if (m > 0 && n > 0 && !A) return -1;
     return 0;
@@ -207,6 +213,7 @@ void qrdm_default_params(qrdm_params *p) {
     p->precision = QRDM_PREC_FP64;
     p->poll_lag = 4;
     p->profile = 0;
+    p->certified = 0;
 }
 
 const char *qrdm_strerror(int code) {
@@ -289,6 +296,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     a.delta = p.delta;
     a.kmax = p.kmax;
     a.stop_rule = p.stop_rule;
+    a.certified = p.certified;
     // working precision of the trailing data: 2^-52 (FP64) or 2^-23 (FP32 updates)
     const double eps_w = (p.precision == QRDM_PREC_MIXED) ? 1.1920928955078125e-07 : 2.220446049250313e-16;
     a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * eps_w;
@@ -371,6 +379,8 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
                     b.l = sn.l;
                     b.fallback = sn.fallback;
                     b.umax = 0.0;
+                    b.gamma = sn.gamma;
+                    b.sigma_bound = sn.sigma_bound;
                     log[nrec] = b;
                 }
                 ++nrec;

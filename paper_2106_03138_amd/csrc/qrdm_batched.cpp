@@ -71,6 +71,7 @@ hipError_t enqueue(qrdm_batch_plan *pl, double *const *A, double *const *tau_hou
         q.kmax = pl->p.kmax;
         q.stop_rule = pl->p.stop_rule;
         q.eps1_scale = pl->p.eps1_scale;
+        q.certified = pl->p.certified;
         hipError_t e = launch_qrdm_batched(q, pl->tune[c].variant, pl->grid[c], s);
         if (e != hipSuccess) return e;
     }
@@ -89,7 +90,8 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
     if (batch > 0 && (!m || !n || !lda)) return -1;
     if (!p) return -5;
     if (!(p->tau > 0.0 && p->tau <= 1.0) || !(p->delta >= 0.0 && p->delta <= 1.0) || p->kmax < 1 ||
-        p->stop_rule < 0 || p->stop_rule > 2 || p->precision != QRDM_PREC_FP64)
+        p->stop_rule < 0 || p->stop_rule > 2 || p->precision != QRDM_PREC_FP64 || p->certified < 0 ||
+        p->certified > 1)
         return -5;
     if (p->kmax > QRDM_BATCH_KMAX) return QRDM_ERR_UNSUPPORTED;
     if (tune) {

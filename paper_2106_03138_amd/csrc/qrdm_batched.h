@@ -25,6 +25,7 @@ struct QbArgs {
     double tau, delta;
     int32_t kmax, stop_rule;
     double eps1_scale;
+    int32_t certified;  // delta <= tau^2 / (nL - 1) per step (eq. delta_max)
 };
 
 // variant: 0 = 256 threads, 16 columns per wavefront in the trailing update,

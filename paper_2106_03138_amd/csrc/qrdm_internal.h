@@ -18,6 +18,8 @@ struct QrdmCtl {
     int32_t done;    // 1 = no further step
     int32_t fallback;  // current step uses scalar pivoting
     int32_t jmax;
+    double gamma;        // Lemma 1 on the current step's accepted columns: diagonal-dominance gap
+    double sigma_bound;  // and the lower bound of their sigma_min (0 if the lemma does not apply)
     int32_t nswap;     // column moves of the current step
     int32_t nonfinite; // set by the norm sweep
     int32_t error;     // bit 1: a grid barrier timed out
@@ -57,6 +59,7 @@ struct QrdmArgs {
     double tau, delta;
     int32_t kmax;
     int32_t stop_rule;
+    int32_t certified = 0;  // delta <= tau^2 / (nL - 1) per step (eq. delta_max)
     double eps1;    // eps_1 * (applied as eps1 * amax) of the stopping test
     double fbeps;   // eps_w * n: scalar pivoting when max partial norm <= fbeps * amax
     double tol3z;   // sqrt(eps_w): recompute a partial norm when the downdate lost this much

@@ -31,6 +31,8 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(qrdm_params, eps1_scale), offsetof(qrdm_params, profile),
          offsetof(qrdm_stats, total_ms));
   printf("%zu %zu\n", offsetof(qrdm_block, fallback), offsetof(qrdm_block, umax));
+  printf("%zu %zu %zu\n", offsetof(qrdm_params, certified), offsetof(qrdm_block, gamma),
+         offsetof(qrdm_block, sigma_bound));
   printf("%zu %zu %zu\n", sizeof(qrdm_batch_params), offsetof(qrdm_batch_params, kmax), sizeof(qrdm_batch_tune));
   return 0;
 }
@@ -49,7 +51,8 @@ def lib():
 def test_header_declares_the_expected_entry_points():
     names = _declared_functions()
     for want in ["qrdm_factor", "qrdm_factor_ex", "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
-                 "qrdm_dm_step", "qrdm_default_params", "qrdm_release", "qrdm_strerror"]:
+                 "qrdm_dm_step", "qrdm_default_params", "qrdm_release", "qrdm_strerror", "qrdm_lstsq",
+                 "qrdm_batch_lstsq", "qrdm_truncate_rank", "qrdm_batch_truncate_rank"]:
         assert want in names, names
 
 
@@ -74,6 +77,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     want = [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.Stats), ctypes.sizeof(_lib.Block),
             _lib.Params.eps1_scale.offset, _lib.Params.profile.offset, _lib.Stats.total_ms.offset,
             _lib.Block.fallback.offset, _lib.Block.umax.offset,
+            _lib.Params.certified.offset, _lib.Block.gamma.offset, _lib.Block.sigma_bound.offset,
             ctypes.sizeof(_lib.BatchParams), _lib.BatchParams.kmax.offset, ctypes.sizeof(_lib.BatchTune)]
     assert got == want
 
@@ -83,7 +87,7 @@ def test_defaults_and_error_strings_without_a_device(lib):
     lib.qrdm_default_params.argtypes = [ctypes.POINTER(_lib.Params)]
     p = _lib.Params()
     lib.qrdm_default_params(ctypes.byref(p))
-    assert (p.tau, p.delta, p.kmax, p.stop_rule, p.precision) == (0.15, 0.9, 64, 0, 0)
+    assert (p.tau, p.delta, p.kmax, p.stop_rule, p.precision, p.certified) == (0.15, 0.9, 64, 0, 0, 0)
     lib.qrdm_strerror.restype = ctypes.c_char_p
     lib.qrdm_strerror.argtypes = [ctypes.c_int]
     for code in (0, 1, 2, 3, -1, 1001):
@@ -138,3 +142,22 @@ def test_batched_plan_rejects_bad_arguments_on_the_host(lib):
     tune = (_lib.BatchTune * 4)(*[_lib.BatchTune(9, 0)] * 4)
     assert f(arr(8), arr(4), arr(8), 1, ctypes.byref(p), tune, ctypes.byref(plan)) == -6
     assert not plan.value
+
+
+def test_lstsq_and_truncation_reject_bad_arguments_on_the_host(lib):
+    from paper_2106_03138_amd import _lib
+    f = lib.qrdm_lstsq
+    f.restype, f.argtypes = _lib.SIGNATURES["qrdm_lstsq"]
+    d = ctypes.c_void_p(16)
+    assert f(d, -1, 4, 4, d, d, 2, d, 4, 1, d, 4, None, None) == -2
+    assert f(d, 8, 4, 4, d, d, 2, d, 8, 1, d, 4, None, None) == -4
+    assert f(d, 8, 4, 8, d, d, 2, d, 4, 1, d, 4, None, None) == -9
+    assert f(d, 8, 4, 8, d, d, 2, d, 8, -1, d, 4, None, None) == -10
+    assert f(d, 8, 4, 8, d, d, 2, d, 8, 1, d, 2, None, None) == -12
+    assert f(d, 8, 4, 8, d, d, 2, None, 8, 1, d, 4, None, None) == -8
+    assert f(d, 8, 4, 8, d, d, 2, d, 8, 0, d, 4, None, None) == 0  # nothing to solve
+    t = lib.qrdm_truncate_rank
+    t.restype, t.argtypes = _lib.SIGNATURES["qrdm_truncate_rank"]
+    assert t(d, 8, 4, 4, 2, 0.0, d, None) == -4
+    assert t(d, 8, 4, 8, 2, 0.0, None, None) == -7
+    assert t(d, 8, 4, 8, 2, float("nan"), d, None) == -6
