@@ -59,7 +59,8 @@ extern "C" {
 #define QRDM_KMAX_LIMIT 128 /* largest supported block size k_DM                          */
 
 typedef struct {
-    double tau;         /* candidate threshold, Algorithm 1; 0 < tau <= 1 (default 0.15)  */
+    double tau;         /* candidate threshold, Algorithm 1; 0 <= tau <= 1 (default 0.15);
+                           tau = 0 admits every column and disables the panel break    */
     double delta;       /* cosine bound, Algorithm 1; 0 <= delta <= 1 (default 0.9)      */
     int32_t kmax;       /* block size k_DM, eq. (candidate_set_limited_by_kDM); 1..128 (64) */
     int32_t stop_rule;  /* QRDM_STOP_* (default QRDM_STOP_PAPER)                          */

@@ -288,7 +288,8 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
     if (n < 0) return -3;
     if (lda < (m > 1 ? m : 1)) return -4;
     if (!prm) return -5;
-    if (!(prm->tau > 0.0 && prm->tau <= 1.0)) return -5;
+    /* tau = 0 (a corner of the grid study of Section 5) admits every column */
+    if (!(prm->tau >= 0.0 && prm->tau <= 1.0)) return -5;
     if (!(prm->delta >= 0.0 && prm->delta <= 1.0)) return -5;
     if (prm->kmax < 1) return -5;
     if (prm->stop_rule < 0 || prm->stop_rule > 2) return -5;

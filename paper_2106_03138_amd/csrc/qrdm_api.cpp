@@ -145,7 +145,7 @@ int check_common(const double *A, int64_t m, int64_t n, int64_t lda, const qrdm_
     if (n < 0) return -3;
     if (lda < std::max<int64_t>(1, m)) return -4;
     if (p) {
-        if (!(p->tau > 0.0 && p->tau <= 1.0)) return -5;
+        if (!(p->tau >= 0.0 && p->tau <= 1.0)) return -5;
         if (!(p->delta >= 0.0 && p->delta <= 1.0)) return -5;
         if (p->kmax < 1 || p->kmax > QRDM_KMAX_LIMIT) return -5;
         if (p->stop_rule < 0 || p->stop_rule > 2) return -5;

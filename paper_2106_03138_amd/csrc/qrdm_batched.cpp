@@ -89,7 +89,7 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
     if (batch < 0) return -4;
     if (batch > 0 && (!m || !n || !lda)) return -1;
     if (!p) return -5;
-    if (!(p->tau > 0.0 && p->tau <= 1.0) || !(p->delta >= 0.0 && p->delta <= 1.0) || p->kmax < 1 ||
+    if (!(p->tau >= 0.0 && p->tau <= 1.0) || !(p->delta >= 0.0 && p->delta <= 1.0) || p->kmax < 1 ||
         p->stop_rule < 0 || p->stop_rule > 2 || p->precision != QRDM_PREC_FP64 || p->certified < 0 ||
         p->certified > 1)
         return -5;

@@ -136,7 +136,7 @@ def test_degenerate():
     r1 = Q.device_matrix(I.rank1(64, 20, 1))
     assert Q.qrdm_factor(r1).rank == 1
     with pytest.raises(Q.QrdmError) as ei:
-        Q.qrdm_factor(Q.device_matrix(I.gaussian(8, 8, 0)), tau=0.0)
+        Q.qrdm_factor(Q.device_matrix(I.gaussian(8, 8, 0)), tau=-0.1)
     assert ei.value.code == -5
 
 

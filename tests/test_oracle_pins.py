@@ -361,7 +361,7 @@ def test_degenerate_inputs():
 
 def test_invalid_arguments():
     a = I.gaussian(5, 5, 0)
-    assert oracle.qrdm(a, tau=0.0).code == -5
+    assert oracle.qrdm(a, tau=-0.1).code == -5
     assert oracle.qrdm(a, tau=1.5).code == -5
     assert oracle.qrdm(a, delta=-0.1).code == -5
     assert oracle.qrdm(a, kmax=0).code == -5
