@@ -78,7 +78,7 @@ Layout make_layout(int64_t m, int64_t n) {
     L.g = take(sizeof(double) * QK_KM * QK_KM);
     L.theta = take(sizeof(double) * QK_KM * QK_KM);
     const int64_t pmax = (mm + kMinRowsPerWg - 1) / kMinRowsPerWg;
-    L.pb = take(sizeof(double) * 2 * (size_t)pmax * 2 * QK_KM);
+    L.pb = take(sizeof(double) * 2 * (size_t)pmax * 4 * QK_KM);
     L.tm = take(sizeof(double) * QK_KM * QK_KM);
     L.vw = take(sizeof(double) * (size_t)QK_KM * mm);
     L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
