@@ -26,6 +26,7 @@
 
 #define PN_THREADS 512
 #define PN_RB 4  // slab rows whose LDS loads are issued together in the row loops
+#define PN_FLAGS 4096  // arrival flags (one per workgroup) at the head of the partials buffer
 #define PN_WAVES (PN_THREADS / 64)
 #define PN_SPIN_LIMIT (1 << 26)
 
@@ -41,6 +42,26 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, int
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int it = 0;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++it > PN_SPIN_LIMIT) {
+                atomicOr(err, 2);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Flag barrier: every workgroup raises its own arrival flag (no single
+// contended counter) and polls the others' flags, one thread per workgroup.
+// Flags carry a launch epoch, so they are never reset within a factorization.
+__device__ __forceinline__ void flag_barrier(uint32_t *flags, int P, int wg, uint32_t target, int32_t *err) {
+    __builtin_amdgcn_s_waitcnt(0);  // every wave's published stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + wg, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)threadIdx.x < P) {
+        int it = 0;
+        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++it > PN_SPIN_LIMIT) {
                 atomicOr(err, 2);
@@ -149,6 +170,12 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks;
     const double eps_s = ctl->eps_s;
+    // PB: [PN_FLAGS] arrival flags | [2][2 QK_KM] rows c, c+1 of the round |
+    // [2][P][2 QK_KM] partial dots (double-buffered by round parity)
+    uint32_t *flags = (uint32_t *)PB;
+    double *topb = PB + PN_FLAGS / 2;
+    double *part = topb + 4 * QK_KM;
+    const uint32_t epoch = (uint32_t)ctl->npanel * 1024u;  // rounds per panel <= QK_KM < 1024
     const int64_t t = a.m - ns;
     const int P = gridDim.x;
     const int wg = blockIdx.x;
@@ -207,8 +234,7 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
     uint32_t round = 0;
     for (int i = 0; i < ks;) {
         const bool pair = i + 1 < ks;
-        const int nseg = pair ? 4 : 2;
-        const int nval = nseg * ks;
+        const int nval = (pair ? 2 : 1) * ks;  // reduced values: Dall (and Dall2)
         int gpv = PN_THREADS / nval;  // thread groups per reduced value
         if (gpv > PN_WAVES / 2) gpv = PN_WAVES / 2;
         if (gpv < 1) gpv = 1;
@@ -230,26 +256,22 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
             red2[wv * QK_KM + jj] = s2;
         }
         __syncthreads();
-        double *pb = PB + ((size_t)(round & 1) * P + wg) * (4 * QK_KM);
+        double *pb = part + ((size_t)(round & 1) * P + wg) * (2 * QK_KM);
+        double *tb = topb + (size_t)(round & 1) * (2 * QK_KM);
         if (tid < nval) {
             const int seg = tid / ks, jj = tid - seg * ks;
+            const double *rr = seg == 0 ? red : red2;
             double v = 0.0;
-            if (seg == 0) {
 #pragma unroll
-                for (int w = 0; w < PN_WAVES; ++w) v += red[w * QK_KM + jj];
-            } else if (seg == 1) {
-                v = (cl >= 0) ? S[cl * ksp + jj] : 0.0;
-            } else if (seg == 2) {
-#pragma unroll
-                for (int w = 0; w < PN_WAVES; ++w) v += red2[w * QK_KM + jj];
-            } else {
-                v = (cl2 >= 0) ? S[cl2 * ksp + jj] : 0.0;
-            }
+            for (int w = 0; w < PN_WAVES; ++w) v += rr[w * QK_KM + jj];
             st_coherent(pb + seg * QK_KM + jj, v);
         }
-        grid_barrier(&ctl->bar, (uint32_t)P * (round + 1), &ctl->error);
+        // rows c and c+1 come from the one workgroup that holds each
+        if (cl >= 0 && tid < ks) st_coherent(tb + tid, S[cl * ksp + tid]);
+        if (pair && cl2 >= 0 && tid < ks) st_coherent(tb + QK_KM + tid, S[cl2 * ksp + tid]);
+        flag_barrier(flags, P, wg, epoch + round + 1, &ctl->error);
         // ---- fixed-order reduction of all partials (every workgroup, identically)
-        const double *pb0 = PB + (size_t)(round & 1) * P * (4 * QK_KM);
+        const double *pb0 = part + (size_t)(round & 1) * P * (2 * QK_KM);
         {
             const int my_e = tid % nval, my_g = tid / nval;
             const int wper = (P + gpv - 1) / gpv;
@@ -263,11 +285,15 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
                     double v[16];
 #pragma unroll
                     for (int u = 0; u < 16; ++u)
-                        v[u] = (wb + u < w1) ? ld_coherent(pb0 + (size_t)(wb + u) * (4 * QK_KM) + o) : 0.0;
+                        v[u] = (wb + u < w1) ? ld_coherent(pb0 + (size_t)(wb + u) * (2 * QK_KM) + o) : 0.0;
 #pragma unroll
                     for (int u = 0; u < 16; ++u) s += v[u];
                 }
                 red[my_g * nval + my_e] = s;
+            }
+            if (tid < ks) {
+                sTop[tid] = ld_coherent(tb + tid);
+                if (pair) sTop2[tid] = ld_coherent(tb + QK_KM + tid);
             }
         }
         __syncthreads();
@@ -275,7 +301,7 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
             double s = 0.0;
             for (int g = 0; g < gpv; ++g) s += red[g * nval + tid];
             const int seg = tid / ks, jj = tid - seg * ks;
-            (seg == 0 ? sR : seg == 1 ? sTop : seg == 2 ? sG2 : sTop2)[jj] = s;
+            (seg == 0 ? sR : sG2)[jj] = s;
         }
         __syncthreads();
         const double alpha = sTop[i];
@@ -454,6 +480,7 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *V
     if (t_bound <= 0) return hipSuccess;
     int P = (int)((t_bound + rows_per_wg - 1) / rows_per_wg);
     if (P < 1) P = 1;
+    if (P > PN_THREADS || P > PN_FLAGS) return hipErrorInvalidValue;  // one polling thread per workgroup
     const int kk = a.kmax < QK_KM ? a.kmax : QK_KM;
     const int lds = panel_lds_bytes(rows_per_wg, kk);
     static bool attr_set = false;

@@ -78,7 +78,8 @@ Layout make_layout(int64_t m, int64_t n) {
     L.g = take(sizeof(double) * QK_KM * QK_KM);
     L.theta = take(sizeof(double) * QK_KM * QK_KM);
     const int64_t pmax = (mm + kMinRowsPerWg - 1) / kMinRowsPerWg;
-    L.pb = take(sizeof(double) * 2 * (size_t)pmax * 4 * QK_KM);
+    // panel: 4096 arrival flags (16 KB), rows c and c+1 (2 x 2 QK_KM), partial dots (2 x pmax x 2 QK_KM)
+    L.pb = take(16384 + sizeof(double) * (4 * QK_KM + 2 * (size_t)pmax * 2 * QK_KM));
     L.tm = take(sizeof(double) * QK_KM * QK_KM);
     L.vw = take(sizeof(double) * (size_t)QK_KM * mm);
     L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
@@ -332,6 +333,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     const int rows_per_wg = panel_rows_per_wg(std::min<int>(p.kmax, QK_KM));
     bool switch_qp3 = false;
     HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
+    HIP_TRY(hipMemsetAsync(ws + L.pb, 0, 16384, s));  // panel arrival flags (epochs restart with the loop state)
     int64_t ns_known = 0;
     int64_t nrec = 0;
     int64_t iter = 0;
