@@ -7,8 +7,9 @@
 //     Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b),   Y = V^T A_tr,
 // (Z_a = 0 when tau_a = 0, the identity reflector), with v_b^T v_a recorded by
 // the panel.  Two kernels on gfx950 MFMA:
-//   k_gemm1  Y = V^T A_tr, split over rows; the last workgroup of each
-//            256-column tile sums the partials and runs the recurrence -> Z;
+//   k_gemm1  Y = V^T A_tr, split over rows, partial products published;
+//   k_zsum   per 64 trailing columns: Y = sum of the partials in split order,
+//            then the recurrence -> Z;
 //   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once.
 // Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode runs both products
 // on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and the
@@ -54,7 +55,10 @@ template <> struct Mfma<float> {
 #define G1_CPP (G1_TH / G1_KC)          // columns staged per pass (one thread per row of a column)
 #define G1_AU (G1_NT / G1_CPP)          // staged A elements per thread per step
 #define G1_VU (64 / G1_CPP)             // staged V elements per thread per step
-#define G1_LD (G1_KC + 1)
+#ifndef G1_PAD
+#define G1_PAD 1    // LDS row padding of the staged tiles (doubles)
+#endif
+#define G1_LD (G1_KC + G1_PAD)
 
 __device__ __forceinline__ void st_coh(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -65,13 +69,10 @@ __device__ __forceinline__ double ld_coh(const double *p) {
 
 // Split-K: workgroup (x, y, z) forms rows [64z, 64z+64) of the partial
 // Y_y = V^T A_tr over rows [y*krows, (y+1)*krows) of A_tr, for trailing columns
-// [256x, 256x+256), and publishes it with agent-coherent stores.  The last
-// workgroup of a column tile to arrive (tile counter) sums the partials in
-// split order and runs the recurrence for Z, 64 columns at a time.
+// [256x, 256x+256), and writes it to Yp[y] (k_zsum, the next launch, sums them).
 template <typename T>
 __global__ void __launch_bounds__(G1_TH)
-k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restrict__ VV, double *Yp,
-        uint32_t *tile_cnt, T *__restrict__ Z, int64_t ldz, int krows) {
+k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ldz, int krows) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
@@ -95,7 +96,6 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
     extern __shared__ double g1_lds[];
     T *Vs = reinterpret_cast<T *>(g1_lds);  // [64][G1_LD]
     T *As = Vs + 64 * G1_LD;                // [G1_NT][G1_LD]
-    __shared__ int s_last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     typedef typename Mfma<T>::acc_t acc_t;
     acc_t acc[4 * G1_CT];  // 4 row tiles x G1_CT column tiles
@@ -147,7 +147,7 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
             }
         }
     }
-    // publish the partial: Yp[sp][q0 + row][jb + col] (double, agent-coherent)
+    // the partial: Yp[sp][q0 + row][jb + col] (double)
     double *yp = Yp + ((int64_t)sp * QK_KM + q0) * ldz;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
@@ -158,71 +158,100 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const double *__restri
                 if (col < w2) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        st_coh(yp + (ti * 16 + Mfma<T>::row(lane, v)) * ldz + col, (double)acc[ti * G1_CT + c][v]);
+                        yp[(ti * 16 + Mfma<T>::row(lane, v)) * ldz + col] = (double)acc[ti * G1_CT + c][v];
                 }
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores have completed
-    __syncthreads();
-    if (tid == 0) {
-        const uint32_t arrivals = (uint32_t)(nsplit * nz);
-        const uint32_t old = __hip_atomic_fetch_add(tile_cnt + blockIdx.x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (old == arrivals - 1);
-        if (s_last) __hip_atomic_store(tile_cnt + blockIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+#define ZS_LDY 72  // row stride of the staged Y: the 8 lanes of a column group and the 8
+                   // column groups of a wavefront fall on distinct LDS banks
+
+// One step of the recurrence for the column of lanes g = 0..7: the products
+// (v_b^T v_aa) Z_b, b = g, g + 8, ... < aa, loaded together, summed in increasing b.
+template <int NU>
+__device__ __forceinline__ double zs_step(const double *vc, const double *Ys, int aa, int g, int jl) {
+    double x[NU], y[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int b = g + 8 * u;
+        const bool in = b < aa;
+        x[u] = in ? vc[b] : 0.0;
+        y[u] = in ? Ys[b * ZS_LDY + jl] : 0.0;
     }
-    __syncthreads();
-    if (!s_last) return;
-    // ---- last workgroup of this tile: Y = sum of partials in split order, then
-    // the recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column
-    const int lp = lt * 16;
-    double *Ys = g1_lds;                           // [lp][64]
-    double *VVs = Ys + lp * 64;                    // packed strict upper triangle
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+        if (g + 8 * u < aa) part += x[u] * y[u];
+    return part;
+}
+
+// Z for 64 trailing columns per workgroup: Y = the k_gemm1 partials summed in
+// split order, then the recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b)
+// per column (Z_a = 0 when tau_a = 0).
+template <typename T>
+__global__ void __launch_bounds__(G1_TH)
+k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz,
+       int krows) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int64_t ns = ctl->ns;
+    const int ks = ctl->ks, l = ctl->l;
+    const int64_t t = a.m - ns;
+    const int64_t w2 = a.n - (ns + ks);
+    const int64_t cb = (int64_t)blockIdx.x * 64;
+    if (l <= 0 || cb >= w2 || t <= 0) return;
+    const int nsplit = (int)((t + krows - 1) / krows);
+    const int ncols = (int)((w2 - cb) < 64 ? (w2 - cb) : 64);
+    const int tid = threadIdx.x;
+    const int lp = ((l + 15) >> 4) * 16;
+    extern __shared__ double zs_lds[];
+    double *Ys = zs_lds;                           // [lp][ZS_LDY]
+    double *VVs = Ys + lp * ZS_LDY;                // packed strict upper triangle
     double *taus = VVs + (lp * (lp - 1)) / 2 + 1;  // [lp]
     for (int e = tid; e < l * l; e += G1_TH) {
         const int b = e / l, aa = e - b * l;
         if (b < aa) VVs[aa * (aa - 1) / 2 + b] = VV[b * QK_KM + aa];
     }
     for (int e = tid; e < l; e += G1_TH) taus[e] = a.tau_house[ns + e];
-    const int jl = tid >> 3, g = tid & 7;  // 8 lanes of one wavefront per column
-    for (int cb = 0; cb < ncols; cb += 64) {
-        __syncthreads();
-        // every split's partial of an element is loaded before any is summed
-        // (QK_SPLIT_MAX loads in flight per element), then summed in split order
-        for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 2) {
+    // every split's partial of an element is loaded before any is summed
+    // (QK_SPLIT_MAX loads in flight per element), then summed in split order
+    for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 2) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = e0 + u * G1_TH + tid;
-                const int aa = e >> 6, j = e & 63;
-                const bool ok = e < l * 64 && cb + j < ncols;
-                double v[QK_SPLIT_MAX];
-#pragma unroll
-                for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2)
-                    v[s2] = (ok && s2 < nsplit) ? ld_coh(Yp + ((int64_t)s2 * QK_KM + aa) * ldz + jb + cb + j) : 0.0;
-                double sum = 0.0;
-#pragma unroll
-                for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
-                if (e < l * 64) Ys[e] = sum;
-            }
-        }
-        __syncthreads();
-        for (int aa = 0; aa < l; ++aa) {
-            const double *vc = VVs + aa * (aa - 1) / 2;
-            double part = 0.0;
-            for (int b = g; b < aa; b += 8) part += vc[b] * Ys[b * 64 + jl];
-            part += __shfl_xor(part, 1, 64);
-            part += __shfl_xor(part, 2, 64);
-            part += __shfl_xor(part, 4, 64);
-            if (g == 0) {
-                const double ta = taus[aa];
-                Ys[aa * 64 + jl] = (ta == 0.0) ? 0.0 : ta * (Ys[aa * 64 + jl] - part);
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < l * 64; e += G1_TH) {
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * G1_TH + tid;
             const int aa = e >> 6, j = e & 63;
-            if (cb + j < ncols) Z[(int64_t)aa * ldz + jb + cb + j] = (T)Ys[e];
+            const bool ok = e < l * 64 && j < ncols;
+            double v[QK_SPLIT_MAX];
+#pragma unroll
+            for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2)
+                v[s2] = (ok && s2 < nsplit) ? Yp[((int64_t)s2 * QK_KM + aa) * ldz + cb + j] : 0.0;
+            double sum = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
+            if (e < l * 64) Ys[aa * ZS_LDY + j] = sum;
         }
+    }
+    __syncthreads();
+    // 8 lanes of one wavefront per column; the products of a step are loaded
+    // together and summed in increasing b
+    const int jl = tid >> 3, g = tid & 7;
+    for (int aa = 0; aa < l; ++aa) {
+        const double *vc = VVs + aa * (aa - 1) / 2;
+        double part = l <= 64 ? zs_step<8>(vc, Ys, aa, g, jl) : zs_step<QK_KM / 8>(vc, Ys, aa, g, jl);
+        part += __shfl_xor(part, 1, 64);
+        part += __shfl_xor(part, 2, 64);
+        part += __shfl_xor(part, 4, 64);
+        if (g == 0) {
+            const double ta = taus[aa];
+            Ys[aa * ZS_LDY + jl] = (ta == 0.0) ? 0.0 : ta * (Ys[aa * ZS_LDY + jl] - part);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < l * 64; e += G1_TH) {
+        const int aa = e >> 6, j = e & 63;
+        if (j < ncols) Z[(int64_t)aa * ldz + cb + j] = (T)Ys[aa * ZS_LDY + j];
     }
 }
 
@@ -358,8 +387,8 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
 }
 
 hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Z, double *Yp, uint32_t *tile_cnt, int64_t t_bound, int64_t w_bound,
-                        hipStream_t s, hipEvent_t *ev) {
+                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, hipStream_t s,
+                        hipEvent_t *ev) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     const int64_t ldz = a.n;
     const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
@@ -376,21 +405,28 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const int kp = ((a.kmax < QK_KM ? a.kmax : QK_KM) + 15) & ~15;
     const size_t tsz = precision == 0 ? sizeof(double) : sizeof(float);
     const size_t main_b = (size_t)(64 + G1_NT) * G1_LD * tsz;
-    const size_t epi_b = ((size_t)kp * 64 + (size_t)kp * (kp - 1) / 2 + 1 + kp) * sizeof(double);
-    const size_t lds = main_b > epi_b ? main_b : epi_b;
+    const size_t epi_b = ((size_t)kp * ZS_LDY + (size_t)kp * (kp - 1) / 2 + 1 + kp) * sizeof(double);
     static bool attr = false;
     if (!attr) {
-        hipError_t e1 = hipFuncSetAttribute((const void *)k_gemm1<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        hipError_t e2 = hipFuncSetAttribute((const void *)k_gemm1<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-        if (e1 != hipSuccess) return e1;
-        if (e2 != hipSuccess) return e2;
+        const void *fs[4] = {(const void *)k_gemm1<double>, (const void *)k_gemm1<float>, (const void *)k_zsum<double>,
+                             (const void *)k_zsum<float>};
+        for (const void *f : fs) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+            if (e != hipSuccess) return e;
+        }
         attr = true;
     }
+    const dim3 gz((unsigned)((w_bound + 63) / 64));
     if (ev) (void)hipEventRecord(ev[0], s);
-    if (precision == 0)
-        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), lds, s, a, Vw, ldv, VV, Yp, tile_cnt, (double *)Z, ldz, krows);
-    else
-        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), lds, s, a, Vw32, ldv, VV, Yp, tile_cnt, (float *)Z, ldz, krows);
+    if (precision == 0) {
+        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz, krows);
+        hipLaunchKernelGGL(k_zsum<double>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz,
+                           krows);
+    } else {
+        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz, krows);
+        hipLaunchKernelGGL(k_zsum<float>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz,
+                           krows);
+    }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);
     if (precision == 0)

@@ -59,7 +59,7 @@ int prof_events(size_t count) {
 }
 
 struct Layout {
-    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, tcnt, pb2, fz, flag, perm_dbg, total;
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, perm_dbg, total;
 };
 
 const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
@@ -85,7 +85,6 @@ Layout make_layout(int64_t m, int64_t n) {
     L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
     L.z = take(sizeof(double) * (size_t)QK_KM * nn);
     L.yp = take(sizeof(double) * 16 * (size_t)QK_KM * nn);
-    L.tcnt = take(sizeof(uint32_t) * (size_t)((nn + 63) / 64 + 1));  // one counter per column tile (tiles >= 64 columns)
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
     L.fz = take(sizeof(double) * 64 * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
@@ -318,7 +317,6 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
     // the GEMM tile counters self-reset, but their place in the cached workspace
     // depends on (m, n): clear them for this call
-    HIP_TRY(hipMemsetAsync(ws + L.tcnt, 0, sizeof(uint32_t) * (size_t)((n + 63) / 64 + 1), s));
     HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
     int32_t nf = 0;
     HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
@@ -360,8 +358,8 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
         if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), (uint32_t *)(ws + L.tcnt),
-                             tb, wb, s, ev ? ev + 3 : nullptr));
+        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, s,
+                             ev ? ev + 3 : nullptr));
         HIP_TRY(launch_downdate(a, wb, s));
         if (ev) HIP_TRY(hipEventRecord(ev[7], s));
         Snapshot *hs = g_ws.host_snap + (iter % ring);
