@@ -187,9 +187,85 @@ __device__ __forceinline__ double zs_step(const double *vc, const double *Ys, in
     return part;
 }
 
+#define ZT_LD 80  // row stride of T, V^T V and Y on the explicit-T path: the four K
+                  // rows of an MFMA operand fall on distinct LDS bank halves
+
+// Z = T^T Y for l <= 64 reflectors with the forward triangular factor T of
+// H_0 ... H_{l-1} = I - V T V^T (Section 3.2), formed blockwise: 16 x 16
+// diagonal blocks by the column recurrence T_{r,i} = -tau_i sum_{r<=b<i} T_{r,b}
+// (v_b^T v_i), T_ii = tau_i (one lane per row), then
+// T_12 = -T_11 (V_1^T V_2) T_22 for 16- and 32-column halves.  Reflectors
+// a >= l have tau = 0 and vanish.  Z on FP64 MFMA (16x16x4): A = T^T, B = Y.
+__device__ __forceinline__ void zs_tmat(const double *VVf, double *Tm, double *Mt, const double *taus) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // diagonal blocks: wavefront w < 4 forms rows/columns [16w, 16w + 16)
+    if (wv < 4 && lane < 16) {
+        const int base = 16 * wv, r = lane;
+        double *trow = Tm + (base + r) * ZT_LD + base;
+        for (int i = 0; i < 16; ++i) {
+            const int ia = base + i;
+            if (r < i) {
+                double x = 0.0;
+                for (int b = 0; b < 16; ++b)
+                    if (b >= r && b < i) x += trow[b] * VVf[(base + b) * ZT_LD + ia];
+                trow[i] = -taus[ia] * x;
+            } else if (r == i) {
+                trow[i] = taus[ia];
+            }
+        }
+    }
+    __syncthreads();
+    for (int sh = 16; sh < 64; sh *= 2) {
+        // pairs (r1, r2) = ([2 sh p, 2 sh p + sh), [2 sh p + sh, 2 sh (p + 1))): M = (V_1^T V_2) T_22
+        const int np = 64 / (2 * sh), nout = np * sh * sh;
+        for (int e = tid; e < nout; e += G1_TH) {
+            const int p = e / (sh * sh), x = (e / sh) % sh, y = e % sh;
+            const int r1 = 2 * sh * p, r2 = r1 + sh;
+            double m = 0.0;
+            for (int z = 0; z < sh; ++z)
+                if (z <= y) m += VVf[(r1 + x) * ZT_LD + r2 + z] * Tm[(r2 + z) * ZT_LD + r2 + y];
+            Mt[(r1 + x) * ZT_LD + r2 + y] = m;
+        }
+        __syncthreads();
+        // T_12 = -T_11 M
+        for (int e = tid; e < nout; e += G1_TH) {
+            const int p = e / (sh * sh), x = (e / sh) % sh, y = e % sh;
+            const int r1 = 2 * sh * p, r2 = r1 + sh;
+            double v = 0.0;
+            for (int z = 0; z < sh; ++z)
+                if (z >= x) v += Tm[(r1 + x) * ZT_LD + r1 + z] * Mt[(r1 + z) * ZT_LD + r2 + y];
+            Tm[(r1 + x) * ZT_LD + r2 + y] = -v;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int l, int ncols, T *__restrict__ Z,
+                                         int64_t ldz, int64_t cb) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // Z = T^T Y: wavefront w takes output tiles 2w and 2w + 1 of the 4 x 4 grid
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int q = 2 * wv + h, ta = q >> 2, tj = q & 3;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        const int i = lane & 15, k = lane >> 4;
+        for (int kb = 0; kb < 16 * ta + 16; kb += 4) {  // T_{b,a} = 0 for b > a
+            const double av = Tm[(kb + k) * ZT_LD + 16 * ta + i];
+            const double bv = Ys[(kb + k) * ZT_LD + 16 * tj + i];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int aa = 16 * ta + 4 * v + k, j = 16 * tj + i;
+            if (aa < l && j < ncols) Z[(int64_t)aa * ldz + cb + j] = (T)acc[v];
+        }
+    }
+}
+
 // Z for 64 trailing columns per workgroup: Y = the k_gemm1 partials summed in
-// split order, then the recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b)
-// per column (Z_a = 0 when tau_a = 0).
+// split order, then Z = T^T Y (l <= 64, explicit T) or the recurrence
+// Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
 template <typename T>
 __global__ void __launch_bounds__(G1_TH)
 k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz,
@@ -206,15 +282,32 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
     const int ncols = (int)((w2 - cb) < 64 ? (w2 - cb) : 64);
     const int tid = threadIdx.x;
     const int lp = ((l + 15) >> 4) * 16;
+    const bool xt = l <= 64;  // explicit-T path
+    const int ldy = xt ? ZT_LD : ZS_LDY;
     extern __shared__ double zs_lds[];
-    double *Ys = zs_lds;                           // [lp][ZS_LDY]
-    double *VVs = Ys + lp * ZS_LDY;                // packed strict upper triangle
+    double *Ys = zs_lds;                           // [lp][ldy]
+    double *VVs = Ys + lp * ldy;                   // recurrence: packed strict upper triangle
     double *taus = VVs + (lp * (lp - 1)) / 2 + 1;  // [lp]
-    for (int e = tid; e < l * l; e += G1_TH) {
-        const int b = e / l, aa = e - b * l;
-        if (b < aa) VVs[aa * (aa - 1) / 2 + b] = VV[b * QK_KM + aa];
+    double *VVf = Ys + 64 * ZT_LD;                 // explicit T: [64][ZT_LD] v_b^T v_a (b < a)
+    double *Tm = VVf + 64 * ZT_LD;                 // [64][ZT_LD]
+    double *taux = Tm + 64 * ZT_LD;                // [64]
+    if (xt) {
+        for (int e = tid; e < 64 * ZT_LD; e += G1_TH) {
+            const int b = e / ZT_LD, aa = e - b * ZT_LD;
+            VVf[e] = (b < aa && aa < l) ? VV[b * QK_KM + aa] : 0.0;
+            Tm[e] = 0.0;
+        }
+        for (int e = tid; e < 64; e += G1_TH) taux[e] = e < l ? a.tau_house[ns + e] : 0.0;
+        __syncthreads();
+        zs_tmat(VVf, Tm, Ys, taux);  // the Y area is the product's scratch until the partials are summed
+        __syncthreads();
+    } else {
+        for (int e = tid; e < l * l; e += G1_TH) {
+            const int b = e / l, aa = e - b * l;
+            if (b < aa) VVs[aa * (aa - 1) / 2 + b] = VV[b * QK_KM + aa];
+        }
+        for (int e = tid; e < l; e += G1_TH) taus[e] = a.tau_house[ns + e];
     }
-    for (int e = tid; e < l; e += G1_TH) taus[e] = a.tau_house[ns + e];
     // every split's partial of an element is loaded before any is summed
     // (QK_SPLIT_MAX loads in flight per element), then summed in split order
     for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 2) {
@@ -230,8 +323,14 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
             double sum = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
-            if (e < l * 64) Ys[aa * ZS_LDY + j] = sum;
+            if (e < l * 64) Ys[aa * ldy + j] = sum;
         }
+    }
+    if (xt) {
+        for (int e = l * 64 + tid; e < 64 * 64; e += G1_TH) Ys[(e >> 6) * ldy + (e & 63)] = 0.0;  // rows a >= l
+        __syncthreads();
+        zs_apply<T>(Ys, Tm, l, ncols, Z, ldz, cb);
+        return;
     }
     __syncthreads();
     // 8 lanes of one wavefront per column; the products of a step are loaded
@@ -405,7 +504,9 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const int kp = ((a.kmax < QK_KM ? a.kmax : QK_KM) + 15) & ~15;
     const size_t tsz = precision == 0 ? sizeof(double) : sizeof(float);
     const size_t main_b = (size_t)(64 + G1_NT) * G1_LD * tsz;
-    const size_t epi_b = ((size_t)kp * ZS_LDY + (size_t)kp * (kp - 1) / 2 + 1 + kp) * sizeof(double);
+    const size_t epi_rec = ((size_t)kp * ZS_LDY + (size_t)kp * (kp - 1) / 2 + 1 + kp) * sizeof(double);
+    const size_t epi_xt = ((size_t)3 * 64 * ZT_LD + 64) * sizeof(double);
+    const size_t epi_b = epi_rec > epi_xt ? epi_rec : epi_xt;
     static bool attr = false;
     if (!attr) {
         const void *fs[4] = {(const void *)k_gemm1<double>, (const void *)k_gemm1<float>, (const void *)k_zsum<double>,
