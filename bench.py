@@ -164,6 +164,7 @@ def batched_leg(args, torch, Q):
         seg = host[int(b.off[i]): int(b.off[i]) + m * n].reshape((m, n), order="F")
         d = np.sort(np.abs(np.diag(seg)[:nr]))[::-1]
         worst = min(worst, float(np.min(d / sig[:nr])))
+    solve = lstsq_leg(args, torch, Q, b, plan, shapes, ms)
     plan.close()
     learned = learned_leg(args, torch, Q, b, pristine, shapes, ms) if args.learned else None
     return {"metric": "batched QRDM matrices/s", "matrices": len(shapes), "ms": round(ms, 3),
@@ -175,7 +176,43 @@ def batched_leg(args, torch, Q):
             "tune": [list(t) for t in tune], "launch": "hipGraph replay",
             "quality": {"rank_equals_numerical_rank": exact, "max_rank_over": over,
                         "min_d_over_sigma": round(worst, 4)},
-            "learned": learned}
+            "lstsq": solve, "learned": learned}
+
+
+def lstsq_leg(args, torch, Q, b, plan, shapes, factor_ms):
+    """After the batched factorization: the basic least-squares solution for one
+    seeded right-hand side per matrix (qrdm_batch_lstsq) and the post-hoc rank
+    truncation (qrdm_batch_truncate_rank), each timed with HIP events (median of
+    the reps; B restored outside the timed region).  The truncated ranks are
+    compared with the numerical rank fixed by construction."""
+    rng = np.random.default_rng(args.seed + 1)
+    rhs = Q.BatchRHS(b, 1)
+    rhs.load([rng.standard_normal(m) for m, _, _ in shapes])
+    b0 = rhs.b.clone()
+    times, ttr = [], []
+    for _ in range(args.batched_reps):
+        rhs.b.copy_(b0)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        plan.lstsq(rhs)
+        e1.record()
+        tr = plan.truncate_rank()
+        e2.record()
+        e2.synchronize()
+        times.append(e0.elapsed_time(e1))
+        ttr.append(e1.elapsed_time(e2))
+    ms = float(np.median(times))
+    tr = tr.cpu().numpy()
+    exact, over = 0, 0
+    for i, (m, n, r) in enumerate(shapes):
+        sig = np.logspace(0.0, -14.0, r) if r > 1 else np.ones(1)
+        nr = int(np.sum(sig > np.finfo(np.float64).eps * n * sig[0]))
+        exact += int(tr[i] == nr)
+        over = max(over, int(tr[i]) - nr)
+    return {"nrhs": 1, "ms": round(ms, 3), "truncate_ms": round(float(np.median(ttr)), 3),
+            "factor_plus_solve_matrices_per_s": round(len(shapes) / ((factor_ms + ms) * 1e-3), 1),
+            "truncated_rank_equals_numerical_rank": exact, "truncated_max_rank_over": over,
+            "timing": "HIP events around the launch on the current stream"}
 
 
 def quality_of(b, shapes):
