@@ -69,7 +69,6 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
     __shared__ int s_cj[QK_KM];
     __shared__ int s_branch;  // 0 = stop, 1 = single pivot, 2 = DM list
     __shared__ double s_umax;
-    __shared__ int s_jmax;
 
     const int tid = threadIdx.x;
     if (ctl->done) return;
@@ -158,7 +157,6 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         }
         s_branch = branch;
         s_umax = uv;
-        s_jmax = uj;
     }
     __syncthreads();
     if (s_branch != 2) return;

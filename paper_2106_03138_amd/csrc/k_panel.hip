@@ -27,6 +27,12 @@
 #define PN_THREADS 512
 #define PN_RB 4  // slab rows whose LDS loads are issued together in the row loops
 #define PN_FLAGS 4096  // arrival flags (one per workgroup) at the head of the partials buffer
+#ifndef PN_MAX_ROWS
+#define PN_MAX_ROWS 256  // tallest slab per workgroup
+#endif
+#ifndef PN_PREF_ROWS
+#define PN_PREF_ROWS 128  // preferred slab height
+#endif
 #define PN_WAVES (PN_THREADS / 64)
 #define PN_SPIN_LIMIT (1 << 26)
 
@@ -457,22 +463,38 @@ int panel_lds_bytes(int rows_per_wg, int kmax) {
     return (rows_per_wg * (kmax + 1) + PN_LDS_FIXED) * (int)sizeof(double);
 }
 
-// Tallest slab (multiple of 16 rows, at most 256) whose LDS fits in the budget.
+// Tallest slab (multiple of 16 rows, at most PN_MAX_ROWS) whose LDS fits in the budget.
 int panel_rows_per_wg(int kmax) {
     const int budget = PN_LDS_BUDGET / (int)sizeof(double) - PN_LDS_FIXED;
     int r = budget / (kmax + 1);
-    if (r > 256) r = 256;
+    if (r > PN_MAX_ROWS) r = PN_MAX_ROWS;
     r &= ~15;
     return r < 16 ? 16 : r;
 }
 
 int panel_max_wgs(int rows_per_wg) {
     (void)rows_per_wg;
+    static int cus[64] = {0};  // per device, queried once
     int dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1;
-    return prop.multiProcessorCount;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1;
+    if (cus[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 1;
+        cus[dev] = prop.multiProcessorCount;
+    }
+    return cus[dev];
+}
+
+// Slab height for an m-row panel: PN_PREF_ROWS (shorter slabs mean less LDS work
+// per round for more partials to gather; 128 measured fastest at 8192 rows),
+// taller when that many workgroups would not all be co-resident (one per CU),
+// never above the LDS budget.
+int panel_rows_for(int64_t m, int kmax) {
+    const int cap = panel_rows_per_wg(kmax);
+    int r = PN_PREF_ROWS < cap ? PN_PREF_ROWS : cap;
+    const int ncu = panel_max_wgs(r);
+    while (r < cap && (m + r - 1) / r > ncu) r += 16;
+    return r;
 }
 
 hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv,

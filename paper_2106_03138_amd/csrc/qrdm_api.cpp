@@ -328,7 +328,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (prof_events(3) != 0) return QRDM_ERR_NOMEM;
         HIP_TRY(hipEventRecord(g_prof_ev[0], s));
     }
-    const int rows_per_wg = panel_rows_per_wg(std::min<int>(p.kmax, QK_KM));
+    const int rows_per_wg = panel_rows_for(m, std::min<int>(p.kmax, QK_KM));
     bool switch_qp3 = false;
     HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
     HIP_TRY(hipMemsetAsync(ws + L.pb, 0, 16384, s));  // panel arrival flags (epochs restart with the loop state)

@@ -111,3 +111,4 @@ hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const dou
 hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s);
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
+int panel_rows_for(int64_t m, int kmax);
