@@ -285,15 +285,19 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
     __shared__ double auxv[QP_NBMAX];
     const int nv = 2 + 2 * b;
     const int npart = (int)((a.m + QP_ROWS - 1) / QP_ROWS);
-    // fixed-order reduction of the pivot-column partials (every workgroup)
+    // fixed-order reduction of the pivot-column partials (every workgroup); the
+    // row slabs above row j hold no live row and contribute exact zeros, so the
+    // sum starts at the slab of row j, with up to 32 loads in flight
+    const int wfirst = (int)(j / QP_ROWS);
     for (int e = tid; e < nv; e += 256) {
         double acc = 0.0;
-        for (int w0 = 0; w0 < npart; w0 += 8) {
-            double v[8];
+        for (int w0 = wfirst; w0 < npart; w0 += 32) {
+            double v[32];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = (w0 + u < npart) ? PB2[(int64_t)(w0 + u) * (2 + 2 * QP_NBMAX) + e] : 0.0;
+            for (int u = 0; u < 32; ++u)
+                v[u] = (w0 + u < npart) ? PB2[(int64_t)(w0 + u) * (2 + 2 * QP_NBMAX) + e] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += v[u];
+            for (int u = 0; u < 32; ++u) acc += v[u];
         }
         sv[e] = acc;
     }
@@ -329,16 +333,20 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
     if (c >= a.n) return;
     const double *xc = a.A + j * a.lda;
     const double *ac = a.A + c * a.lda;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;  // four chains keep four loads in flight
+    double dd[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // eight chains: sixteen loads in flight
     int64_t r = j + 1 + lane;
-    for (; r + 192 < a.m; r += 256) {
-        d0 += xc[r] * ac[r];
-        d1 += xc[r + 64] * ac[r + 64];
-        d2 += xc[r + 128] * ac[r + 128];
-        d3 += xc[r + 192] * ac[r + 192];
+    for (; r + 448 < a.m; r += 512) {
+        double xv[8], av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            xv[u] = xc[r + 64 * u];
+            av[u] = ac[r + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dd[u] += xv[u] * av[u];
     }
-    for (; r < a.m; r += 64) d0 += xc[r] * ac[r];
-    const double d = wave_sum((d0 + d1) + (d2 + d3));
+    for (int u = 0; r < a.m; r += 64, ++u) dd[u & 7] += xc[r] * ac[r];
+    const double d = wave_sum(((dd[0] + dd[1]) + (dd[2] + dd[3])) + ((dd[4] + dd[5]) + (dd[6] + dd[7])));
     // the F row of column c, one earlier reflector per lane (b <= 64)
     const double fz = lane < b ? Fz[(int64_t)lane * a.n + c] : 0.0;
     const double corr = wave_sum(lane < b ? fz * auxv[lane] : 0.0);
