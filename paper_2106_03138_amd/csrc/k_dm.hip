@@ -394,6 +394,12 @@ __device__ __forceinline__ int sel4(int r0, int r1, int r2, int r3, int k) {
     return k == 0 ? r0 : (k == 1 ? r1 : (k == 2 ? r2 : r3));
 }
 
+__device__ __forceinline__ unsigned long long dm_readlane64(unsigned long long v, int l) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, double *theta_out) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
@@ -401,6 +407,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     __shared__ double sG[QK_KM * QK_KM];
     __shared__ int sJ[QK_KM];
     __shared__ int sAi[QK_KM];  // candidate index (row of G) of each accepted column
+    __shared__ unsigned long long sbad[QK_KM][2];  // bit j of row i: candidate j conflicts with i
     __shared__ int sjslot[QK_KM];
     __shared__ int soutpos[QK_KM];
     __shared__ int s_ks;
@@ -434,28 +441,41 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
         // eq. (delta_max): delta <= tau^2 / (k_max - 1), k_max the candidate
         // count, puts every accepted block under the hypotheses of Lemma 1
         const double delta = a.certified ? fmin(a.delta, a.tau * a.tau / (double)(nL - 1)) : a.delta;
+        // conflicts |theta_ij| >= delta (or undefined) of every candidate i with
+        // every earlier j, as bit masks, all wavefronts in parallel
+        for (int i = tid >> 6; i < nL; i += 4) {
+            const double di = sd[i];
+            bool bad0 = false, bad1 = false;
+            if (lane < i) bad0 = !(fabs(G[i * QK_KM + lane] / (di * sd[lane])) < delta);
+            if (lane + 64 < i) bad1 = !(fabs(G[i * QK_KM + lane + 64] / (di * sd[lane + 64])) < delta);
+            const unsigned long long m0 = __ballot(bad0), m1 = __ballot(bad1);
+            if (lane == 0) {
+                sbad[i][0] = m0;
+                sbad[i][1] = m1;
+            }
+        }
+        __syncthreads();
         if (tid < 64) {
-            // greedy acceptance in candidate order, one wavefront; lane owns
-            // candidates lane and lane+64
-            bool acc0 = (lane == 0), acc1 = false;
+            // greedy acceptance in candidate order (Algorithm 1): candidate i joins
+            // when it conflicts with no accepted candidate and its norm is nonzero;
+            // lane L holds the masks of candidates L and L + 64
+            const unsigned long long r00 = lane < nL ? sbad[lane][0] : 0ull, r01 = lane < nL ? sbad[lane][1] : 0ull;
+            const unsigned long long r10 = lane + 64 < nL ? sbad[lane + 64][0] : 0ull;
+            const unsigned long long r11 = lane + 64 < nL ? sbad[lane + 64][1] : 0ull;
+            const bool pos0 = lane < nL && sd[lane] > 0.0, pos1 = lane + 64 < nL && sd[lane + 64] > 0.0;
+            const unsigned long long p0 = __ballot(pos0), p1 = __ballot(pos1);
+            unsigned long long A0 = 1ull, A1 = 0ull;
             for (int i = 1; i < nL; ++i) {
-                const double di = sd[i];
-                bool bad = false;
-                if (lane < i && acc0) {
-                    double th = fabs(G[i * QK_KM + lane] / (di * sd[lane]));
-                    bad = !(th < delta);
-                }
-                if (lane + 64 < i && acc1) {
-                    double th = fabs(G[i * QK_KM + lane + 64] / (di * sd[lane + 64]));
-                    bad = bad || !(th < delta);
-                }
-                const bool any_bad = __any(bad);
-                const bool ok = !any_bad && (di > 0.0);
-                if (ok) {
-                    if (i == lane) acc0 = true;
-                    if (i == lane + 64) acc1 = true;
+                const int L = i & 63;
+                const bool hi = i >= 64;
+                const unsigned long long b0 = dm_readlane64(hi ? r10 : r00, L), b1 = dm_readlane64(hi ? r11 : r01, L);
+                const bool pos = ((hi ? p1 : p0) >> L) & 1ull;
+                if (pos && !((b0 & A0) | (b1 & A1))) {
+                    if (hi) A1 |= 1ull << L;
+                    else A0 |= 1ull << L;
                 }
             }
+            const bool acc0 = (A0 >> lane) & 1ull, acc1 = (A1 >> lane) & 1ull;
             // compact accepted candidates in order
             unsigned long long b0 = __ballot(acc0), b1 = __ballot(acc1);
             int c0 = __popcll(b0);
