@@ -28,6 +28,49 @@
 #define QP_ROWS 256  // rows per workgroup of the pivot-column pass
 #define QP_NBMAX 64
 
+// Lane exchanges on the VALU (DPP row operations and the gfx950 lane swaps)
+// instead of LDS permutes, whose latency the reductions of these latency-bound
+// kernels would otherwise pay once per level: qp_x<K>(v) is v of lane ^ K for
+// K = 32, 16, 8, 2, 1, and qp_x<7> that of lane ^ 7 (the mirror within each
+// group of 8 lanes), which takes the place of lane ^ 4 in the trees below.
+// Every kernel of this file reduces through them, so all its paths sum in
+// the same order.
+template <int K>
+__device__ __forceinline__ uint32_t qp_xu(uint32_t v) {
+    if constexpr (K == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    } else if constexpr (K == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        // row_ror:8, row_half_mirror, quad_perm(2,3,0,1), quad_perm(1,0,3,2)
+        constexpr int ctrl = K == 8 ? 0x128 : K == 7 ? 0x141 : K == 2 ? 0x4e : 0xb1;
+        static_assert(K == 8 || K == 7 || K == 2 || K == 1, "lane exchange");
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
+    }
+}
+template <int K>
+__device__ __forceinline__ double qp_x(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = qp_xu<K>((uint32_t)b), hi = qp_xu<K>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <int K>
+__device__ __forceinline__ int qp_xi(int v) {
+    return (int)qp_xu<K>((uint32_t)v);
+}
+// Sum over the 64 lanes, the same value in every lane.
+__device__ __forceinline__ double qp_wave_sum(double v) {
+    v += qp_x<32>(v);
+    v += qp_x<16>(v);
+    v += qp_x<8>(v);
+    v += qp_x<7>(v);
+    v += qp_x<2>(v);
+    v += qp_x<1>(v);
+    return v;
+}
+
 hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
                             int64_t w_bound, hipStream_t s);
 
@@ -66,6 +109,23 @@ __device__ __forceinline__ bool qp_better(double va, int ja, double vb, int jb) 
     return va > vb || (va == vb && ja < jb);
 }
 
+// Arg-max over the 64 lanes of (v, j) pairs in qp_better's order (a total
+// order, so the result does not depend on the tree), in every lane.
+template <int K>
+__device__ __forceinline__ void qp_argmax_step(double &bv, int &bj) {
+    const double ov = qp_x<K>(bv);
+    const int oj = qp_xi<K>(bj);
+    if (qp_better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
+}
+__device__ __forceinline__ void qp_argmax_lanes(double &bv, int &bj) {
+    qp_argmax_step<32>(bv, bj);
+    qp_argmax_step<16>(bv, bj);
+    qp_argmax_step<8>(bv, bj);
+    qp_argmax_step<7>(bv, bj);
+    qp_argmax_step<2>(bv, bj);
+    qp_argmax_step<1>(bv, bj);
+}
+
 __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
     QrdmCtl *ctl = a.ctl;
     __shared__ double s_v[16];
@@ -73,6 +133,10 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
     __shared__ int s_go, s_norm;
     if (ctl->done) return;
     const int tid = threadIdx.x;
+    if (ctl->qp_stop) {  // the block closed by the stopping test is updated and normalized
+        if (tid == 0) ctl->done = 1;
+        return;
+    }
     if (tid == 0 && ctl->l == 1) {
         // advance from the previous step, which made the reflector of column ns;
         // that reflector stays pending (normalized by the next column pass)
@@ -105,12 +169,7 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
         const double v = a.vn1[c];
         if (v > bv) { bv = v; bj = (int)c; }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oj = __shfl_xor(bj, o, 64);
-        if (qp_better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
-    }
+    qp_argmax_lanes(bv, bj);
     if ((tid & 63) == 0) { s_v[tid >> 6] = bv; s_j[tid >> 6] = bj; }
     __syncthreads();
     if (tid == 0) {
@@ -175,21 +234,23 @@ __global__ void __launch_bounds__(1024) k_qp_select(QrdmArgs a, double *Fz) {
 // ------------------------------------------------------------ pivot column
 #define QP_NB_REG 32  // earlier reflectors of the block held in registers per row
 
-// Sum of 32 values over a wavefront by butterfly reduce-scatter (32 shuffles):
-// on return lane L holds the sum of value (L >> 1) when L is even.
+// Sum of 32 values over a wavefront by butterfly reduce-scatter (32 lane
+// exchanges): on return lane L holds the sum of value (L >> 1) when L is even.
+// At each level a lane keeps the half of its values selected by its own lane
+// bit and adds the partner's copy of that half.
 __device__ __forceinline__ double qp_reduce_scatter32(const double (&v)[QP_NB_REG], int lane) {
     double c16[16], c8[8], c4[4], c2[2];
     const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4, b1 = lane & 2;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) c16[k] = (b5 ? v[16 + k] : v[k]) + __shfl_xor(b5 ? v[k] : v[16 + k], 32, 64);
+    for (int k = 0; k < 16; ++k) c16[k] = (b5 ? v[16 + k] : v[k]) + qp_x<32>(b5 ? v[k] : v[16 + k]);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c8[k] = (b4 ? c16[8 + k] : c16[k]) + __shfl_xor(b4 ? c16[k] : c16[8 + k], 16, 64);
+    for (int k = 0; k < 8; ++k) c8[k] = (b4 ? c16[8 + k] : c16[k]) + qp_x<16>(b4 ? c16[k] : c16[8 + k]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) c4[k] = (b3 ? c8[4 + k] : c8[k]) + __shfl_xor(b3 ? c8[k] : c8[4 + k], 8, 64);
+    for (int k = 0; k < 4; ++k) c4[k] = (b3 ? c8[4 + k] : c8[k]) + qp_x<8>(b3 ? c8[k] : c8[4 + k]);
 #pragma unroll
-    for (int k = 0; k < 2; ++k) c2[k] = (b2 ? c4[2 + k] : c4[k]) + __shfl_xor(b2 ? c4[k] : c4[2 + k], 4, 64);
-    const double c1 = (b1 ? c2[1] : c2[0]) + __shfl_xor(b1 ? c2[0] : c2[1], 2, 64);
-    return c1 + __shfl_xor(c1, 1, 64);
+    for (int k = 0; k < 2; ++k) c2[k] = (b2 ? c4[2 + k] : c4[k]) + qp_x<7>(b2 ? c4[k] : c4[2 + k]);
+    const double c1 = (b1 ? c2[1] : c2[0]) + qp_x<2>(b1 ? c2[0] : c2[1]);
+    return c1 + qp_x<1>(c1);
 }
 
 __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz, double *PB2) {
@@ -256,14 +317,14 @@ __global__ void __launch_bounds__(256) k_qp_column(QrdmArgs a, const double *Fz,
         }
         for (int bb = 0; bb < b; ++bb) {
             const double vb = (below || atj) ? a.A[(k0 + bb) * a.lda + r] : 0.0;
-            const double d = wave_sum(below ? vb * x : 0.0);
+            const double d = qp_wave_sum(below ? vb * x : 0.0);
             if (lane == 0) red[wv][2 + bb] = d;
             if (atj) stp[bb] = vb;
         }
     }
     // [0] sum_{r>j} x^2, [1] x_j, [2+bb] sum_{r>j} v_bb[r] x_r, [2+b+bb] v_bb[j]
-    const double s0 = wave_sum(below ? x * x : 0.0);
-    const double s1 = wave_sum(atj ? x : 0.0);
+    const double s0 = qp_wave_sum(below ? x * x : 0.0);
+    const double s1 = qp_wave_sum(atj ? x : 0.0);
     if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
     __syncthreads();
     const int nv = 2 + 2 * b;
@@ -346,11 +407,11 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
         for (int u = 0; u < 8; ++u) dd[u] += xv[u] * av[u];
     }
     for (int u = 0; r < a.m; r += 64, ++u) dd[u & 7] += xc[r] * ac[r];
-    const double d = wave_sum(((dd[0] + dd[1]) + (dd[2] + dd[3])) + ((dd[4] + dd[5]) + (dd[6] + dd[7])));
+    const double d = qp_wave_sum(((dd[0] + dd[1]) + (dd[2] + dd[3])) + ((dd[4] + dd[5]) + (dd[6] + dd[7])));
     // the F row of column c, one earlier reflector per lane (b <= 64)
     const double fz = lane < b ? Fz[(int64_t)lane * a.n + c] : 0.0;
-    const double corr = wave_sum(lane < b ? fz * auxv[lane] : 0.0);
-    const double rcor = wave_sum(lane < b ? fz * sv[2 + b + lane] : 0.0);
+    const double corr = qp_wave_sum(lane < b ? fz * auxv[lane] : 0.0);
+    const double rcor = qp_wave_sum(lane < b ? fz * sv[2 + b + lane] : 0.0);
     if (lane == 0) {
         // F[c, b] = tau v^T a_c - tau sum_{b'<b} F[c, b'] (V^T v)_{b'}
         double f = ac[j] + d / den;
@@ -394,7 +455,7 @@ __global__ void __launch_bounds__(256) k_qp_close(QrdmArgs a, int32_t *flag, int
         const double *col = a.A + c * a.lda;
         double t = 0.0;
         for (int64_t r = last + 1 + lane; r < a.m; r += 64) t += col[r] * col[r];
-        t = wave_sum(t);
+        t = qp_wave_sum(t);
         if (lane == 0) {
             const double v = sqrt(t);
             a.vn1[c] = v;
@@ -411,7 +472,8 @@ __global__ void __launch_bounds__(256) k_qp_close(QrdmArgs a, int32_t *flag, int
             a.A[last * a.lda + r] *= rden;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.A[last * a.lda + last] = ctl->qp_beta;
     }
-    if (final_step && blockIdx.x == 0 && threadIdx.x == 0 && ctl->qp_stop) ctl->done = 1;
+    // after a stop, `done` is raised by the next k_qp_select / k_qp_run: raised
+    // here, it could make a workgroup of this grid that starts late skip its rows
 }
 
 hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s) {
@@ -424,4 +486,561 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int6
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_qp_close, dim3(g_cols), dim3(256), 0, s, a, bf.flag, nb);
     return hipGetLastError();
+}
+
+// ======================================================= persistent QP3 block
+// The steps of one QP3 block (up to nb pivots) in one cooperative launch, with
+// the arithmetic of k_qp_select / k_qp_column / k_qp_gemv in the same order.
+// Per step:
+//   arg-max (from the partials of the previous step) and the stopping test ->
+//   pivot-column pass over 256-row slabs -> grid barrier -> GEMV over the
+//   trailing columns, which also updates the partial norms and publishes each
+//   workgroup's arg-max of them -> grid barrier.
+// Every workgroup carries the loop state in registers and takes the same
+// decisions from the same exchanged values.  Row slab s belongs to workgroup
+// s % G for the whole launch, so the rows of the block's reflectors are only
+// ever written and read by one thread; the trailing columns are split evenly
+// over the workgroups afresh at each step, and everything that crosses
+// workgroups (the pivot column, F, the norms, the partials) goes through
+// agent-scope atomic loads and stores.  The swap bookkeeping of a pivot
+// (norms, perm, F rows) is done by the workgroup that owns the pivot's old
+// column in the GEMV phase; the column pass reads the pivot's F row from that
+// old column.  Each workgroup stages the pivot column below the diagonal in LDS
+// (m <= QR_XS_MAX + 1).  The launch returns at the block end (or at the stop);
+// the deferred update (k_gemm2 mode 1) and k_qp_close follow as separate
+// launches.
+#define QR_THREADS 256
+#define QR_XS_MAX 16384  // rows of the staged pivot column (128 KB of LDS)
+#define QR_SPIN_LIMIT (1 << 26)
+
+__device__ __forceinline__ double qr_ld(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void qr_st(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t qr_ldi(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void qr_sti(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Flag barrier: each workgroup raises its arrival flag, one thread per
+// workgroup polls the others' (bounded; on timeout the error flag is set, the
+// kernel runs on and later barriers no longer wait).
+__device__ __forceinline__ void qr_barrier(uint32_t *flags, int G, uint32_t target, int32_t *err) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)threadIdx.x < G && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
+        int it = 0;
+        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++it > QR_SPIN_LIMIT) {
+                atomicOr(err, 2);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup arg-max of (v, j) pairs (largest value, lowest index on ties).
+__device__ __forceinline__ void qr_wg_argmax(double &bv, int &bj, double *sv, int *sj) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    qp_argmax_lanes(bv, bj);
+    if (lane == 0) { sv[wv] = bv; sj[wv] = bj; }
+    __syncthreads();
+    bv = sv[0];
+    bj = sj[0];
+    for (int w = 1; w < QR_THREADS / 64; ++w)
+        if (qp_better(sv[w], sj[w], bv, bj)) { bv = sv[w]; bj = sj[w]; }
+    __syncthreads();
+}
+
+// Arg-max over the G published partials (the unique largest value with the
+// lowest index, whatever the order) and the OR of their recompute flags.
+__device__ __forceinline__ void qr_reduce_partials(const double *amx, int G, double &uv, int64_t &uj, int &fl,
+                                                   double *sv, int *sj, int *sf) {
+    double bv = -1.0;
+    int bj = 0x7fffffff, f = 0;
+    for (int w = threadIdx.x; w < G; w += QR_THREADS) {
+        const double v = qr_ld(amx + 4 * w), jd = qr_ld(amx + 4 * w + 1), fd = qr_ld(amx + 4 * w + 2);
+        const int jj = (int)jd;
+        if (qp_better(v, jj, bv, bj)) { bv = v; bj = jj; }
+        f |= fd != 0.0;
+    }
+    f = __any(f);
+    if ((threadIdx.x & 63) == 0) sf[threadIdx.x >> 6] = f;
+    qr_wg_argmax(bv, bj, sv, sj);
+    int ff = 0;
+    for (int w = 0; w < QR_THREADS / 64; ++w) ff |= sf[w];
+    uv = bv;
+    uj = bj;
+    fl = ff;
+}
+
+// One batch of the dots of columns ca and cb (cb < 0: none) with the staged
+// pivot column, rows r0 .. r0+1535 (below m), added to the chains of
+// k_qp_gemv: row j+1+64k goes to chain k mod 8 (1536 rows = 24 row-groups, a
+// multiple of 8), each chain in increasing k.
+#define QR_DOT_ROWS 24
+__device__ __forceinline__ void qr_dot2_batch(const double *pa, const double *pb, bool two, int64_t m, int64_t j,
+                                              int64_t r0, const double *xs, int lane, double (&ea)[8],
+                                              double (&eb)[8]) {
+    double av[QR_DOT_ROWS], bv[QR_DOT_ROWS];
+#pragma unroll
+    for (int u = 0; u < QR_DOT_ROWS; ++u) {
+        const int64_t r = r0 + lane + 64 * u;
+        av[u] = r < m ? qr_ld(pa + r) : 0.0;
+        bv[u] = (two && r < m) ? qr_ld(pb + r) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < QR_DOT_ROWS; ++u) {
+        const int64_t r = r0 + lane + 64 * u;
+        if (r < m) {
+            const double x = xs[r - j - 1];
+            ea[u & 7] += x * av[u];
+            eb[u & 7] += x * bv[u];
+        }
+    }
+}
+
+extern __shared__ double qr_xs[];
+
+__global__ void __launch_bounds__(QR_THREADS)
+k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, double *amx, uint32_t epoch0, int nb) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) return;
+    const int G = gridDim.x, wg = blockIdx.x;
+    if (ctl->qp_stop) {  // the block closed by the stopping test is updated and normalized
+        if (wg == 0 && threadIdx.x == 0) ctl->done = 1;
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t p = p_of(a);
+    const int npart = (int)((a.m + QP_ROWS - 1) / QP_ROWS);
+    __shared__ double s_v[QR_THREADS / 64];
+    __shared__ int s_j[QR_THREADS / 64];
+    __shared__ int s_f[QR_THREADS / 64];
+    __shared__ double sF[QP_NBMAX];
+    __shared__ double red[4][2 + 2 * QP_NBMAX];
+    __shared__ double stp[QP_NBMAX];
+    __shared__ double sv[2 + 2 * QP_NBMAX];
+    __shared__ double auxv[QP_NBMAX];
+    // loop state (identical in every workgroup)
+    int64_t ns = ctl->ns, rank = ctl->rank, k0 = ctl->qp_k0, nblocks = ctl->nblocks, jm = ctl->jmax;
+    int l = ctl->l, b = ctl->qp_b, pend = ctl->qp_pend, qstop = ctl->qp_stop, qflag = ctl->qp_flag, done = 0;
+    double amax = ctl->amax, pbeta = ctl->qp_beta, pden = ctl->qp_den, umax = ctl->umax;
+    uint32_t bar = 0;
+    bool first = true;
+    double uv = 0.0;
+    int64_t uj = 0;
+    for (;;) {
+        // ---- advance past the previous step's reflector (k_qp_select)
+        if (l == 1) {
+            const bool closes = qstop || (b + 1 == nb) || (ns + 1 == p) || qflag;
+            const int kb = qstop ? b : b + 1;
+            if (closes) {
+                k0 = k0 + kb;
+                b = 0;
+                qflag = 0;
+            } else {
+                b += 1;
+            }
+            pend = 1;
+            ns += 1;
+            l = 0;
+        }
+        const int64_t j = ns;
+        if (j >= p) {
+            done = 1;
+            if (rank < 0) rank = j;
+            break;
+        }
+        if (first) {
+            // arg-max over the columns from j, this workgroup's share, then exchange
+            double bv = -1.0;
+            int bj = 0x7fffffff;
+            for (int64_t c = j + (int64_t)wg * QR_THREADS + tid; c < a.n; c += (int64_t)G * QR_THREADS) {
+                const double v = qr_ld(a.vn1 + c);
+                if (qp_better(v, (int)c, bv, bj)) { bv = v; bj = (int)c; }
+            }
+            qr_wg_argmax(bv, bj, s_v, s_j);
+            if (tid == 0) {
+                qr_st(amx + 4 * wg, bv);
+                qr_st(amx + 4 * wg + 1, (double)bj);
+                qr_st(amx + 4 * wg + 2, 0.0);
+            }
+            qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+            int fl;
+            qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
+            first = false;
+        }
+        // ---- stopping test (k_qp_select)
+        if (nblocks == 0 && j == 0) amax = uv;
+        int go = 1, snorm = 0;
+        if (amax == 0.0) {
+            rank = 0;
+            done = 1;
+            go = 0;
+        } else if (rank < 0) {
+            const double lhs = (a.stop_rule == 1) ? uv : sqrt((double)(a.n - j)) * uv;
+            if (lhs <= a.eps1 * amax) {
+                rank = j;
+                if (a.stop_rule != 2) {
+                    go = 0;
+                    if (b > 0) {
+                        qstop = 1;
+                    } else {
+                        done = 1;
+                        snorm = pend;
+                    }
+                }
+            }
+        }
+        if (!go) {
+            if (snorm) {  // stopping right after a block end: normalize reflector j-1 in place
+                const double rden = 1.0 / pden;
+                for (int64_t r = j + (int64_t)wg * QR_THREADS + tid; r < a.m; r += (int64_t)G * QR_THREADS)
+                    a.A[(j - 1) * a.lda + r] *= rden;
+                if (wg == 0 && tid == 0) a.A[(j - 1) * a.lda + (j - 1)] = pbeta;
+            }
+            break;
+        }
+        jm = uj;
+        umax = uv;
+        nblocks += 1;
+        // ---- pivot-column pass (k_qp_column), one row slab per workgroup:
+        // every load of the slab first, then arithmetic, then every store
+        for (int s = wg; s < npart; s += G) {
+            const int64_t r = (int64_t)s * QP_ROWS + tid;
+            const bool inm = r < a.m;
+            const bool live = inm && (r >= j);
+            const bool below = live && (r > j);
+            const bool atj = live && (r == j);
+            const int64_t pc = j - 1;
+            const bool npend = pend && inm && r > pc;  // rows of the pending reflector scaled by 1/den
+            const bool big = b > QP_NB_REG;
+            double pv = npend ? a.A[pc * a.lda + r] : 0.0;
+            double t1 = 0.0, t2 = 0.0;
+            if (inm && (jm != j || live)) t1 = qr_ld(a.A + j * a.lda + r);
+            if (inm && jm != j) t2 = qr_ld(a.A + jm * a.lda + r);
+            double vr[QP_NB_REG];
+#pragma unroll
+            for (int u = 0; u < QP_NB_REG; ++u)
+                vr[u] = (!big && live && u < b && !(pend && u == b - 1)) ? a.A[(k0 + u) * a.lda + r] : 0.0;
+            for (int bb = tid; bb < QP_NBMAX; bb += QR_THREADS) {
+                sF[bb] = bb < b ? qr_ld(Fz + (int64_t)bb * a.n + jm) : 0.0;  // the pivot's F row, before its swap
+                stp[bb] = 0.0;
+            }
+            __syncthreads();
+            if (npend) pv *= 1.0 / pden;
+            if (!big && pend) {
+#pragma unroll
+                for (int u = 0; u < QP_NB_REG; ++u)
+                    if (u == b - 1 && live) vr[u] = pv;
+            }
+            double x = live ? (jm != j ? t2 : t1) : 0.0;
+            if (!big) {
+                if (live) {
+#pragma unroll
+                    for (int u = 0; u < QP_NB_REG; ++u) x -= vr[u] * sF[u];
+                }
+                if (atj) {
+#pragma unroll
+                    for (int u = 0; u < QP_NB_REG; ++u)
+                        if (u < b) stp[u] = vr[u];
+                }
+                double pvv[QP_NB_REG];
+#pragma unroll
+                for (int u = 0; u < QP_NB_REG; ++u) pvv[u] = below ? vr[u] * x : 0.0;
+                const double d = qp_reduce_scatter32(pvv, lane);
+                if ((lane & 1) == 0 && (lane >> 1) < b) red[wv][2 + (lane >> 1)] = d;
+            } else {
+                // more than 32 reflectors: one wavefront sum per reflector (the
+                // pending one, column k0 + b - 1, from the scaled register copy)
+                if (live) {
+                    for (int bb = 0; bb < b; ++bb)
+                        x -= (bb == b - 1 ? pv : a.A[(k0 + bb) * a.lda + r]) * sF[bb];
+                }
+                for (int bb = 0; bb < b; ++bb) {
+                    const double vb = (below || atj) ? (bb == b - 1 ? pv : a.A[(k0 + bb) * a.lda + r]) : 0.0;
+                    const double d = qp_wave_sum(below ? vb * x : 0.0);
+                    if (lane == 0) red[wv][2 + bb] = d;
+                    if (atj) stp[bb] = vb;
+                }
+            }
+            const double s0 = qp_wave_sum(below ? x * x : 0.0);
+            const double s1 = qp_wave_sum(atj ? x : 0.0);
+            if (lane == 0) { red[wv][0] = s0; red[wv][1] = s1; }
+            __syncthreads();
+            const int nv = 2 + 2 * b;
+            for (int e = tid; e < nv; e += QR_THREADS) {
+                const double v = e < 2 + b ? red[0][e] + red[1][e] + red[2][e] + red[3][e] : stp[e - 2 - b];
+                qr_st(PB2 + (int64_t)s * (2 + 2 * QP_NBMAX) + e, v);
+            }
+            if (npend) a.A[pc * a.lda + r] = pv;
+            else if (pend && inm && r == pc) a.A[pc * a.lda + r] = pbeta;
+            if (inm && jm != j) {
+                if (!live) qr_st(a.A + j * a.lda + r, t2);  // rows above j: plain swap
+                qr_st(a.A + jm * a.lda + r, t1);
+            }
+            if (live) qr_st(a.A + j * a.lda + r, x);
+            __syncthreads();
+        }
+        qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+        // ---- GEMV (k_qp_gemv): the pivot column below j into LDS, the
+        // reflector scalars from the slab partials (every workgroup)
+        const double *xc = a.A + j * a.lda;
+        {
+            // the slab partials (rows from j's slab on: the slabs above hold no
+            // live row) and the pivot column below j, loads issued together
+            const int nv = 2 + 2 * b;
+            const int wfirst = (int)(j / QP_ROWS);
+            const int64_t nrow = a.m - j - 1;
+            double pvv[32], xv[8];
+            const bool mine = tid < nv;
+#pragma unroll
+            for (int u = 0; u < 32; ++u)
+                pvv[u] = (mine && wfirst + u < npart) ? qr_ld(PB2 + (int64_t)(wfirst + u) * (2 + 2 * QP_NBMAX) + tid)
+                                                      : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = tid + QR_THREADS * u;
+                xv[u] = i < nrow ? qr_ld(xc + j + 1 + i) : 0.0;
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < 32; ++u) acc += pvv[u];
+            for (int w0 = wfirst + 32; w0 < npart; w0 += 32) {  // more than 32 live slabs
+#pragma unroll
+                for (int u = 0; u < 32; ++u)
+                    pvv[u] = (mine && w0 + u < npart) ? qr_ld(PB2 + (int64_t)(w0 + u) * (2 + 2 * QP_NBMAX) + tid)
+                                                      : 0.0;
+#pragma unroll
+                for (int u = 0; u < 32; ++u) acc += pvv[u];
+            }
+            if (mine) sv[tid] = acc;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = tid + QR_THREADS * u;
+                if (i < nrow) qr_xs[i] = xv[u];
+            }
+            for (int64_t i0 = 8 * QR_THREADS; i0 < nrow; i0 += 8 * QR_THREADS) {  // more than 2048 rows
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t i = i0 + tid + QR_THREADS * u;
+                    xv[u] = i < nrow ? qr_ld(xc + j + 1 + i) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t i = i0 + tid + QR_THREADS * u;
+                    if (i < nrow) qr_xs[i] = xv[u];
+                }
+            }
+            __syncthreads();
+        }
+        const double sp = sv[0], alpha = sv[1];
+        double beta, ti, den;
+        {
+            const double nrm = sqrt(alpha * alpha + sp);
+            if (sp == 0.0) {
+                ti = 0.0;
+                beta = alpha;
+                den = 1.0;
+            } else {
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                ti = (beta - alpha) / beta;
+                den = alpha - beta;
+            }
+        }
+        if (wg == 0 && tid == 0) a.tau_house[j] = ti;
+        for (int bb = tid; bb < b; bb += QR_THREADS) auxv[bb] = sv[2 + b + bb] + sv[2 + bb] / den;  // V^T v
+        __syncthreads();
+        // this step's share of the trailing columns: a contiguous range per
+        // workgroup, column c_lo + i to wavefront i % 4, two columns at a time
+        const int64_t q = (a.n - j - 1 + G - 1) / G;
+        const int64_t c_lo = j + 1 + (int64_t)wg * q;
+        const int64_t c_hi = c_lo + q < a.n ? c_lo + q : a.n;
+        double bv = -1.0;
+        int bj = 0x7fffffff, fany = 0;
+        for (int64_t ca = c_lo + wv; ca < c_hi; ca += 8) {
+            const int64_t cb = ca + 4 < c_hi ? ca + 4 : -1;
+            const bool two = cb >= 0;
+            const int hs = (jm != j && ca == jm) ? 0 : ((jm != j && cb == jm) ? 1 : -1);  // holds the pivot's old column
+            // loads: F rows, norms and row j of both columns (for the pivot's
+            // old column, F and the norms of column j: their values after the
+            // swap), the swap's other half, then the first batch of the dots
+            double fz[2], acj[2] = {0.0, 0.0}, n1[2] = {0.0, 0.0}, n2[2] = {0.0, 0.0};
+            double sw_f = 0.0, sw_n1 = 0.0, sw_n2 = 0.0;
+            int32_t sw_p1 = 0, sw_p2 = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t c = h ? cb : ca;
+                const int64_t cs = (h == hs) ? j : c;
+                fz[h] = (lane < b && c >= 0) ? qr_ld(Fz + (int64_t)lane * a.n + cs) : 0.0;
+                if (lane == 0 && c >= 0) {
+                    acj[h] = qr_ld(a.A + c * a.lda + j);
+                    n1[h] = qr_ld(a.vn1 + cs);
+                    n2[h] = qr_ld(a.vn2 + cs);
+                }
+            }
+            if (hs >= 0) {
+                sw_f = lane < b ? qr_ld(Fz + (int64_t)lane * a.n + jm) : 0.0;
+                if (lane == 0) {
+                    sw_n1 = qr_ld(a.vn1 + jm);
+                    sw_n2 = qr_ld(a.vn2 + jm);
+                    sw_p1 = qr_ldi(a.perm + j);
+                    sw_p2 = qr_ldi(a.perm + jm);
+                }
+            }
+            const double *pa = a.A + ca * a.lda, *pb = a.A + (two ? cb : ca) * a.lda;
+            double ea[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, eb[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int64_t r0 = j + 1; r0 < a.m; r0 += 64 * QR_DOT_ROWS)
+                qr_dot2_batch(pa, pb, two, a.m, j, r0, qr_xs, lane, ea, eb);
+            double dots[2];
+            dots[0] = qp_wave_sum(((ea[0] + ea[1]) + (ea[2] + ea[3])) + ((ea[4] + ea[5]) + (ea[6] + ea[7])));
+            dots[1] = qp_wave_sum(((eb[0] + eb[1]) + (eb[2] + eb[3])) + ((eb[4] + eb[5]) + (eb[6] + eb[7])));
+            double fnew[2], rjc[2], v1n[2];
+            int upd[2] = {0, 0}, flg[2] = {0, 0};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t c = h ? cb : ca;
+                const double corr = qp_wave_sum(lane < b ? fz[h] * auxv[lane] : 0.0);
+                const double rcor = qp_wave_sum(lane < b ? fz[h] * sv[2 + b + lane] : 0.0);
+                double f = acj[h] + dots[h] / den;
+                f = ti * f - ti * corr;
+                fnew[h] = f;
+                rjc[h] = acj[h] - f - rcor;
+                double v1 = n1[h];
+                if (v1 != 0.0) {
+                    double qq = 1.0 - (rjc[h] * rjc[h]) / (v1 * v1);
+                    if (qq < 0.0) qq = 0.0;
+                    const double r12 = v1 / n2[h];
+                    const double q2 = qq * (r12 * r12);
+                    if (q2 <= a.tol3z) {
+                        flg[h] = 1;
+                    } else {
+                        v1 = v1 * sqrt(qq);
+                        upd[h] = 1;
+                    }
+                }
+                v1n[h] = v1;
+                if (lane == 0 && c >= 0) {
+                    fany |= flg[h];
+                    if (qp_better(v1, (int)c, bv, bj)) { bv = v1; bj = (int)c; }
+                }
+            }
+            // stores: the swap of the pivot's old column with column j, then
+            // both columns' F entry, pivot row entry and norm
+            if (hs >= 0) {
+                if (lane < b) {
+                    qr_st(Fz + (int64_t)lane * a.n + j, sw_f);
+                    qr_st(Fz + (int64_t)lane * a.n + jm, fz[hs]);
+                }
+                if (lane == 0) {
+                    qr_st(a.vn1 + j, sw_n1);
+                    qr_st(a.vn2 + j, sw_n2);
+                    qr_st(a.vn2 + jm, n2[hs]);
+                    qr_sti(a.perm + j, sw_p2);
+                    qr_sti(a.perm + jm, sw_p1);
+                }
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t c = h ? cb : ca;
+                    if (c < 0) continue;
+                    qr_st(Fz + (int64_t)b * a.n + c, fnew[h]);
+                    qr_st(a.A + c * a.lda + j, rjc[h]);
+                    if (upd[h] || h == hs) qr_st(a.vn1 + c, v1n[h]);
+                    if (flg[h]) qr_sti(flag + c, 1);
+                }
+            }
+        }
+        // this workgroup's arg-max of the updated norms, and its recompute flag
+        fany = __any(fany);
+        if (lane == 0) s_f[wv] = fany;
+        qr_wg_argmax(bv, bj, s_v, s_j);
+        if (tid == 0) {
+            int ff = 0;
+            for (int w = 0; w < QR_THREADS / 64; ++w) ff |= s_f[w];
+            qr_st(amx + 4 * wg, bv);
+            qr_st(amx + 4 * wg + 1, (double)bj);
+            qr_st(amx + 4 * wg + 2, (double)ff);
+        }
+        pbeta = beta;
+        pden = den;
+        l = 1;
+        qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+        int fl;
+        qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
+        qflag = qflag || fl;
+        if ((b + 1 == nb) || (j + 1 == p) || qflag) break;  // block end: the deferred update follows
+    }
+    // every workgroup has read the loop state before it is written back
+    if (bar == 0) qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+    if (wg == 0 && tid == 0) {
+        ctl->ns = ns;
+        ctl->rank = rank;
+        ctl->qp_k0 = k0;
+        ctl->nblocks = nblocks;
+        ctl->jmax = jm;
+        ctl->l = l;
+        ctl->qp_b = b;
+        ctl->qp_pend = pend;
+        ctl->qp_stop = qstop;
+        ctl->qp_flag = qflag;
+        ctl->amax = amax;
+        ctl->qp_beta = pbeta;
+        ctl->qp_den = pden;
+        ctl->umax = umax;
+        if (done) ctl->done = 1;
+    }
+}
+
+static size_t qr_lds_bytes(int64_t m) {
+    const int64_t rows = m > 1 ? m - 1 : 1;
+    return sizeof(double) * (size_t)rows;
+}
+
+// One QP3 block as a persistent launch, then the block-end kernels.  Returns
+// hipErrorCooperativeLaunchTooLarge (nothing launched) when the grid cannot be
+// co-resident.
+hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
+                            int grid, hipStream_t s) {
+    if (grid < 1 || grid > QP_RUN_MAXWG || nb < 1 || nb > QP_NBMAX || a.m > QR_XS_MAX + 1) return hipErrorInvalidValue;
+    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb};
+    hipError_t e = hipLaunchCooperativeKernel((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args,
+                                              (unsigned)qr_lds_bytes(a.m), s);
+    if (e != hipSuccess) return e;
+    e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
+    if (e != hipSuccess) return e;
+    const unsigned g_cols = (unsigned)((w_bound + 3) / 4 + 1);
+    hipLaunchKernelGGL(k_qp_close, dim3(g_cols), dim3(256), 0, s, a, bf.flag, nb);
+    return hipGetLastError();
+}
+
+// One workgroup per compute unit (all co-resident: the kernel needs one slot
+// per CU with its LDS), capped at QP_RUN_MAXWG; 0 (the per-step kernels) when
+// the device cannot hold that grid, the pivot column would not fit in LDS, or
+// the row slabs would be more than 8 per workgroup.
+int qp3_block_grid(int64_t m) {
+    if (m > QR_XS_MAX + 1) return 0;
+    const int64_t npart = (m + QP_ROWS - 1) / QP_ROWS;
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipFuncSetAttribute((const void *)k_qp_run, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)qr_lds_bytes(QR_XS_MAX + 1)) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_run, QR_THREADS,
+                                                     qr_lds_bytes(m)) != hipSuccess ||
+        per_cu < 1)
+        return 0;
+    const int g = ncu < QP_RUN_MAXWG ? ncu : QP_RUN_MAXWG;
+    if (g < 1 || npart > 8 * (int64_t)g) return 0;
+    return g;
 }

@@ -59,7 +59,7 @@ int prof_events(size_t count) {
 }
 
 struct Layout {
-    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, perm_dbg, total;
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, perm_dbg, total;
 };
 
 const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
@@ -88,6 +88,8 @@ Layout make_layout(int64_t m, int64_t n) {
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
     L.fz = take(sizeof(double) * 64 * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
+    // QP3 block kernel: arrival flags, then 4 doubles of arg-max partials per workgroup
+    L.qrb = take(sizeof(uint32_t) * QP_RUN_MAXWG + sizeof(double) * 4 * QP_RUN_MAXWG);
     L.perm_dbg = take(sizeof(int32_t) * nn);
     L.total = off;
     return L;
@@ -173,9 +175,35 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
     bf.PB2 = (double *)(ws + L.pb2);
     bf.Fz = (double *)(ws + L.fz);
     bf.flag = (int32_t *)(ws + L.flag);
+    bf.bflags = (uint32_t *)(ws + L.qrb);
+    bf.amx = (double *)(ws + L.qrb + sizeof(uint32_t) * QP_RUN_MAXWG);
     HIP_TRY(launch_qp3_init(a, nb, s));
     const int ring = g_ws.ring;
     const int64_t pmin = std::min(a.m, a.n);
+    const char *mode = getenv("QRDM_QP3_STEPS");  // "1": the per-step kernels (comparison runs)
+    const int grid = (mode && strcmp(mode, "1") == 0) ? 0 : qp3_block_grid(a.m);
+    if (grid > 0) {
+        // one block of up to nb steps per launch; a snapshot after each, the
+        // host waiting on the one `lag` launches back
+        HIP_TRY(hipMemsetAsync(bf.bflags, 0, sizeof(uint32_t) * QP_RUN_MAXWG, s));
+        for (int64_t iter = 0;; ++iter) {
+            const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
+            const uint32_t epoch0 = (uint32_t)(iter + 1) * 256u;  // > 2 nb + 2 barriers per launch
+            HIP_TRY(launch_qp3_block(a, bf, epoch0, nb, tb, wb, grid, s));
+            Snapshot *hs = g_ws.host_snap + (iter % ring);
+            HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
+            if (iter >= lag) {
+                const int64_t k = iter - lag;
+                HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
+                const Snapshot sn = g_ws.host_snap[k % ring];
+                if (sn.ns > ns_known) ns_known = sn.ns;
+                if (sn.done) break;
+            }
+            if (iter > pmin + lag + 4) break;  // cannot happen: every launch takes at least one step
+        }
+        return 0;
+    }
     // snapshots every kStride steps; the host waits on the one `lag` snapshots back
     const int kStride = 4;
     int64_t nsnap = 0;
@@ -586,6 +614,7 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;
     HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
+    if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     *rank = cf.rank >= 0 ? cf.rank : cf.ns;
     if (stats) {
         stats->nblocks = cf.nblocks;

@@ -99,16 +99,26 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
                         hipEvent_t *ev);
 hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s);
 
-// QP3 (LAPACK xgeqp3-style) column loop: one step per column, launched by the host
+// QP3 (LAPACK xgeqp3-style) column loop: either one block of up to nb steps
+// per cooperative launch, or one step per group of launches
+#define QP_RUN_MAXWG 256  // workgroups of the persistent block kernel (at most)
 struct Qp3Bufs {
-    double *PB2;      // [ceil(m/QP_ROWS)][2 + 2 nb] partials of the pivot column pass
+    double *PB2;      // [ceil(m/256)][2 + 2 * 64] partials of the pivot column pass
     double *Fz;       // [nb][n]: F^T of the deferred update, absolute column index
     int32_t *flag;    // [n]: partial norm needs recomputation
+    uint32_t *bflags; // [QP_RUN_MAXWG]: arrival flags of the block kernel's grid barrier
+    double *amx;      // [QP_RUN_MAXWG][4]: per-workgroup arg-max partials of the block kernel
 };
 hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s);
 hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
                             int64_t w_bound, hipStream_t s);
 hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s);
+// Grid of the block kernel for m rows (0: use the per-step kernels).  epoch0
+// must exceed every flag value of earlier launches by the same flags (a launch
+// raises them by at most 2 nb + 2).
+int qp3_block_grid(int64_t m);
+hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
+                            int grid, hipStream_t s);
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
 int panel_rows_for(int64_t m, int kmax);
