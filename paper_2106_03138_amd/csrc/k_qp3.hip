@@ -511,6 +511,8 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int6
 // launches.
 #define QR_THREADS 256
 #define QR_XS_MAX 16384  // rows of the staged pivot column (128 KB of LDS)
+#define QR_CACHE_ROWS 2048  // rows of the column cache (the owner's reload is one batch of 8 per thread)
+#define QR_LDS_DYN (144 * 1024)  // dynamic LDS of the block kernel (at most)
 #define QR_SPIN_LIMIT (1 << 26)
 
 __device__ __forceinline__ double qr_ld(const double *p) {
@@ -610,7 +612,8 @@ __device__ __forceinline__ void qr_dot2_batch(const double *pa, const double *pb
 extern __shared__ double qr_xs[];
 
 __global__ void __launch_bounds__(QR_THREADS)
-k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, double *amx, uint32_t epoch0, int nb) {
+k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, double *amx, uint32_t epoch0, int nb,
+         int cq, int crows) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int G = gridDim.x, wg = blockIdx.x;
@@ -621,6 +624,10 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t p = p_of(a);
     const int npart = (int)((a.m + QP_ROWS - 1) / QP_ROWS);
+    if (npart > G) {  // one row slab per workgroup at most (the host's grid ensures it)
+        if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
+        return;
+    }
     __shared__ double s_v[QR_THREADS / 64];
     __shared__ int s_j[QR_THREADS / 64];
     __shared__ int s_f[QR_THREADS / 64];
@@ -637,6 +644,56 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
     bool first = true;
     double uv = 0.0;
     int64_t uj = 0;
+    // Column cache (cq > 0): this workgroup's trailing columns are fixed for
+    // the launch, [cw0, cw1) from the block's first column j0, and held in LDS
+    // from row j0 down with their F entries and partial norms; within a block
+    // A changes only in the pivot rows (written through here) and by the pivot
+    // swaps (the owner of the pivot's old column reloads it).  Otherwise the
+    // columns are split afresh at each step and read from memory.
+    const bool cached = cq > 0;
+    const int64_t j0 = ns + (l == 1 ? 1 : 0);
+    const int64_t q0 = a.n > j0 ? (a.n - j0 + G - 1) / G : 0;
+    const int64_t cw0 = j0 + (int64_t)wg * q0;
+    const int64_t cw1 = cw0 + q0 < a.n ? cw0 + q0 : a.n;
+    const int64_t rows0 = a.m > j0 ? a.m - j0 : 0;
+    double *xs = qr_xs;
+    double *cc = qr_xs + crows;                    // [cq][crows], rows from j0
+    double *fzc = cc + (int64_t)cq * crows;         // [cq][64]: F entries of the block
+    double *n1c = fzc + (int64_t)cq * QP_NBMAX;     // [cq]
+    double *n2c = n1c + cq;                         // [cq]
+    // the row's entries of the block's reflectors (b <= 32) and its pivot-column
+    // value of the previous step, kept in registers by the row's owner (one
+    // row slab per workgroup at most, for the whole launch)
+    double vr[QP_NB_REG];
+#pragma unroll
+    for (int u = 0; u < QP_NB_REG; ++u) vr[u] = 0.0;
+    double xlast = 0.0;
+    if (cached) {
+        // the host sized the cache from bounds on j0 (cannot fail)
+        if (q0 > cq || rows0 > crows || crows > QR_CACHE_ROWS) {
+            if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
+            return;
+        }
+        const int64_t tot = (cw1 > cw0 ? cw1 - cw0 : 0) * rows0;
+        for (int64_t i0 = 0; i0 < tot; i0 += 8 * QR_THREADS) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + tid + QR_THREADS * u;
+                v[u] = i < tot ? qr_ld(a.A + (cw0 + i / rows0) * a.lda + j0 + i % rows0) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + tid + QR_THREADS * u;
+                if (i < tot) cc[(i / rows0) * crows + i % rows0] = v[u];
+            }
+        }
+        for (int64_t c = cw0 + tid; c < cw1; c += QR_THREADS) {
+            n1c[c - cw0] = qr_ld(a.vn1 + c);
+            n2c[c - cw0] = qr_ld(a.vn2 + c);
+        }
+        __syncthreads();
+    }
     for (;;) {
         // ---- advance past the previous step's reflector (k_qp_select)
         if (l == 1) {
@@ -712,9 +769,10 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
         jm = uj;
         umax = uv;
         nblocks += 1;
-        // ---- pivot-column pass (k_qp_column), one row slab per workgroup:
+        // ---- pivot-column pass (k_qp_column), row slab wg (npart <= G):
         // every load of the slab first, then arithmetic, then every store
-        for (int s = wg; s < npart; s += G) {
+        if (wg < npart) {
+            const int s = wg;
             const int64_t r = (int64_t)s * QP_ROWS + tid;
             const bool inm = r < a.m;
             const bool live = inm && (r >= j);
@@ -723,14 +781,12 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
             const int64_t pc = j - 1;
             const bool npend = pend && inm && r > pc;  // rows of the pending reflector scaled by 1/den
             const bool big = b > QP_NB_REG;
-            double pv = npend ? a.A[pc * a.lda + r] : 0.0;
+            // the pending reflector's row: this thread's pivot-column value of
+            // the previous step, or from memory at the launch's first step
+            double pv = npend ? (b > 0 ? xlast : a.A[pc * a.lda + r]) : 0.0;
             double t1 = 0.0, t2 = 0.0;
             if (inm && (jm != j || live)) t1 = qr_ld(a.A + j * a.lda + r);
             if (inm && jm != j) t2 = qr_ld(a.A + jm * a.lda + r);
-            double vr[QP_NB_REG];
-#pragma unroll
-            for (int u = 0; u < QP_NB_REG; ++u)
-                vr[u] = (!big && live && u < b && !(pend && u == b - 1)) ? a.A[(k0 + u) * a.lda + r] : 0.0;
             for (int bb = tid; bb < QP_NBMAX; bb += QR_THREADS) {
                 sF[bb] = bb < b ? qr_ld(Fz + (int64_t)bb * a.n + jm) : 0.0;  // the pivot's F row, before its swap
                 stp[bb] = 0.0;
@@ -788,12 +844,39 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
                 qr_st(a.A + jm * a.lda + r, t1);
             }
             if (live) qr_st(a.A + j * a.lda + r, x);
+            xlast = x;
             __syncthreads();
         }
         qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
         // ---- GEMV (k_qp_gemv): the pivot column below j into LDS, the
         // reflector scalars from the slab partials (every workgroup)
         const double *xc = a.A + j * a.lda;
+        // with the column cache, the workgroup that owns the pivot's old
+        // column jm takes over what column j held: its rows (swapped in by
+        // the column pass), F entries and norms; its own go to column j
+        const bool own_jm = cached && jm != j && jm >= cw0 && jm < cw1;
+        const int64_t jmi = jm - cw0;
+        double rv[8], rf = 0.0, rn1 = 0.0, rn2 = 0.0, of = 0.0, on1 = 0.0, on2 = 0.0;
+        int32_t pj = 0, pm = 0;
+        if (own_jm) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = tid + QR_THREADS * u;
+                rv[u] = i < rows0 ? qr_ld(a.A + jm * a.lda + j0 + i) : 0.0;
+            }
+            if (tid < b) {
+                rf = qr_ld(Fz + (int64_t)tid * a.n + j);
+                of = fzc[jmi * QP_NBMAX + tid];
+            }
+            if (tid == 0) {
+                rn1 = qr_ld(a.vn1 + j);
+                rn2 = qr_ld(a.vn2 + j);
+                on1 = n1c[jmi];
+                on2 = n2c[jmi];
+                pj = qr_ldi(a.perm + j);
+                pm = qr_ldi(a.perm + jm);
+            }
+        }
         {
             // the slab partials (rows from j's slab on: the slabs above hold no
             // live row) and the pivot column below j, loads issued together
@@ -840,6 +923,27 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
                     if (i < nrow) qr_xs[i] = xv[u];
                 }
             }
+            if (own_jm) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t i = tid + QR_THREADS * u;
+                    if (i < rows0) cc[jmi * crows + i] = rv[u];
+                }
+                if (tid < b) {
+                    fzc[jmi * QP_NBMAX + tid] = rf;
+                    qr_st(Fz + (int64_t)tid * a.n + j, of);
+                    qr_st(Fz + (int64_t)tid * a.n + jm, rf);
+                }
+                if (tid == 0) {
+                    n1c[jmi] = rn1;
+                    n2c[jmi] = rn2;
+                    qr_st(a.vn1 + j, on1);
+                    qr_st(a.vn2 + j, on2);
+                    qr_st(a.vn2 + jm, rn2);  // vn1[jm] is written once, by the column loop
+                    qr_sti(a.perm + j, pm);
+                    qr_sti(a.perm + jm, pj);
+                }
+            }
             __syncthreads();
         }
         const double sp = sv[0], alpha = sv[1];
@@ -859,13 +963,91 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
         if (wg == 0 && tid == 0) a.tau_house[j] = ti;
         for (int bb = tid; bb < b; bb += QR_THREADS) auxv[bb] = sv[2 + b + bb] + sv[2 + bb] / den;  // V^T v
         __syncthreads();
+        double bv = -1.0;
+        int bj = 0x7fffffff, fany = 0;
+        if (cached) {
+            // this workgroup's columns after j, column cs + i to wavefront i % 4,
+            // two at a time; every operand from LDS
+            const int64_t cs = cw0 > j + 1 ? cw0 : j + 1;
+            for (int64_t ca = cs + wv; ca < cw1; ca += 8) {
+                const int64_t cb = ca + 4 < cw1 ? ca + 4 : -1;
+                const bool two = cb >= 0;
+                const double *pa = cc + (ca - cw0) * crows - j0, *pb = cc + ((two ? cb : ca) - cw0) * crows - j0;
+                double ea[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+                       eb[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                // row j+1+64k to chain k mod 8, each chain in increasing k
+                int64_t r = j + 1 + lane;
+                for (; r + 448 < a.m; r += 512) {
+                    double xv[8], av[8], bw[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        xv[u] = xs[r - j - 1 + 64 * u];
+                        av[u] = pa[r + 64 * u];
+                        bw[u] = two ? pb[r + 64 * u] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        ea[u] += xv[u] * av[u];
+                        eb[u] += xv[u] * bw[u];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t rr = r + 64 * u;
+                    if (rr < a.m) {
+                        const double x = xs[rr - j - 1];
+                        ea[u] += x * pa[rr];
+                        eb[u] += x * (two ? pb[rr] : 0.0);
+                    }
+                }
+                double dots[2];
+                dots[0] = qp_wave_sum(((ea[0] + ea[1]) + (ea[2] + ea[3])) + ((ea[4] + ea[5]) + (ea[6] + ea[7])));
+                dots[1] = qp_wave_sum(((eb[0] + eb[1]) + (eb[2] + eb[3])) + ((eb[4] + eb[5]) + (eb[6] + eb[7])));
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t c = h ? cb : ca;
+                    if (c < 0) continue;
+                    const int64_t ci = c - cw0;
+                    const double fz = lane < b ? fzc[ci * QP_NBMAX + lane] : 0.0;
+                    const double corr = qp_wave_sum(lane < b ? fz * auxv[lane] : 0.0);
+                    const double rcor = qp_wave_sum(lane < b ? fz * sv[2 + b + lane] : 0.0);
+                    if (lane == 0) {
+                        const double acj = cc[ci * crows + (j - j0)];
+                        double f = acj + dots[h] / den;
+                        f = ti * f - ti * corr;
+                        const double rjc = acj - f - rcor;
+                        double v1 = n1c[ci];
+                        int upd = 0, flg = 0;
+                        if (v1 != 0.0) {
+                            double qq = 1.0 - (rjc * rjc) / (v1 * v1);
+                            if (qq < 0.0) qq = 0.0;
+                            const double r12 = v1 / n2c[ci];
+                            const double q2 = qq * (r12 * r12);
+                            if (q2 <= a.tol3z) {
+                                flg = 1;
+                            } else {
+                                v1 = v1 * sqrt(qq);
+                                upd = 1;
+                            }
+                        }
+                        fzc[ci * QP_NBMAX + b] = f;
+                        cc[ci * crows + (j - j0)] = rjc;
+                        qr_st(Fz + (int64_t)b * a.n + c, f);
+                        qr_st(a.A + c * a.lda + j, rjc);
+                        if (upd) n1c[ci] = v1;
+                        if (upd || c == jm) qr_st(a.vn1 + c, v1);
+                        if (flg) qr_sti(flag + c, 1);
+                        fany |= flg;
+                        if (qp_better(v1, (int)c, bv, bj)) { bv = v1; bj = (int)c; }
+                    }
+                }
+            }
+        } else {
         // this step's share of the trailing columns: a contiguous range per
         // workgroup, column c_lo + i to wavefront i % 4, two columns at a time
         const int64_t q = (a.n - j - 1 + G - 1) / G;
         const int64_t c_lo = j + 1 + (int64_t)wg * q;
         const int64_t c_hi = c_lo + q < a.n ? c_lo + q : a.n;
-        double bv = -1.0;
-        int bj = 0x7fffffff, fany = 0;
         for (int64_t ca = c_lo + wv; ca < c_hi; ca += 8) {
             const int64_t cb = ca + 4 < c_hi ? ca + 4 : -1;
             const bool two = cb >= 0;
@@ -960,6 +1142,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
                 }
             }
         }
+        }
         // this workgroup's arg-max of the updated norms, and its recompute flag
         fany = __any(fany);
         if (lane == 0) s_f[wv] = fany;
@@ -1001,9 +1184,26 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
     }
 }
 
+// Dynamic LDS of the uncached mode: the pivot column below the diagonal.
 static size_t qr_lds_bytes(int64_t m) {
     const int64_t rows = m > 1 ? m - 1 : 1;
     return sizeof(double) * (size_t)rows;
+}
+
+// Column cache of the next launch from bounds on its first column j0 >= n - w_bound:
+// at most t_bound rows and ceil(w_bound / grid) columns per workgroup.  0 columns
+// when the cache would not fit.
+static void qr_cache_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, int *crows, size_t *bytes) {
+    *cq = 0;
+    *crows = 0;
+    const int64_t rows = t_bound > 1 ? t_bound : 1;
+    const int64_t q = (w_bound + grid - 1) / grid;
+    const size_t need = sizeof(double) * (size_t)(rows + q * rows + q * QP_NBMAX + 2 * q);
+    if (rows <= QR_CACHE_ROWS && q >= 1 && need <= QR_LDS_DYN) {
+        *cq = (int)q;
+        *crows = (int)rows;
+        *bytes = need;
+    }
 }
 
 // One QP3 block as a persistent launch, then the block-end kernels.  Returns
@@ -1012,9 +1212,12 @@ static size_t qr_lds_bytes(int64_t m) {
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
                             int grid, hipStream_t s) {
     if (grid < 1 || grid > QP_RUN_MAXWG || nb < 1 || nb > QP_NBMAX || a.m > QR_XS_MAX + 1) return hipErrorInvalidValue;
-    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb};
+    int cq = 0, crows = 0;
+    size_t lds = qr_lds_bytes(a.m);
+    qr_cache_shape(t_bound, w_bound, grid, &cq, &crows, &lds);
+    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb, &cq, &crows};
     hipError_t e = hipLaunchCooperativeKernel((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args,
-                                              (unsigned)qr_lds_bytes(a.m), s);
+                                              (unsigned)lds, s);
     if (e != hipSuccess) return e;
     e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
     if (e != hipSuccess) return e;
@@ -1026,21 +1229,21 @@ hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int
 // One workgroup per compute unit (all co-resident: the kernel needs one slot
 // per CU with its LDS), capped at QP_RUN_MAXWG; 0 (the per-step kernels) when
 // the device cannot hold that grid, the pivot column would not fit in LDS, or
-// the row slabs would be more than 8 per workgroup.
+// the row slabs would outnumber the workgroups.
 int qp3_block_grid(int64_t m) {
     if (m > QR_XS_MAX + 1) return 0;
     const int64_t npart = (m + QP_ROWS - 1) / QP_ROWS;
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipFuncSetAttribute((const void *)k_qp_run, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)qr_lds_bytes(QR_XS_MAX + 1)) != hipSuccess)
+    if (hipFuncSetAttribute((const void *)k_qp_run, hipFuncAttributeMaxDynamicSharedMemorySize, QR_LDS_DYN) !=
+        hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_run, QR_THREADS,
-                                                     qr_lds_bytes(m)) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_run, QR_THREADS, QR_LDS_DYN) !=
+            hipSuccess ||
         per_cu < 1)
         return 0;
     const int g = ncu < QP_RUN_MAXWG ? ncu : QP_RUN_MAXWG;
-    if (g < 1 || npart > 8 * (int64_t)g) return 0;
+    if (g < 1 || npart > (int64_t)g) return 0;
     return g;
 }

@@ -2,7 +2,10 @@
 to nb pivots per cooperative launch; the per-step kernels remain selectable
 (QRDM_QP3_STEPS=1).  Both carry out the same arithmetic in the same order, so
 pivots and rank must agree exactly and R / tau to rounding of the contraction
-(1e-13 relative).  The block path is also checked against the oracle."""
+(1e-13 relative).  The block kernel holds its columns in LDS when they fit
+(2048 rows at most) and reads them from memory otherwise: tall_2200x400
+starts in the second mode and ends in the first.  The block path is also
+checked against the oracle."""
 import numpy as np
 import pytest
 
@@ -28,6 +31,8 @@ def _graded(m, n, seed):
 CASES = {
     "tall_700x300": lambda: np.random.default_rng(11).standard_normal((700, 300)),
     "wide_200x500": lambda: np.random.default_rng(12).standard_normal((200, 500)),
+    "wide_150x3000": lambda: np.random.default_rng(16).standard_normal((150, 3000)),
+    "tall_2200x400": lambda: np.random.default_rng(17).standard_normal((2200, 400)),
     "half_rank_384": lambda: I.half_rank_noise(384, 2),
     "graded_600x200": lambda: _graded(600, 200, 13),
     "rank64_256": lambda: I.small_rank64(5),
