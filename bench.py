@@ -68,7 +68,8 @@ def flops_cols(m, n, r):
     return float(np.sum(4.0 * (m - s) * (n - s)))
 
 
-KERNEL_SOURCES = {"k_panel": "k_panel.hip", "k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip"}
+KERNEL_SOURCES = {"k_panel": "k_panel.hip", "k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip",
+                  "k_qp_run": "k_qp3.hip"}
 
 
 def source_sha(kernel):
@@ -100,11 +101,19 @@ def measured_traffic(kernel, workload_tag):
 def roofline(prof, prec, Q, workload_tag=None):
     """Roofline of the kernel with the largest summed time.  The panel is
     HBM-bound (arithmetic intensity k_s/8 flop/B is below the FP64 ridge of
-    78.6/8 = 9.8 flop/B); the two trailing GEMMs are MFMA-bound."""
-    times = {"k_panel": prof["panel_ms"], "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"]}
+    78.6/8 = 9.8 flop/B); the two trailing GEMMs are MFMA-bound; the QP3 block
+    kernel (column pivoting, a matrix-vector product over the trailing matrix
+    per pivot, 2 flop per 8 B) is HBM-bound."""
+    times = {"k_panel": prof["panel_ms"], "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"],
+             "k_qp_run": prof.get("qp3_run_ms", 0.0)}
     dom = max(times, key=times.get)
     nlaunch = max(int(prof["npanel"]), 1)  # one panel and one launch of each GEMM per block
-    if dom == "k_panel":
+    if dom == "k_qp_run":
+        nlaunch = max(int(prof["nqp3_launch"]), 1)
+        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
+        work = prof["qp3_bytes"]
+        achieved = work / (times[dom] * 1e-3) / 1e9
+    elif dom == "k_panel":
         bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
         work = prof["panel_bytes"]
         achieved = work / (times[dom] * 1e-3) / 1e9
@@ -121,6 +130,7 @@ def roofline(prof, prec, Q, workload_tag=None):
             "phase_ms": {"dm_select": round(prof["dm_ms"], 3), "panel": round(prof["panel_ms"], 3),
                          "gemm1": round(prof["gemm1_ms"], 3), "gemm2": round(prof["gemm2_ms"], 3),
                          "downdate": round(prof["downdate_ms"], 3), "qp3_tail": round(prof["qp3_ms"], 3),
+                         "qp3_block_kernel": round(prof.get("qp3_run_ms", 0.0), 3),
                          "loop_total": round(prof["total_ms"], 3)}}
 
 

@@ -97,6 +97,11 @@ typedef struct {
                             (t-i)(2 + 4(k_s-1-i))                                          */
     double panel_bytes;  /* algorithmic bytes of the panels: 16 t k_s per block            */
     int64_t npanel;      /* panel launches that factored a block (always filled)            */
+    /* the column-pivoting loop (QRP; QRDM's scalar-pivoting tail), profile = 1:           */
+    double qp3_run_ms;   /* summed event time of its block-kernel launches                 */
+    double qp3_bytes;    /* algorithmic bytes: 8 (m-j)(n-j) per pivot step j (the trailing
+                            matrix read once by the step's matrix-vector product)          */
+    int64_t nqp3_launch; /* block-kernel launches (0 when the per-step kernels ran)        */
 } qrdm_stats;
 
 /* One record per outer step, for tests and tracing. */

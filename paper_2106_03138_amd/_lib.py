@@ -27,7 +27,8 @@ class Stats(ctypes.Structure):
                 ("gemm1_ms", ctypes.c_double), ("gemm2_ms", ctypes.c_double), ("gemm_flop", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("dm_ms", ctypes.c_double), ("panel_ms", ctypes.c_double),
                 ("downdate_ms", ctypes.c_double), ("qp3_ms", ctypes.c_double), ("panel_flop", ctypes.c_double),
-                ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64)]
+                ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64),
+                ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64)]
 
 
 class Block(ctypes.Structure):

@@ -79,6 +79,7 @@ __global__ void k_qp_init(QrdmArgs a, int nb) {
     QrdmCtl *c = a.ctl;
     if (!c->done) c->ns += c->l;  // finish the advance of a preceding QRDM step
     c->qp_k0 = c->ns;
+    c->qp3_start = c->ns;
     c->qp_b = 0;
     c->qp_pend = 0;
     c->qp_end = 0;
@@ -1210,15 +1211,17 @@ static void qr_cache_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, 
 // hipErrorCooperativeLaunchTooLarge (nothing launched) when the grid cannot be
 // co-resident.
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
-                            int grid, hipStream_t s) {
+                            int grid, hipStream_t s, hipEvent_t *ev) {
     if (grid < 1 || grid > QP_RUN_MAXWG || nb < 1 || nb > QP_NBMAX || a.m > QR_XS_MAX + 1) return hipErrorInvalidValue;
     int cq = 0, crows = 0;
     size_t lds = qr_lds_bytes(a.m);
     qr_cache_shape(t_bound, w_bound, grid, &cq, &crows, &lds);
     void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb, &cq, &crows};
-    hipError_t e = hipLaunchCooperativeKernel((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args,
-                                              (unsigned)lds, s);
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    e = hipLaunchCooperativeKernel((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args, (unsigned)lds, s);
     if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
     if (e != hipSuccess) return e;
     const unsigned g_cols = (unsigned)((w_bound + 3) / 4 + 1);

@@ -49,13 +49,37 @@ Workspace g_ws;
 
 // timing events of the profiling mode (grown on demand, kept for reuse)
 std::vector<hipEvent_t> g_prof_ev;
-int prof_events(size_t count) {
-    while (g_prof_ev.size() < count) {
+std::vector<hipEvent_t> g_qp_ev;  // around each QP3 block-kernel launch
+int grow_events(std::vector<hipEvent_t> &v, size_t count) {
+    while (v.size() < count) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
-        g_prof_ev.push_back(e);
+        v.push_back(e);
     }
     return 0;
+}
+int prof_events(size_t count) { return grow_events(g_prof_ev, count); }
+
+// Timing of the QP3 loop's block-kernel launches (profile mode).
+struct Qp3Prof {
+    bool on = false;
+    int64_t launches = 0;
+};
+
+// Algorithmic bytes of the pivot steps j0 .. j1-1: 8 (m-j)(n-j) each.
+double qp3_bytes(int64_t m, int64_t n, int64_t j0, int64_t j1) {
+    double b = 0.0;
+    for (int64_t j = j0; j < j1; ++j) b += 8.0 * (double)(m - j) * (double)(n - j);
+    return b;
+}
+
+double qp3_run_ms(int64_t launches) {
+    double t = 0.0;
+    for (int64_t i = 0; i < launches; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_qp_ev[2 * i], g_qp_ev[2 * i + 1]) == hipSuccess) t += ms;
+    }
+    return t;
 }
 
 struct Layout {
@@ -170,7 +194,8 @@ QrdmCtl initial_ctl() {
 const int kQp3Nb = 32;  // block size of the column-pivoting update
 
 // Column pivoting steps from the device's current n_s until the loop is done.
-int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64_t ns_known, hipStream_t s) {
+int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64_t ns_known, hipStream_t s,
+            Qp3Prof *prof) {
     Qp3Bufs bf;
     bf.PB2 = (double *)(ws + L.pb2);
     bf.Fz = (double *)(ws + L.fz);
@@ -189,7 +214,13 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
         for (int64_t iter = 0;; ++iter) {
             const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
             const uint32_t epoch0 = (uint32_t)(iter + 1) * 256u;  // > 2 nb + 2 barriers per launch
-            HIP_TRY(launch_qp3_block(a, bf, epoch0, nb, tb, wb, grid, s));
+            hipEvent_t *ev = nullptr;
+            if (prof && prof->on) {
+                if (grow_events(g_qp_ev, 2 * (size_t)(iter + 1)) != 0) return QRDM_ERR_NOMEM;
+                ev = g_qp_ev.data() + 2 * iter;
+                prof->launches = iter + 1;
+            }
+            HIP_TRY(launch_qp3_block(a, bf, epoch0, nb, tb, wb, grid, s, ev));
             Snapshot *hs = g_ws.host_snap + (iter % ring);
             HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
@@ -421,10 +452,12 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (iter > max_iter + lag + 1) break;  // cannot happen: every block advances n_s
     }
     if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
+    Qp3Prof qprof;
+    qprof.on = p.profile != 0;
     if (switch_qp3 && !finished) {
         // the partial norms reached the noise level: the rest is scalar pivoting,
         // run in the blocked column-pivoting form (deferred trailing update)
-        rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s);
+        rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s, &qprof);
         if (rc) return rc;
     }
     if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[2], s));
@@ -453,6 +486,9 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, g_prof_ev[1], g_prof_ev[2]) == hipSuccess) stats->qp3_ms = ms;
         if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[2]) == hipSuccess) stats->total_ms = ms;
+        stats->nqp3_launch = qprof.launches;
+        stats->qp3_run_ms = qp3_run_ms(qprof.launches);
+        stats->qp3_bytes = qprof.launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
     }
     if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     *rank = cf.rank >= 0 ? cf.rank : cf.ns;
@@ -609,8 +645,15 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     HIP_TRY(hipStreamSynchronize(s));
     if (nf) return QRDM_ERR_NONFINITE;
     HIP_TRY(launch_init(a, s));
-    rc = run_qp3(a, ws, L, nb, p.poll_lag, 0, s);
+    Qp3Prof qprof;
+    qprof.on = p.profile != 0;
+    if (p.profile) {
+        if (prof_events(2) != 0) return QRDM_ERR_NOMEM;
+        HIP_TRY(hipEventRecord(g_prof_ev[0], s));
+    }
+    rc = run_qp3(a, ws, L, nb, p.poll_lag, 0, s, &qprof);
     if (rc) return rc;
+    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;
     HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
@@ -620,6 +663,13 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
         stats->nblocks = cf.nblocks;
         stats->nrecompute = cf.nrecompute;
         stats->ncols_factored = cf.ns;
+        if (p.profile) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[1]) == hipSuccess) stats->qp3_ms = stats->total_ms = ms;
+            stats->nqp3_launch = qprof.launches;
+            stats->qp3_run_ms = qp3_run_ms(qprof.launches);
+            stats->qp3_bytes = qprof.launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
+        }
     }
     return 0;
 }

@@ -51,6 +51,7 @@ struct QrdmCtl {
     int32_t qp_nb;      // block size
     int32_t qp_pad;
     double qp_beta, qp_den;  // scalars of the pending reflector
+    int64_t qp3_start;       // first column of the column-pivoting loop
 };
 
 struct QrdmArgs {
@@ -118,7 +119,7 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64
 // raises them by at most 2 nb + 2).
 int qp3_block_grid(int64_t m);
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
-                            int grid, hipStream_t s);
+                            int grid, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
 int panel_rows_for(int64_t m, int kmax);
