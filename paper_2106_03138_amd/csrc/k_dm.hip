@@ -409,6 +409,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     __shared__ int sAi[QK_KM];  // candidate index (row of G) of each accepted column
     __shared__ unsigned long long sbad[QK_KM][2];  // bit j of row i: candidate j conflicts with i
     __shared__ int sjslot[QK_KM];
+    __shared__ int s_cont[QK_SWAP_MAX], s_pos[QK_SWAP_MAX];  // transposition bookkeeping (slots)
     __shared__ int soutpos[QK_KM];
     __shared__ int s_ks;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -465,15 +466,15 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             const bool pos0 = lane < nL && sd[lane] > 0.0, pos1 = lane + 64 < nL && sd[lane + 64] > 0.0;
             const unsigned long long p0 = __ballot(pos0), p1 = __ballot(pos1);
             unsigned long long A0 = 1ull, A1 = 0ull;
-            for (int i = 1; i < nL; ++i) {
-                const int L = i & 63;
-                const bool hi = i >= 64;
-                const unsigned long long b0 = dm_readlane64(hi ? r10 : r00, L), b1 = dm_readlane64(hi ? r11 : r01, L);
-                const bool pos = ((hi ? p1 : p0) >> L) & 1ull;
-                if (pos && !((b0 & A0) | (b1 & A1))) {
-                    if (hi) A1 |= 1ull << L;
-                    else A0 |= 1ull << L;
-                }
+            const int nlo = nL < 64 ? nL : 64;
+            for (int i = 1; i < nlo; ++i) {  // candidates 1..63: masks of lane i, first register pair
+                const unsigned long long b0 = dm_readlane64(r00, i);
+                if (((p0 >> i) & 1ull) && !(b0 & A0)) A0 |= 1ull << i;
+            }
+            for (int i = 64; i < nL; ++i) {  // candidates 64..: second register pair
+                const int L = i - 64;
+                const unsigned long long b0 = dm_readlane64(r10, L), b1 = dm_readlane64(r11, L);
+                if (((p1 >> L) & 1ull) && !((b0 & A0) | (b1 & A1))) A1 |= 1ull << L;
             }
             const bool acc0 = (A0 >> lane) & 1ull, acc1 = (A1 >> lane) & 1ull;
             // compact accepted candidates in order
@@ -503,16 +504,34 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     if (tid >= 64 && tid < 128) {
         double cmax = 0.0, cmin = INFINITY, gmin = INFINITY;
         if (nL > 1) {
+            // lane L holds accepted columns L and L + 64: their candidate index and norm
+            const int aiv0 = lane < ks ? sAi[lane] : 0, aiv1 = lane + 64 < ks ? sAi[lane + 64] : 0;
+            const double dv0 = sd[aiv0], dv1 = sd[aiv1];
             for (int i = lane; i < ks; i += 64) {
-                const int ai = sAi[i];
-                const double da = sd[ai];
+                const int ai = i < 64 ? aiv0 : aiv1;
+                const double da = i < 64 ? dv0 : dv1;
                 cmax = fmax(cmax, da);
                 cmin = fmin(cmin, da);
                 double rs = 0.0;
-                for (int j = 0; j < ks; ++j) {
-                    if (j == i) continue;
-                    const int bj = sAi[j];
-                    rs += fabs(G[ai * QK_KM + bj] / (da * sd[bj]));
+                for (int j0 = 0; j0 < ks; j0 += 8) {
+                    double g[8], db[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int j = j0 + u;
+                        const int bj = j < ks ? __builtin_amdgcn_readlane(j < 64 ? aiv0 : aiv1, j & 63) : 0;
+                        const double d = __longlong_as_double(
+                            ((long long)(unsigned)__builtin_amdgcn_readlane(
+                                 (int)((unsigned long long)__double_as_longlong(j < 64 ? dv0 : dv1) >> 32), j & 63)
+                             << 32) |
+                            (unsigned)__builtin_amdgcn_readlane((int)__double_as_longlong(j < 64 ? dv0 : dv1), j & 63));
+                        g[u] = j < ks ? G[ai * QK_KM + bj] : 0.0;
+                        db[u] = d;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int j = j0 + u;
+                        if (j < ks && j != i) rs += fabs(g[u] / (da * db[u]));
+                    }
                 }
                 gmin = fmin(gmin, 1.0 - rs);
             }
@@ -557,31 +576,22 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             nout += __popcll(bo);
         }
         const int nslots = ks + nout;
-        // cont[s]: slot whose original column sits in slot s; posof[c]: slot of column c
-        int c0 = lane, c1 = lane + 64, c2 = lane + 128, c3 = lane + 192;
-        int p0 = c0, p1 = c1, p2 = c2, p3 = c3;
+        // cont[s]: slot whose original column sits in slot s; posof[c]: slot of
+        // column c.  The transpositions are applied in order by the whole
+        // wavefront on the same LDS words (same addresses, same values in every
+        // lane): one LDS round trip per transposition.
+        for (int u = 0; u < 4; ++u) {
+            s_cont[lane + 64 * u] = lane + 64 * u;
+            s_pos[lane + 64 * u] = lane + 64 * u;
+        }
         for (int i = 0; i < ks; ++i) {
             const int js = sjslot[i];
-            const int ps = i;
-            const int q = __shfl(sel4(p0, p1, p2, p3, js >> 6), js & 63, 64);
-            const int c = __shfl(sel4(c0, c1, c2, c3, ps >> 6), ps & 63, 64);
-            // cont[ps] = js; cont[q] = c; posof[c] = q; posof[js] = ps
-            if (lane == (ps & 63)) {
-                int k = ps >> 6;
-                if (k == 0) c0 = js; else if (k == 1) c1 = js; else if (k == 2) c2 = js; else c3 = js;
-            }
-            if (lane == (q & 63)) {
-                int k = q >> 6;
-                if (k == 0) c0 = c; else if (k == 1) c1 = c; else if (k == 2) c2 = c; else c3 = c;
-            }
-            if (lane == (c & 63)) {
-                int k = c >> 6;
-                if (k == 0) p0 = q; else if (k == 1) p1 = q; else if (k == 2) p2 = q; else p3 = q;
-            }
-            if (lane == (js & 63)) {
-                int k = js >> 6;
-                if (k == 0) p0 = ps; else if (k == 1) p1 = ps; else if (k == 2) p2 = ps; else p3 = ps;
-            }
+            const int q = s_pos[js];
+            const int c = s_cont[i];
+            s_cont[i] = js;
+            s_cont[q] = c;
+            s_pos[c] = q;
+            s_pos[js] = i;
         }
         // moves: slot s receives the column that was at slot cont[s]
         int nmv = 0;
@@ -591,7 +601,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int sl = lane + 64 * u;
-            const int cs = sel4(c0, c1, c2, c3, u);
+            const int cs = s_cont[sl];
             mv[u] = (sl < nslots) && (cs != sl);
             dpos[u] = (sl < ks) ? (int)(ns + sl) : (sl < nslots ? soutpos[sl - ks] : 0);
             spos[u] = (cs < ks) ? (int)(ns + cs) : (cs < nslots ? soutpos[cs - ks] : 0);
