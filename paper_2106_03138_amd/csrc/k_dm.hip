@@ -29,6 +29,12 @@
 __device__ __forceinline__ bool better(double va, int ja, double vb, int jb) {
     return va > vb || (va == vb && ja < jb);
 }
+template <int K>
+__device__ __forceinline__ void sel_argmax_step(double &bv, int &bj) {
+    const double ov = lane_xd<K>(bv);
+    const int oj = (int)lane_xu<K>((uint32_t)bj);
+    if (better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
+}
 
 // exclusive prefix sum over the 1024 threads (position order = thread order)
 __device__ int block_excl_scan(int v, int *wsum, int *total) {
@@ -65,6 +71,7 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
     __shared__ int s_hist[256];
     __shared__ unsigned long long s_prefix;
     __shared__ int s_krem;
+    __shared__ int s_exact;
     __shared__ double s_cv[QK_KM];
     __shared__ int s_cj[QK_KM];
     __shared__ int s_branch;  // 0 = stop, 1 = single pivot, 2 = DM list
@@ -74,6 +81,9 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
     if (ctl->done) return;
     const int64_t ns = ctl->ns + ctl->l;
     const int64_t nblk = ctl->nblocks;
+    const double amax0 = ctl->amax;  // read with the rest of the state, before the keys
+    const int64_t rank0 = ctl->rank;
+    const int64_t nfb0 = ctl->nfallback;
     __syncthreads();
     const int64_t p = p_of(a);
     if (tid == 0) {
@@ -108,12 +118,13 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
 #pragma unroll
     for (int q = 0; q < SEL_KEYS; ++q)
         if (keys[q] > bv) { bv = keys[q]; bj = (int)(j0 + q); }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double ov = __shfl_xor(bv, o, 64);
-        int oj = __shfl_xor(bj, o, 64);
-        if (better(ov, oj, bv, bj)) { bv = ov; bj = oj; }
-    }
+    // over the wavefront (a total order: the tree does not matter)
+    sel_argmax_step<32>(bv, bj);
+    sel_argmax_step<16>(bv, bj);
+    sel_argmax_step<8>(bv, bj);
+    sel_argmax_step<7>(bv, bj);
+    sel_argmax_step<2>(bv, bj);
+    sel_argmax_step<1>(bv, bj);
     if ((tid & 63) == 0) { s_bv[tid >> 6] = bv; s_bj[tid >> 6] = bj; }
     __syncthreads();
     if (tid == 0) {
@@ -121,13 +132,13 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         int uj = s_bj[0];
         for (int i = 1; i < SEL_WAVES; ++i)
             if (better(s_bv[i], s_bj[i], uv, uj)) { uv = s_bv[i]; uj = s_bj[i]; }
-        double amax = ctl->amax;
+        double amax = amax0;
         if (nblk == 0) { amax = uv; ctl->amax = amax; }
         int branch = 2;
         if (amax == 0.0) {
             ctl->rank = 0;
             branch = 0;
-        } else if (ctl->rank < 0) {
+        } else if (rank0 < 0) {
             double lhs = (a.stop_rule == 1) ? uv : sqrt((double)(a.n - ns)) * uv;
             if (lhs <= a.eps1 * amax) {
                 ctl->rank = ns;
@@ -140,7 +151,7 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
             if (fb || cap == 1) {
                 branch = 1;
                 ctl->fallback = fb ? 1 : 0;
-                if (fb) ctl->nfallback += 1;
+                if (fb) ctl->nfallback = nfb0 + 1;
             }
         }
         if (branch == 0) {
@@ -179,8 +190,13 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         // radix select of the cap-th largest key (bit patterns of non-negative
         // doubles order like the values)
         unsigned long long prefix = 0, pmask = 0;
-        if (tid == 0) s_krem = cap;
+        if (tid == 0) {
+            s_krem = cap;
+            s_exact = 0;
+        }
+        bool fin = false;  // the same in every thread
         for (int pass = 0; pass < 8; ++pass) {
+            if (fin) continue;
             const int shift = 56 - 8 * pass;
             if (tid < 256) s_hist[tid] = 0;
             __syncthreads();
@@ -193,8 +209,8 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
                 // in few bins); the others add individually
                 const unsigned long long act = __ballot(in);
                 if (act) {
-                    const int lead = __ffsll((long long)act) - 1;
-                    const int ld = __shfl(dg, lead, 64);
+                    const int lead = __ffsll((long long)act) - 1;  // the same in every lane
+                    const int ld = __builtin_amdgcn_readlane(dg, lead);
                     const unsigned long long same = __ballot(in && dg == ld);
                     if ((threadIdx.x & 63) == lead) atomicAdd(&s_hist[ld], __popcll(same));
                     if (in && dg != ld) atomicAdd(&s_hist[dg], 1);
@@ -225,33 +241,43 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
                     }
                     s_krem = krem - before;
                     s_prefix = prefix | ((unsigned long long)dig << shift);
+                    // every key of the chosen bin is needed: the set is decided
+                    if (before + s_hist[dig] == krem) s_exact = 1;
                 }
             }
             __syncthreads();
             prefix = s_prefix;
             pmask |= (255ull << shift);
+            const int exact = s_exact;
             __syncthreads();
+            fin = exact != 0;
         }
+        // from here keys compare with the chosen bin [lo, hi] of the bits decided
+        // so far (one value unless the loop stopped early, when the whole last
+        // bin is taken)
+        const unsigned long long lo = prefix, hi = prefix | ~pmask;
         const int need_eq = s_krem;  // keys equal to the cut value to take
         const int ngt = cap - need_eq;
         int cgt = 0, ceq = 0;
 #pragma unroll
         for (int q = 0; q < SEL_KEYS; ++q) {
-            if (keys[q] >= 0.0) {
+            if (keys[q] >= thr) {  // candidates only: a partly decided bin may reach below thr
                 unsigned long long kb = (unsigned long long)__double_as_longlong(keys[q]);
-                cgt += (kb > prefix) ? 1 : 0;
-                ceq += (kb == prefix) ? 1 : 0;
+                cgt += (kb > hi) ? 1 : 0;
+                ceq += (kb >= lo && kb <= hi) ? 1 : 0;
             }
         }
-        int ogt = block_excl_scan(cgt, s_wsum, &s_total);
-        int oeq = block_excl_scan(ceq, s_wsum, &s_total);
+        // one scan for both counts: keys above the cut number fewer than cap <= 128
+        const int both = block_excl_scan(cgt | (ceq << 8), s_wsum, &s_total);
+        int ogt = both & 0xff;
+        int oeq = both >> 8;
 #pragma unroll
         for (int q = 0; q < SEL_KEYS; ++q) {
-            if (keys[q] >= 0.0) {
+            if (keys[q] >= thr) {  // candidates only: a partly decided bin may reach below thr
                 unsigned long long kb = (unsigned long long)__double_as_longlong(keys[q]);
-                if (kb > prefix) {
+                if (kb > hi) {
                     s_cv[ogt] = keys[q]; s_cj[ogt] = (int)(j0 + q); ++ogt;
-                } else if (kb == prefix) {
+                } else if (kb >= lo && kb <= hi) {
                     if (oeq < need_eq) { s_cv[ngt + oeq] = keys[q]; s_cj[ngt + oeq] = (int)(j0 + q); }
                     ++oeq;
                 }
@@ -261,12 +287,25 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
     }
     __syncthreads();
     // ---- order the list: norm descending, position ascending
-    if (tid < nsel) {
-        const double v = s_cv[tid];
-        const int j = s_cj[tid];
+    // rank of candidate i = tid / 8 among the list: eight threads count over
+    // sixteen entries each, then sum within their group of eight lanes
+    {
+        const int i = tid >> 3, part = tid & 7;
+        const bool mine = i < nsel;
+        const double v = mine ? s_cv[i] : 0.0;
+        const int j = mine ? s_cj[i] : 0;
         int r = 0;
-        for (int e = 0; e < nsel; ++e) r += better(s_cv[e], s_cj[e], v, j) ? 1 : 0;
-        ctl->L[r] = j;
+        if (mine) {
+#pragma unroll
+            for (int u = 0; u < QK_KM / 8; ++u) {
+                const int e = part * (QK_KM / 8) + u;
+                if (e < nsel) r += better(s_cv[e], s_cj[e], v, j) ? 1 : 0;
+            }
+        }
+        r += (int)lane_xu<1>((uint32_t)r);
+        r += (int)lane_xu<2>((uint32_t)r);
+        r += (int)lane_xu<7>((uint32_t)r);
+        if (mine && part == 0) ctl->L[r] = j;
     }
     if (tid == 0) ctl->nL = nsel;
 }

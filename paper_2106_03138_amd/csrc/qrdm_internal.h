@@ -80,6 +80,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ int64_t p_of(const QrdmArgs &a) { return a.m < a.n ? a.m : a.n; }
 
+// Lane exchanges on the VALU (DPP and the gfx950 lane swaps): lane_xu<K>(v) is
+// v of lane ^ K for K = 32, 16, 8, 2, 1, and of lane ^ 7 (the mirror within
+// each group of 8) for K = 7.
+template <int K>
+__device__ __forceinline__ uint32_t lane_xu(uint32_t v) {
+    if constexpr (K == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (threadIdx.x & 32) ? r[0] : r[1];
+    } else if constexpr (K == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (threadIdx.x & 16) ? r[0] : r[1];
+    } else {
+        static_assert(K == 8 || K == 7 || K == 2 || K == 1, "lane exchange");
+        constexpr int ctrl = K == 8 ? 0x128 : K == 7 ? 0x141 : K == 2 ? 0x4e : 0xb1;  // row_ror:8, row_half_mirror, quad_perm
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
+    }
+}
+template <int K>
+__device__ __forceinline__ double lane_xd(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = lane_xu<K>((uint32_t)b), hi = lane_xu<K>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 // ------------------------------------------------------------ launchers
 // Each returns hipGetLastError() of its launch.
 hipError_t launch_colnorm(const double *A, int64_t m, int64_t n, int64_t lda, double *vn1, double *vn2,
