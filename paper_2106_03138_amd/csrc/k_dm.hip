@@ -316,7 +316,7 @@ hipError_t launch_select(QrdmArgs a, hipStream_t s) {
 }
 
 // ================================================================ k_gram
-#define GR_ROWS 256   // rows of C per workgroup
+#define GR_ROWS 128   // rows of C per workgroup
 #define GR_CHUNK 64   // rows staged in LDS at a time
 #define GR_LD (GR_CHUNK + 1)
 
@@ -415,8 +415,15 @@ __global__ void __launch_bounds__(256) k_gram_reduce(QrdmArgs a, const double *G
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= nL * nL) return;
     const int i = e / nL, j = e % nL;
+    // fixed order over the partials, sixteen loads in flight
     double s = 0.0;
-    for (int w = 0; w < np; ++w) s += Gp[(int64_t)w * QK_KM * QK_KM + i * QK_KM + j];
+    for (int w0 = 0; w0 < np; w0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = w0 + u < np ? Gp[(int64_t)(w0 + u) * QK_KM * QK_KM + i * QK_KM + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
     G[i * QK_KM + j] = s;
 }
 
