@@ -686,7 +686,12 @@ hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipS
 }
 
 // ================================================================= k_swap
-#define SW_ROWS 32
+// Column moves of a DM block on a 64-row band per workgroup: wavefront w moves
+// columns w, w+4, ... with one row per lane; every source is read into
+// registers before any destination is written (a destination is often another
+// move's source).
+#define SW_ROWS 64
+#define SW_PER (QK_SWAP_MAX / 4)
 
 __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
@@ -695,20 +700,23 @@ __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     if (nsw == 0) return;
     const int64_t r0 = (int64_t)blockIdx.x * SW_ROWS;
     if (r0 >= a.m) return;
-    __shared__ double buf[QK_SWAP_MAX * SW_ROWS];
     __shared__ int sdst[QK_SWAP_MAX], ssrc[QK_SWAP_MAX];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int e = tid; e < nsw; e += 256) { sdst[e] = ctl->swp_dst[e]; ssrc[e] = ctl->swp_src[e]; }
     __syncthreads();
-    const int rows = (int)((a.m - r0) < SW_ROWS ? (a.m - r0) : SW_ROWS);
-    for (int idx = tid; idx < nsw * SW_ROWS; idx += 256) {
-        const int e = idx / SW_ROWS, r = idx % SW_ROWS;
-        if (r < rows) buf[idx] = a.A[(int64_t)ssrc[e] * a.lda + r0 + r];
+    const bool in = r0 + lane < a.m;
+    double v[SW_PER];
+#pragma unroll
+    for (int u = 0; u < SW_PER; ++u) {
+        const int e = wv + 4 * u;
+        v[u] = (e < nsw && in) ? a.A[(int64_t)ssrc[e] * a.lda + r0 + lane] : 0.0;
     }
+    __builtin_amdgcn_s_waitcnt(0);  // every read has returned before any write
     __syncthreads();
-    for (int idx = tid; idx < nsw * SW_ROWS; idx += 256) {
-        const int e = idx / SW_ROWS, r = idx % SW_ROWS;
-        if (r < rows) a.A[(int64_t)sdst[e] * a.lda + r0 + r] = buf[idx];
+#pragma unroll
+    for (int u = 0; u < SW_PER; ++u) {
+        const int e = wv + 4 * u;
+        if (e < nsw && in) a.A[(int64_t)sdst[e] * a.lda + r0 + lane] = v[u];
     }
 }
 
