@@ -46,7 +46,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, int
     __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int it = 0;
+        int it = (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) ? PN_SPIN_LIMIT : 0;
         while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++it > PN_SPIN_LIMIT) {
@@ -65,7 +65,8 @@ __device__ __forceinline__ void flag_barrier(uint32_t *flags, int P, int wg, uin
     __builtin_amdgcn_s_waitcnt(0);  // every wave's published stores have completed
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flags + wg, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)threadIdx.x < P) {
+    // after a timeout (error bit 2) the later barriers no longer wait
+    if ((int)threadIdx.x < P && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
         int it = 0;
         while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -512,5 +513,5 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *V
         attr_set = true;
     }
     void *args[] = {&a, &PB, &VV, &Vw, &Vw32, &ldv};
-    return hipLaunchCooperativeKernel((const void *)k_panel, dim3(P), dim3(PN_THREADS), args, (unsigned)lds, s);
+    return launch_resident((const void *)k_panel, dim3(P), dim3(PN_THREADS), args, (unsigned)lds, s);
 }

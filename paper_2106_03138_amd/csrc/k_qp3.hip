@@ -1219,7 +1219,7 @@ hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int
     void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb, &cq, &crows};
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    e = hipLaunchCooperativeKernel((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args, (unsigned)lds, s);
+    e = launch_resident((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args, (unsigned)lds, s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);

@@ -121,6 +121,20 @@ Layout make_layout(int64_t m, int64_t n) {
 
 int hip_err(hipError_t e) { return e == hipSuccess ? 0 : QRDM_ERR_HIP + (int)e; }
 
+}  // namespace
+
+hipError_t launch_resident(const void *kernel, dim3 grid, dim3 block, void **args, unsigned lds, hipStream_t s) {
+    static int coop = -1;
+    if (coop < 0) {
+        const char *e = getenv("QRDM_COOPERATIVE");
+        coop = (e && strcmp(e, "1") == 0) ? 1 : 0;
+    }
+    if (coop) return hipLaunchCooperativeKernel(kernel, grid, block, args, lds, s);
+    return hipLaunchKernel(kernel, grid, block, args, lds, s);
+}
+
+namespace {
+
 #define HIP_TRY(x)                                  \
     do {                                            \
         hipError_t _e = (x);                        \

@@ -105,6 +105,16 @@ __device__ __forceinline__ double lane_xd(double v) {
 }
 
 // ------------------------------------------------------------ launchers
+// Launch of a kernel whose workgroups wait on each other through memory (the
+// panel, the QP3 block kernel): every workgroup must be resident at once.  The
+// callers size the grid to at most one workgroup per compute unit, with the
+// occupancy of their largest LDS request checked, so a regular dispatch on an
+// otherwise idle device places them all at once, without the extra dispatch
+// time of hipLaunchCooperativeKernel.  QRDM_COOPERATIVE=1 in the environment
+// selects the cooperative launch (the runtime's co-residency guarantee), for
+// devices shared with other work.  Either way the kernels' waits are bounded:
+// a wait that times out raises error bit 2 and the call fails.
+hipError_t launch_resident(const void *kernel, dim3 grid, dim3 block, void **args, unsigned lds, hipStream_t s);
 // Each returns hipGetLastError() of its launch.
 hipError_t launch_colnorm(const double *A, int64_t m, int64_t n, int64_t lda, double *vn1, double *vn2,
                           QrdmCtl *ctl, hipStream_t s);
