@@ -695,6 +695,7 @@ hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipS
 
 __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gbar_clear(a.gbar);  // for the panel launched next
     if (ctl->done) return;
     const int nsw = ctl->nswap;
     if (nsw == 0) return;

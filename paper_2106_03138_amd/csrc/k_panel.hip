@@ -20,13 +20,13 @@
 // in fixed order, so the run is bit-reproducible and every workgroup takes the
 // same branch.
 //
-// The launch must be cooperative (all workgroups co-resident): the rounds are
-// separated by a counter barrier in the loop-state block.
+// All workgroups must be resident at once (launch_resident): the rounds are
+// separated by the grid barrier gbar_wait.
 #include "qrdm_internal.h"
 
 #define PN_THREADS 512
 #define PN_RB 4  // slab rows whose LDS loads are issued together in the row loops
-#define PN_FLAGS 4096  // arrival flags (one per workgroup) at the head of the partials buffer
+#define PN_FLAGS 4096  // reserved words at the head of the partials buffer
 #ifndef PN_MAX_ROWS
 #define PN_MAX_ROWS 256  // tallest slab per workgroup
 #endif
@@ -34,50 +34,7 @@
 #define PN_PREF_ROWS 128  // preferred slab height
 #endif
 #define PN_WAVES (PN_THREADS / 64)
-#define PN_SPIN_LIMIT (1 << 26)
 
-// Grid barrier for the cooperative panel.  Partials are published with
-// agent-scope (sc1) stores, which are coherent across XCDs without a write-back
-// of the whole L2; waiting for them to complete orders them before the counter
-// increment.  The spin is bounded: on timeout the error flag is raised and the
-// kernel runs to completion (the host then reports an error).
-__device__ __forceinline__ void grid_barrier(uint32_t *bar, uint32_t target, int32_t *err) {
-    __builtin_amdgcn_s_waitcnt(0);  // every wave's published stores have completed
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int it = (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) ? PN_SPIN_LIMIT : 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++it > PN_SPIN_LIMIT) {
-                atomicOr(err, 2);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-}
-
-// Flag barrier: every workgroup raises its own arrival flag (no single
-// contended counter) and polls the others' flags, one thread per workgroup.
-// Flags carry a launch epoch, so they are never reset within a factorization.
-__device__ __forceinline__ void flag_barrier(uint32_t *flags, int P, int wg, uint32_t target, int32_t *err) {
-    __builtin_amdgcn_s_waitcnt(0);  // every wave's published stores have completed
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + wg, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // after a timeout (error bit 2) the later barriers no longer wait
-    if ((int)threadIdx.x < P && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
-        int it = 0;
-        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++it > PN_SPIN_LIMIT) {
-                atomicOr(err, 2);
-                break;
-            }
-        }
-    }
-    __syncthreads();
-}
 
 __device__ __forceinline__ void st_coherent(double *p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -177,12 +134,10 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks;
     const double eps_s = ctl->eps_s;
-    // PB: [PN_FLAGS] arrival flags | [2][2 QK_KM] rows c, c+1 of the round |
+    // PB: [PN_FLAGS] (unused) | [2][2 QK_KM] rows c, c+1 of the round |
     // [2][P][2 QK_KM] partial dots (double-buffered by round parity)
-    uint32_t *flags = (uint32_t *)PB;
     double *topb = PB + PN_FLAGS / 2;
     double *part = topb + 4 * QK_KM;
-    const uint32_t epoch = (uint32_t)ctl->npanel * 1024u;  // rounds per panel <= QK_KM < 1024
     const int64_t t = a.m - ns;
     const int P = gridDim.x;
     const int wg = blockIdx.x;
@@ -276,7 +231,7 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
         // rows c and c+1 come from the one workgroup that holds each
         if (cl >= 0 && tid < ks) st_coherent(tb + tid, S[cl * ksp + tid]);
         if (pair && cl2 >= 0 && tid < ks) st_coherent(tb + QK_KM + tid, S[cl2 * ksp + tid]);
-        flag_barrier(flags, P, wg, epoch + round + 1, &ctl->error);
+        gbar_wait(a.gbar, P, (uint32_t)round + 1u, &ctl->error);
         // ---- fixed-order reduction of all partials (every workgroup, identically)
         const double *pb0 = part + (size_t)(round & 1) * P * (2 * QK_KM);
         {

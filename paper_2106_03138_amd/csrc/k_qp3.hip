@@ -77,6 +77,7 @@ hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const dou
 // ------------------------------------------------------------ init / select
 __global__ void k_qp_init(QrdmArgs a, int nb) {
     QrdmCtl *c = a.ctl;
+    gbar_clear(a.gbar);  // for the first block kernel
     if (!c->done) c->ns += c->l;  // finish the advance of a preceding QRDM step
     c->qp_k0 = c->ns;
     c->qp3_start = c->ns;
@@ -445,6 +446,7 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
 // reflector in place.
 __global__ void __launch_bounds__(256) k_qp_close(QrdmArgs a, int32_t *flag, int nb) {
     QrdmCtl *ctl = a.ctl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gbar_clear(a.gbar);  // for the next block kernel
     if (ctl->done) return;
     int kb;
     int64_t last;
@@ -490,7 +492,8 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int6
 }
 
 // ======================================================= persistent QP3 block
-// The steps of one QP3 block (up to nb pivots) in one cooperative launch, with
+// The steps of one QP3 block (up to nb pivots) in one launch (every workgroup
+// resident at once, see launch_resident), with
 // the arithmetic of k_qp_select / k_qp_column / k_qp_gemv in the same order.
 // Per step:
 //   arg-max (from the partials of the previous step) and the stopping test ->
@@ -514,7 +517,6 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int6
 #define QR_XS_MAX 16384  // rows of the staged pivot column (128 KB of LDS)
 #define QR_CACHE_ROWS 2048  // rows of the column cache (the owner's reload is one batch of 8 per thread)
 #define QR_LDS_DYN (144 * 1024)  // dynamic LDS of the block kernel (at most)
-#define QR_SPIN_LIMIT (1 << 26)
 
 __device__ __forceinline__ double qr_ld(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -527,26 +529,6 @@ __device__ __forceinline__ int32_t qr_ldi(const int32_t *p) {
 }
 __device__ __forceinline__ void qr_sti(int32_t *p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Flag barrier: each workgroup raises its arrival flag, one thread per
-// workgroup polls the others' (bounded; on timeout the error flag is set, the
-// kernel runs on and later barriers no longer wait).
-__device__ __forceinline__ void qr_barrier(uint32_t *flags, int G, uint32_t target, int32_t *err) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((int)threadIdx.x < G && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
-        int it = 0;
-        while (__hip_atomic_load(flags + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++it > QR_SPIN_LIMIT) {
-                atomicOr(err, 2);
-                break;
-            }
-        }
-    }
-    __syncthreads();
 }
 
 // Workgroup arg-max of (v, j) pairs (largest value, lowest index on ties).
@@ -613,8 +595,7 @@ __device__ __forceinline__ void qr_dot2_batch(const double *pa, const double *pb
 extern __shared__ double qr_xs[];
 
 __global__ void __launch_bounds__(QR_THREADS)
-k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, double *amx, uint32_t epoch0, int nb,
-         int cq, int crows) {
+k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb, int cq, int crows) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int G = gridDim.x, wg = blockIdx.x;
@@ -731,7 +712,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
                 qr_st(amx + 4 * wg + 1, (double)bj);
                 qr_st(amx + 4 * wg + 2, 0.0);
             }
-            qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+            gbar_wait(a.gbar, G, ++bar, &ctl->error);
             int fl;
             qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
             first = false;
@@ -848,7 +829,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
             xlast = x;
             __syncthreads();
         }
-        qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+        gbar_wait(a.gbar, G, ++bar, &ctl->error);
         // ---- GEMV (k_qp_gemv): the pivot column below j into LDS, the
         // reflector scalars from the slab partials (every workgroup)
         const double *xc = a.A + j * a.lda;
@@ -1158,14 +1139,14 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, uint32_t *flags, do
         pbeta = beta;
         pden = den;
         l = 1;
-        qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+        gbar_wait(a.gbar, G, ++bar, &ctl->error);
         int fl;
         qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
         qflag = qflag || fl;
         if ((b + 1 == nb) || (j + 1 == p) || qflag) break;  // block end: the deferred update follows
     }
     // every workgroup has read the loop state before it is written back
-    if (bar == 0) qr_barrier(flags, G, epoch0 + (++bar), &ctl->error);
+    if (bar == 0) gbar_wait(a.gbar, G, ++bar, &ctl->error);
     if (wg == 0 && tid == 0) {
         ctl->ns = ns;
         ctl->rank = rank;
@@ -1207,16 +1188,15 @@ static void qr_cache_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, 
     }
 }
 
-// One QP3 block as a persistent launch, then the block-end kernels.  Returns
-// hipErrorCooperativeLaunchTooLarge (nothing launched) when the grid cannot be
-// co-resident.
-hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
-                            int grid, hipStream_t s, hipEvent_t *ev) {
+// One QP3 block as a persistent launch, then the block-end kernels.  The grid
+// comes from qp3_block_grid (at most one workgroup per compute unit).
+hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int64_t w_bound, int grid,
+                            hipStream_t s, hipEvent_t *ev) {
     if (grid < 1 || grid > QP_RUN_MAXWG || nb < 1 || nb > QP_NBMAX || a.m > QR_XS_MAX + 1) return hipErrorInvalidValue;
     int cq = 0, crows = 0;
     size_t lds = qr_lds_bytes(a.m);
     qr_cache_shape(t_bound, w_bound, grid, &cq, &crows, &lds);
-    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.bflags, &bf.amx, &epoch0, &nb, &cq, &crows};
+    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.amx, &nb, &cq, &crows};
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     e = launch_resident((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args, (unsigned)lds, s);

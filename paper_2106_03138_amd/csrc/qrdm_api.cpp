@@ -83,7 +83,7 @@ double qp3_run_ms(int64_t launches) {
 }
 
 struct Layout {
-    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, perm_dbg, total;
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, gbar, perm_dbg, total;
 };
 
 const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
@@ -112,8 +112,9 @@ Layout make_layout(int64_t m, int64_t n) {
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
     L.fz = take(sizeof(double) * 64 * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
-    // QP3 block kernel: arrival flags, then 4 doubles of arg-max partials per workgroup
-    L.qrb = take(sizeof(uint32_t) * QP_RUN_MAXWG + sizeof(double) * 4 * QP_RUN_MAXWG);
+    // QP3 block kernel: 4 doubles of arg-max partials per workgroup
+    L.qrb = take(sizeof(double) * 4 * QP_RUN_MAXWG);
+    L.gbar = take(sizeof(uint32_t) * 8 * GBAR_STRIDE);  // grid-barrier counters (panel, QP3 block kernel)
     L.perm_dbg = take(sizeof(int32_t) * nn);
     L.total = off;
     return L;
@@ -214,8 +215,7 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
     bf.PB2 = (double *)(ws + L.pb2);
     bf.Fz = (double *)(ws + L.fz);
     bf.flag = (int32_t *)(ws + L.flag);
-    bf.bflags = (uint32_t *)(ws + L.qrb);
-    bf.amx = (double *)(ws + L.qrb + sizeof(uint32_t) * QP_RUN_MAXWG);
+    bf.amx = (double *)(ws + L.qrb);
     HIP_TRY(launch_qp3_init(a, nb, s));
     const int ring = g_ws.ring;
     const int64_t pmin = std::min(a.m, a.n);
@@ -224,17 +224,15 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
     if (grid > 0) {
         // one block of up to nb steps per launch; a snapshot after each, the
         // host waiting on the one `lag` launches back
-        HIP_TRY(hipMemsetAsync(bf.bflags, 0, sizeof(uint32_t) * QP_RUN_MAXWG, s));
         for (int64_t iter = 0;; ++iter) {
             const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
-            const uint32_t epoch0 = (uint32_t)(iter + 1) * 256u;  // > 2 nb + 2 barriers per launch
             hipEvent_t *ev = nullptr;
             if (prof && prof->on) {
                 if (grow_events(g_qp_ev, 2 * (size_t)(iter + 1)) != 0) return QRDM_ERR_NOMEM;
                 ev = g_qp_ev.data() + 2 * iter;
                 prof->launches = iter + 1;
             }
-            HIP_TRY(launch_qp3_block(a, bf, epoch0, nb, tb, wb, grid, s, ev));
+            HIP_TRY(launch_qp3_block(a, bf, nb, tb, wb, grid, s, ev));
             Snapshot *hs = g_ws.host_snap + (iter % ring);
             HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
@@ -379,6 +377,7 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     a.vn2 = (double *)(ws + L.vn2);
     a.perm = perm;
     a.tau_house = tau_house;
+    a.gbar = (uint32_t *)(ws + L.gbar);
     a.ctl = (QrdmCtl *)(ws + L.ctl);
     double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
     double *VVb = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
@@ -404,7 +403,6 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     const int rows_per_wg = panel_rows_for(m, std::min<int>(p.kmax, QK_KM));
     bool switch_qp3 = false;
     HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
-    HIP_TRY(hipMemsetAsync(ws + L.pb, 0, 16384, s));  // panel arrival flags (epochs restart with the loop state)
     int64_t ns_known = 0;
     int64_t nrec = 0;
     int64_t iter = 0;
@@ -649,6 +647,7 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     a.vn2 = (double *)(ws + L.vn2);
     a.perm = perm;
     a.tau_house = tau_house;
+    a.gbar = (uint32_t *)(ws + L.gbar);
     a.ctl = (QrdmCtl *)(ws + L.ctl);
     QrdmCtl c0 = initial_ctl();
     HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));

@@ -68,6 +68,7 @@ struct QrdmArgs {
     int32_t *perm;
     double *tau_house;
     QrdmCtl *ctl;
+    uint32_t *gbar = nullptr;  // [8 * 64]: arrival counters of the persistent kernels' grid barrier
 };
 
 // ------------------------------------------------------------------ helpers
@@ -79,6 +80,41 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int64_t p_of(const QrdmArgs &a) { return a.m < a.n ? a.m : a.n; }
+
+// Grid barrier of the persistent kernels (all G workgroups resident): workgroup
+// w adds one to counter w % 8 (one counter per group of workgroups, 256 B
+// apart, so the atomics spread), and eight threads of every workgroup poll the
+// eight counters until each holds its group's count times k, for the k-th
+// barrier of the launch.  The counters start at zero for each launch (cleared
+// by the kernel launched before it).  A workgroup's stores before the barrier
+// complete before its increment.  The wait is bounded: on timeout error bit 2
+// is raised, the kernel runs on, and later barriers no longer wait.
+#define GBAR_STRIDE 64
+#define GBAR_SPIN_LIMIT (1 << 26)
+__device__ __forceinline__ void gbar_wait(uint32_t *gbar, int G, uint32_t k, int32_t *err) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(gbar + GBAR_STRIDE * (blockIdx.x & 7), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 8 && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2)) {
+        const uint32_t target = (uint32_t)((G - (int)threadIdx.x + 7) / 8) * k;
+        int it = 0;
+        while (__hip_atomic_load(gbar + GBAR_STRIDE * threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++it > GBAR_SPIN_LIMIT) {
+                atomicOr(err, 2);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+// Clears the eight counters (the calling thread).
+__device__ __forceinline__ void gbar_clear(uint32_t *gbar) {
+    if (gbar)
+        for (int x = 0; x < 8; ++x) __hip_atomic_store(gbar + GBAR_STRIDE * x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Lane exchanges on the VALU (DPP and the gfx950 lane swaps): lane_xu<K>(v) is
 // v of lane ^ K for K = 32, 16, 8, 2, 1, and of lane ^ 7 (the mirror within
@@ -141,19 +177,16 @@ struct Qp3Bufs {
     double *PB2;      // [ceil(m/256)][2 + 2 * 64] partials of the pivot column pass
     double *Fz;       // [nb][n]: F^T of the deferred update, absolute column index
     int32_t *flag;    // [n]: partial norm needs recomputation
-    uint32_t *bflags; // [QP_RUN_MAXWG]: arrival flags of the block kernel's grid barrier
     double *amx;      // [QP_RUN_MAXWG][4]: per-workgroup arg-max partials of the block kernel
 };
 hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s);
 hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
                             int64_t w_bound, hipStream_t s);
 hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, hipStream_t s);
-// Grid of the block kernel for m rows (0: use the per-step kernels).  epoch0
-// must exceed every flag value of earlier launches by the same flags (a launch
-// raises them by at most 2 nb + 2).
+// Grid of the block kernel for m rows (0: use the per-step kernels).
 int qp3_block_grid(int64_t m);
-hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, uint32_t epoch0, int nb, int64_t t_bound, int64_t w_bound,
-                            int grid, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
+hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, int grid,
+                            hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
 int panel_rows_for(int64_t m, int kmax);
