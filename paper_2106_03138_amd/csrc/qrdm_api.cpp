@@ -114,7 +114,7 @@ Layout make_layout(int64_t m, int64_t n) {
     L.flag = take(sizeof(int32_t) * (size_t)nn);
     // QP3 block kernel: 4 doubles of arg-max partials per workgroup
     L.qrb = take(sizeof(double) * 4 * QP_RUN_MAXWG);
-    L.gbar = take(sizeof(uint32_t) * 8 * GBAR_STRIDE);  // grid-barrier counters (panel, QP3 block kernel)
+    L.gbar = take(sizeof(uint32_t) * GBAR_GROUPS * GBAR_STRIDE);  // grid-barrier counters (panel, QP3 block kernel)
     L.perm_dbg = take(sizeof(int32_t) * nn);
     L.total = off;
     return L;
