@@ -77,7 +77,10 @@ hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const dou
 // ------------------------------------------------------------ init / select
 __global__ void k_qp_init(QrdmArgs a, int nb) {
     QrdmCtl *c = a.ctl;
-    gbar_clear(a.gbar);  // for the first block kernel
+    if (a.gbar) {  // both counter sets of the block kernel (launches alternate between them)
+        gbar_clear(a.gbar);
+        gbar_clear(a.gbar + GBAR_GROUPS * GBAR_STRIDE);
+    }
     if (!c->done) c->ns += c->l;  // finish the advance of a preceding QRDM step
     c->qp_k0 = c->ns;
     c->qp3_start = c->ns;
@@ -446,7 +449,6 @@ __global__ void __launch_bounds__(256) k_qp_gemv(QrdmArgs a, double *Fz, const d
 // reflector in place.
 __global__ void __launch_bounds__(256) k_qp_close(QrdmArgs a, int32_t *flag, int nb) {
     QrdmCtl *ctl = a.ctl;
-    if (blockIdx.x == 0 && threadIdx.x == 0) gbar_clear(a.gbar);  // for the next block kernel
     if (ctl->done) return;
     int kb;
     int64_t last;
@@ -595,15 +597,15 @@ __device__ __forceinline__ void qr_dot2_batch(const double *pa, const double *pb
 extern __shared__ double qr_xs[];
 
 __global__ void __launch_bounds__(QR_THREADS)
-k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb, int cq, int crows) {
+k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb, int cq, int crows, int launch) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int G = gridDim.x, wg = blockIdx.x;
-    if (ctl->qp_stop) {  // the block closed by the stopping test is updated and normalized
-        if (wg == 0 && threadIdx.x == 0) ctl->done = 1;
-        return;
-    }
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // barrier counters: launches alternate between two sets, each clearing the
+    // other for the launch after it (the one before has finished)
+    uint32_t *gb = a.gbar + (launch & 1) * GBAR_GROUPS * GBAR_STRIDE;
+    if (wg == 0 && tid == 0) gbar_clear(a.gbar + ((launch + 1) & 1) * GBAR_GROUPS * GBAR_STRIDE);
     const int64_t p = p_of(a);
     const int npart = (int)((a.m + QP_ROWS - 1) / QP_ROWS);
     if (npart > G) {  // one row slab per workgroup at most (the host's grid ensures it)
@@ -676,7 +678,55 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
         }
         __syncthreads();
     }
+    // ---- the previous launch's block (closed at its end, its deferred update
+    // applied by k_gemm2 mode 1 since): what k_qp_close does after the per-step
+    // kernels.  Flagged partial norms of this workgroup's columns are recomputed
+    // from the updated rows below the block (one wavefront per column, the sum
+    // order of k_qp_close); after the last block the last reflector is
+    // normalized in place.
+    const bool prev = (l == 1) || qstop;
+    if (prev) {
+        const int kbp = qstop ? b : b + 1;
+        const int64_t last = k0 + kbp - 1;  // = j0 - 1
+        for (int64_t c = cw0 + wv; c < cw1; c += 4) {
+            if (!qr_ldi(flag + c)) continue;
+            double t = 0.0;
+            if (cached) {
+                const double *col = cc + (c - cw0) * crows - j0;
+                for (int64_t r = last + 1 + lane; r < a.m; r += 64) t += col[r] * col[r];
+            } else {
+                const double *col = a.A + c * a.lda;
+                for (int64_t r = last + 1 + lane; r < a.m; r += 64) {
+                    const double v = qr_ld(col + r);
+                    t += v * v;
+                }
+            }
+            t = qp_wave_sum(t);
+            if (lane == 0) {
+                const double v = sqrt(t);
+                qr_st(a.vn1 + c, v);
+                qr_st(a.vn2 + c, v);
+                qr_sti(flag + c, 0);
+                atomicAdd((unsigned long long *)&ctl->nrecompute, 1ull);
+                if (cached) {
+                    n1c[c - cw0] = v;
+                    n2c[c - cw0] = v;
+                }
+            }
+        }
+        const bool final_step = qstop || last + 1 >= p;
+        if (final_step && kbp > 0) {
+            const double rden = 1.0 / pden;
+            for (int64_t r = last + 1 + (int64_t)wg * QR_THREADS + tid; r < a.m; r += (int64_t)G * QR_THREADS)
+                a.A[last * a.lda + r] *= rden;
+            if (wg == 0 && tid == 0) a.A[last * a.lda + last] = pbeta;
+        }
+        if (final_step && qstop) done = 1;  // the stopping test closed this block: nothing follows
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     for (;;) {
+        if (done) break;
         // ---- advance past the previous step's reflector (k_qp_select)
         if (l == 1) {
             const bool closes = qstop || (b + 1 == nb) || (ns + 1 == p) || qflag;
@@ -699,11 +749,11 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
             break;
         }
         if (first) {
-            // arg-max over the columns from j, this workgroup's share, then exchange
+            // arg-max over this workgroup's columns (from j = j0), then exchange
             double bv = -1.0;
             int bj = 0x7fffffff;
-            for (int64_t c = j + (int64_t)wg * QR_THREADS + tid; c < a.n; c += (int64_t)G * QR_THREADS) {
-                const double v = qr_ld(a.vn1 + c);
+            for (int64_t c = (cw0 > j ? cw0 : j) + tid; c < cw1; c += QR_THREADS) {
+                const double v = cached ? n1c[c - cw0] : qr_ld(a.vn1 + c);
                 if (qp_better(v, (int)c, bv, bj)) { bv = v; bj = (int)c; }
             }
             qr_wg_argmax(bv, bj, s_v, s_j);
@@ -712,7 +762,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
                 qr_st(amx + 4 * wg + 1, (double)bj);
                 qr_st(amx + 4 * wg + 2, 0.0);
             }
-            gbar_wait(a.gbar, G, ++bar, &ctl->error);
+            gbar_wait(gb, G, ++bar, &ctl->error);
             int fl;
             qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
             first = false;
@@ -829,7 +879,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
             xlast = x;
             __syncthreads();
         }
-        gbar_wait(a.gbar, G, ++bar, &ctl->error);
+        gbar_wait(gb, G, ++bar, &ctl->error);
         // ---- GEMV (k_qp_gemv): the pivot column below j into LDS, the
         // reflector scalars from the slab partials (every workgroup)
         const double *xc = a.A + j * a.lda;
@@ -1139,14 +1189,14 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
         pbeta = beta;
         pden = den;
         l = 1;
-        gbar_wait(a.gbar, G, ++bar, &ctl->error);
+        gbar_wait(gb, G, ++bar, &ctl->error);
         int fl;
         qr_reduce_partials(amx, G, uv, uj, fl, s_v, s_j, s_f);
         qflag = qflag || fl;
         if ((b + 1 == nb) || (j + 1 == p) || qflag) break;  // block end: the deferred update follows
     }
     // every workgroup has read the loop state before it is written back
-    if (bar == 0) gbar_wait(a.gbar, G, ++bar, &ctl->error);
+    if (bar == 0) gbar_wait(gb, G, ++bar, &ctl->error);
     if (wg == 0 && tid == 0) {
         ctl->ns = ns;
         ctl->rank = rank;
@@ -1188,25 +1238,24 @@ static void qr_cache_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, 
     }
 }
 
-// One QP3 block as a persistent launch, then the block-end kernels.  The grid
-// comes from qp3_block_grid (at most one workgroup per compute unit).
+// One QP3 block as a persistent launch, then the deferred update.  The grid
+// comes from qp3_block_grid (at most one workgroup per compute unit); launch
+// numbers the launches of one loop from 0 (it selects the barrier counters).
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs bf, int nb, int64_t t_bound, int64_t w_bound, int grid,
-                            hipStream_t s, hipEvent_t *ev) {
+                            int launch, hipStream_t s, hipEvent_t *ev) {
     if (grid < 1 || grid > QP_RUN_MAXWG || nb < 1 || nb > QP_NBMAX || a.m > QR_XS_MAX + 1) return hipErrorInvalidValue;
     int cq = 0, crows = 0;
     size_t lds = qr_lds_bytes(a.m);
     qr_cache_shape(t_bound, w_bound, grid, &cq, &crows, &lds);
-    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.amx, &nb, &cq, &crows};
+    void *args[] = {&a, &bf.Fz, &bf.PB2, &bf.flag, &bf.amx, &nb, &cq, &crows, &launch};
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     e = launch_resident((const void *)k_qp_run, dim3(grid), dim3(QR_THREADS), args, (unsigned)lds, s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    e = launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
-    if (e != hipSuccess) return e;
-    const unsigned g_cols = (unsigned)((w_bound + 3) / 4 + 1);
-    hipLaunchKernelGGL(k_qp_close, dim3(g_cols), dim3(256), 0, s, a, bf.flag, nb);
-    return hipGetLastError();
+    // the block end: the deferred update; the next launch recomputes flagged
+    // norms and, after the last block, normalizes the last reflector
+    return launch_gemm2_qp3(a, a.A, a.lda, bf.Fz, t_bound, w_bound, s);
 }
 
 // One workgroup per compute unit (all co-resident: the kernel needs one slot

@@ -114,7 +114,7 @@ Layout make_layout(int64_t m, int64_t n) {
     L.flag = take(sizeof(int32_t) * (size_t)nn);
     // QP3 block kernel: 4 doubles of arg-max partials per workgroup
     L.qrb = take(sizeof(double) * 4 * QP_RUN_MAXWG);
-    L.gbar = take(sizeof(uint32_t) * GBAR_GROUPS * GBAR_STRIDE);  // grid-barrier counters (panel, QP3 block kernel)
+    L.gbar = take(2 * sizeof(uint32_t) * GBAR_GROUPS * GBAR_STRIDE);  // grid-barrier counters: panel, QP3 block kernel (2 sets)
     L.perm_dbg = take(sizeof(int32_t) * nn);
     L.total = off;
     return L;
@@ -232,7 +232,7 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
                 ev = g_qp_ev.data() + 2 * iter;
                 prof->launches = iter + 1;
             }
-            HIP_TRY(launch_qp3_block(a, bf, nb, tb, wb, grid, s, ev));
+            HIP_TRY(launch_qp3_block(a, bf, nb, tb, wb, grid, (int)iter, s, ev));
             Snapshot *hs = g_ws.host_snap + (iter % ring);
             HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));

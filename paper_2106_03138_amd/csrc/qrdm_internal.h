@@ -190,7 +190,7 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64
 // Grid of the block kernel for m rows (0: use the per-step kernels).
 int qp3_block_grid(int64_t m);
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, int grid,
-                            hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
+                            int launch, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
 int panel_rows_for(int64_t m, int kmax);
