@@ -62,6 +62,8 @@ hipError_t launch_init(QrdmArgs a, hipStream_t s) {
 // the new rows were computed in (FP64, or FP32 for mixed-precision updates).
 __global__ void __launch_bounds__(64 * WAVES_PER_WG) k_downdate(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
+    // the step's state is final here (the next step's selection changes it)
+    if (a.snap && blockIdx.x == 0 && threadIdx.x == 0) qrdm_write_snapshot(ctl, a.snap);
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
     const int l = ctl->l;
@@ -100,7 +102,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_WG) k_downdate(QrdmArgs a) {
 }
 
 hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s) {
-    if (w_bound <= 0) return hipSuccess;
+    if (w_bound <= 0 && !a.snap) return hipSuccess;
+    if (w_bound <= 0) w_bound = 1;  // one workgroup still writes the snapshot
     dim3 grid((unsigned)((w_bound + WAVES_PER_WG - 1) / WAVES_PER_WG));
     hipLaunchKernelGGL(k_downdate, grid, dim3(64 * WAVES_PER_WG), 0, s, a);
     return hipGetLastError();

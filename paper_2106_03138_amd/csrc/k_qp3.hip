@@ -599,7 +599,10 @@ extern __shared__ double qr_xs[];
 __global__ void __launch_bounds__(QR_THREADS)
 k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb, int cq, int crows, int launch) {
     QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (ctl->done) {
+        if (a.snap && blockIdx.x == 0 && threadIdx.x == 0) qrdm_write_snapshot(ctl, a.snap);
+        return;
+    }
     const int G = gridDim.x, wg = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // barrier counters: launches alternate between two sets, each clearing the
@@ -1213,6 +1216,7 @@ k_qp_run(QrdmArgs a, double *Fz, double *PB2, int32_t *flag, double *amx, int nb
         ctl->qp_den = pden;
         ctl->umax = umax;
         if (done) ctl->done = 1;
+        if (a.snap) qrdm_write_snapshot(ctl, a.snap);
     }
 }
 

@@ -31,6 +31,7 @@ struct Snapshot {  // first bytes of QrdmCtl copied back for polling
     int32_t l, ks, nL, done, fallback, jmax;
     double gamma, sigma_bound;
 };
+static_assert(sizeof(Snapshot) == 8 * QRDM_SNAP_WORDS, "the snapshot is the words the kernels write");
 static_assert(offsetof(Snapshot, jmax) == offsetof(QrdmCtl, jmax) &&
                   offsetof(Snapshot, gamma) == offsetof(QrdmCtl, gamma) &&
                   offsetof(Snapshot, sigma_bound) == offsetof(QrdmCtl, sigma_bound),
@@ -41,6 +42,7 @@ struct Workspace {
     size_t bytes = 0;
     char *base = nullptr;
     Snapshot *host_snap = nullptr;  // pinned ring
+    uint64_t *dev_snap = nullptr;   // its device address (written by the kernels)
     int ring = 0;
     std::vector<hipEvent_t> events;
 };
@@ -167,7 +169,10 @@ int ensure_workspace(size_t bytes, int ring) {
         return QRDM_ERR_NOMEM;
     }
     int r = std::max(ring, 8);
-    if (hipHostMalloc((void **)&g_ws.host_snap, sizeof(Snapshot) * r, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&g_ws.host_snap, sizeof(Snapshot) * r, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&g_ws.dev_snap, g_ws.host_snap, 0) != hipSuccess) {
+        if (g_ws.host_snap) (void)hipHostFree(g_ws.host_snap);
+        g_ws.host_snap = nullptr;
         (void)hipFree(g_ws.base);
         g_ws.base = nullptr;
         return QRDM_ERR_NOMEM;
@@ -232,9 +237,9 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
                 ev = g_qp_ev.data() + 2 * iter;
                 prof->launches = iter + 1;
             }
-            HIP_TRY(launch_qp3_block(a, bf, nb, tb, wb, grid, (int)iter, s, ev));
-            Snapshot *hs = g_ws.host_snap + (iter % ring);
-            HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+            QrdmArgs al = a;
+            al.snap = g_ws.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block kernel
+            HIP_TRY(launch_qp3_block(al, bf, nb, tb, wb, grid, (int)iter, s, ev));
             HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
             if (iter >= lag) {
                 const int64_t k = iter - lag;
@@ -431,10 +436,12 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (ev) HIP_TRY(hipEventRecord(ev[2], s));
         HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, s,
                              ev ? ev + 3 : nullptr));
-        HIP_TRY(launch_downdate(a, wb, s));
+        {
+            QrdmArgs al = a;
+            al.snap = g_ws.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the downdate kernel
+            HIP_TRY(launch_downdate(al, wb, s));
+        }
         if (ev) HIP_TRY(hipEventRecord(ev[7], s));
-        Snapshot *hs = g_ws.host_snap + (iter % ring);
-        HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
         if (iter >= lag) {
             const int64_t k = iter - lag;

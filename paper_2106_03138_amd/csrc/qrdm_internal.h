@@ -69,9 +69,18 @@ struct QrdmArgs {
     double *tau_house;
     QrdmCtl *ctl;
     uint32_t *gbar = nullptr;  // [GBAR_GROUPS * GBAR_STRIDE]: counters of the persistent kernels' grid barrier
+    uint64_t *snap = nullptr;  // host-mapped slot for the polled prefix of the control block (or none)
 };
 
 // ------------------------------------------------------------------ helpers
+// The host polls the first QRDM_SNAP_WORDS 8-byte words of QrdmCtl (n_s, rank,
+// l, k_s, |L|, done, fallback, arg-max, gamma, bound).  The last kernel of a
+// step writes them into a slot of pinned host memory, so no copy is queued.
+#define QRDM_SNAP_WORDS 7
+__device__ __forceinline__ void qrdm_write_snapshot(const QrdmCtl *c, uint64_t *dst) {
+    const uint64_t *src = (const uint64_t *)c;
+    for (int i = 0; i < QRDM_SNAP_WORDS; ++i) dst[i] = src[i];
+}
 __device__ __forceinline__ double wave_sum(double v) {
     // fixed-order butterfly over the 64 lanes of a wavefront
 #pragma unroll
