@@ -198,21 +198,34 @@ __device__ __forceinline__ double zs_step(const double *vc, const double *Ys, in
 // a >= l have tau = 0 and vanish.  Z on FP64 MFMA (16x16x4): A = T^T, B = Y.
 __device__ __forceinline__ void zs_tmat(const double *VVf, double *Tm, double *Mt, const double *taus) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // diagonal blocks: wavefront w < 4 forms rows/columns [16w, 16w + 16)
+    // diagonal blocks: wavefront w < 4 forms rows/columns [16w, 16w + 16), lane
+    // r holding its row in registers; column i's v_b^T v_i are the same in
+    // every lane and are read before the row's recurrence uses them
     if (wv < 4 && lane < 16) {
         const int base = 16 * wv, r = lane;
-        double *trow = Tm + (base + r) * ZT_LD + base;
+        double tr[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) tr[i] = 0.0;
+#pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int ia = base + i;
+            double vc[16];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) vc[b] = b < i ? VVf[(base + b) * ZT_LD + ia] : 0.0;
             if (r < i) {
                 double x = 0.0;
+#pragma unroll
                 for (int b = 0; b < 16; ++b)
-                    if (b >= r && b < i) x += trow[b] * VVf[(base + b) * ZT_LD + ia];
-                trow[i] = -taus[ia] * x;
+                    if (b >= r && b < i) x += tr[b] * vc[b];
+                tr[i] = -taus[ia] * x;
             } else if (r == i) {
-                trow[i] = taus[ia];
+                tr[i] = taus[ia];
             }
         }
+        double *trow = Tm + (base + r) * ZT_LD + base;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i >= r) trow[i] = tr[i];
     }
     __syncthreads();
     for (int sh = 16; sh < 64; sh *= 2) {
