@@ -57,6 +57,23 @@ def residual(a: np.ndarray, qr: np.ndarray, tau: np.ndarray, perm: np.ndarray, n
     return float(np.linalg.norm(qtap - r_factor(qr, nref)) / (na if na > 0 else 1.0))
 
 
+def sampled_residual(a: np.ndarray, qr: np.ndarray, tau: np.ndarray, perm: np.ndarray, nref: int,
+                     cols) -> float:
+    """Estimate of ||A P - Q R||_F / ||A||_F from the columns `cols` of A P alone:
+    sqrt(n / |cols| * sum_j ||Q^T A P e_j - R e_j||^2) / ||A||_F.  Equal to residual()
+    when cols lists every column once."""
+    cols = np.asarray(cols, dtype=np.int64)
+    n = a.shape[1]
+    qtap = apply_qt(qr, tau, a[:, np.asarray(perm)[cols]], nref)
+    r = np.array(qr[:, cols], copy=True)
+    for c, j in enumerate(cols):
+        if j < nref:
+            r[j + 1:, c] = 0.0
+    na = np.linalg.norm(a)
+    est = np.sqrt(n / len(cols) * np.sum((qtap - r) ** 2))
+    return float(est / (na if na > 0 else 1.0))
+
+
 def orthogonality(qr: np.ndarray, tau: np.ndarray, nref: int) -> float:
     """max |Q^T Q - I| over the full m x m Q."""
     m = qr.shape[0]

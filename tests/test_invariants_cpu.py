@@ -1,0 +1,97 @@
+"""Pins of the size-independent factorization checks (tests/invariants.py) and of
+the sampled backward error, on the oracle's own factorizations (CPU only).
+
+The checks read Algorithm 1's candidate and greedy rules, the single-pivot rule
+and the practical stopping criterion (Section 4) off the final R; they must hold
+on the oracle's factorizations, and each must fail on a factorization with a
+planted mistake."""
+import numpy as np
+import pytest
+
+import invariants as V
+import oracle
+from oracle import metrics as M
+from paper_2106_03138_amd import inputs as I
+
+
+def _blocks(res):
+    return [(b.ns, b.nL, b.ks, b.l) for b in res.blocks]
+
+
+@pytest.fixture(scope="module")
+def geo():
+    n = 384
+    a = I.from_spectrum(448, n, np.geomspace(1.0, 1e-16, n), 5)
+    res = oracle.qrdm(a, tau=0.15, delta=0.9, kmax=32, stop_rule=oracle.STOP_NONE)
+    return a, res
+
+
+def test_invariants_hold_on_oracle(geo):
+    a, res = geo
+    n = a.shape[1]
+    starts = V.check_blocks(res.qr, _blocks(res), 0.15, 0.9, n)
+    assert any(b.l > 1 for b in res.blocks)
+    V.check_reflectors(res.qr, res.tau, n)
+    r, margin = V.paper_rule_rank(res.qr, np.linalg.norm(a, axis=0).max(), starts)
+    assert margin > 1e-6
+    assert r == res.rank
+
+
+def test_sampled_residual_matches_full(geo):
+    a, res = geo
+    n = a.shape[1]
+    full = M.residual(a, res.qr, res.tau, res.perm, n)
+    assert M.sampled_residual(a, res.qr, res.tau, res.perm, n, np.arange(n)) == pytest.approx(full, rel=1e-12)
+    # a planted error x in one sampled column of R is seen at sqrt(n / |S|) x / ||A||_F
+    qr = res.qr.copy()
+    cols = np.array([3, 50, 200])
+    qr[1, 50] += 1e-6
+    est = M.sampled_residual(a, qr, res.tau, res.perm, n, cols)
+    assert est == pytest.approx(np.sqrt(n / 3) * 1e-6 / np.linalg.norm(a), rel=1e-3)
+    assert M.sampled_residual(a, qr, res.tau, res.perm, n, np.array([3, 200])) < 1e-13
+
+
+def test_planted_column_swap_fails(geo):
+    a, res = geo
+    n = a.shape[1]
+    b = next(b for b in res.blocks if b.l > 1)
+    qr = res.qr.copy()
+    # a block column that was not the largest, shrunk below tau * max
+    c2 = V.suffix_norms2(qr)[b.ns, b.ns:b.ns + b.l]
+    j = b.ns + int(np.argmin(c2))
+    qr[:, j] *= 0.1
+    with pytest.raises(AssertionError, match="tau"):
+        V.check_blocks(qr, _blocks(res), 0.15, 0.9, n, tail_single=False)
+
+
+def test_planted_single_pivot_fails(geo):
+    a, res = geo
+    n = a.shape[1]
+    qr = res.qr.copy()
+    j = n - 40  # a single-pivot step of the noise-level tail
+    qr[:, [j, j + 1]] = qr[:, [j + 1, j]]
+    qr[j + 1, j] = 0.0
+    qr[j, j] *= 1e-3
+    with pytest.raises(AssertionError, match="largest norm"):
+        V.check_blocks(qr, _blocks(res), 0.15, 0.9, n)
+
+
+def test_planted_parallel_pair_fails():
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal((60, 8))
+    a[:, 0] *= 3.0
+    a[:, 1] = a[:, 0] * 0.99 + 1e-3 * rng.standard_normal(60)
+    # an unpivoted R of [a_0 a_1 ...]: a block that claims the parallel pair
+    r = np.zeros((60, 8))
+    r[:8] = np.linalg.qr(a, mode="r")
+    with pytest.raises(AssertionError, match="cos"):
+        V.check_blocks(r, [(0, 2, 2, 2)], 0.15, 0.9, 8, tail_single=False)
+
+
+def test_planted_reflector_fails(geo):
+    a, res = geo
+    n = a.shape[1]
+    tau = res.tau.copy()
+    tau[7] *= 1 + 1e-8
+    with pytest.raises(AssertionError, match="orthogonal"):
+        V.check_reflectors(res.qr, tau, n)
