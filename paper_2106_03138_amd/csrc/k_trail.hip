@@ -382,7 +382,7 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
 // from the first trailing column).  MODE 1: closing a QP3 block (rows and
 // columns from last + 1, K = kb, Z = F^T indexed by absolute column).
 template <typename T, int MODE>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, sizeof(T) == 8 ? 4 : 1)
 k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ Z, int64_t ldz) {
     const QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
@@ -441,8 +441,10 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
             }
             if constexpr (!F64) acc[tc * 2 + tr] = acc_t{0, 0, 0, 0};
         }
-    for (int kc = 0; kc < l; kc += G2_KC) {
-        T vr[4], zr[4];
+    // the V and Z chunks go through registers to LDS; the next chunk's loads are
+    // issued before this chunk's MFMAs so that their latency overlaps them
+    T vr[4], zr[4];
+    auto load_chunk = [&](int kc) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = u * 512 + tid, k = e >> 7, r = e & 127;
@@ -455,6 +457,9 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
             }
             zr[u] = (kok && r < ncol) ? Z[(int64_t)(kc + k) * ldz + jb + r] : (T)0;
         }
+    };
+    load_chunk(0);
+    for (int kc = 0; kc < l; kc += G2_KC) {
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -462,7 +467,8 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
             Zs[u * 512 + tid] = zr[u];
         }
         __syncthreads();
-#pragma unroll
+        if (kc + G2_KC < l) load_chunk(kc + G2_KC);
+#pragma unroll 2
         for (int k = 0; k < G2_KC; k += 4) {
             T zo[4], vo[2];
 #pragma unroll
