@@ -11,8 +11,9 @@ step).  The stopping criterion is off (full factorization) so QRDM and QRP do
 equal work; TFLOP/s uses the algorithmic count F = 2mn^2 - 2n^3/3.
 
 One JSON line is printed.  Besides the contract fields it carries:
-  roofline      the dominant kernel (trailing GEMM) measured live with HIP events
-                inside the library, against the FP64 MFMA peak;
+  roofline      the kernel with the largest summed time, its average launch
+                duration measured live with HIP events inside the library, against
+                the roofline that bounds it (HBM bandwidth or FP64 MFMA);
   cpu_baseline  the CPU oracle timed on the host cores on a bounded sample (the
                 first columns of the same matrix);
   qrp           the GPU QRP baseline on the same matrix and its speedup.
@@ -31,32 +32,6 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-
-
-def make_input(n, spectrum, seed, torch):
-    """Seeded synthetic n x n matrix on the GPU (column-major float64).
-    geometric: sigma 1 -> 1e-16; stairs: steps of 512 dropping 10x; gaussian: N(0,1).
-    U, V are Haar: QR of seeded host Gaussians (signs fixed), formed on the GPU."""
-    rng = np.random.default_rng(seed)
-    if spectrum == "gaussian":
-        a = torch.from_numpy(rng.standard_normal((n, n))).cuda()
-        return a.t().contiguous().t()
-    if spectrum == "geometric":
-        s = np.geomspace(1.0, 1e-16, n)
-    elif spectrum == "stairs":
-        s = 10.0 ** (-np.floor(np.arange(n) / 512))
-    else:
-        raise ValueError(spectrum)
-
-    def haar():
-        g = torch.from_numpy(rng.standard_normal((n, n))).cuda()
-        q, r = torch.linalg.qr(g)
-        return q * torch.sign(torch.diagonal(r))[None, :]
-
-    u, v = haar(), haar()
-    a = (u * torch.from_numpy(s).cuda()[None, :]) @ v.t()
-    del u, v
-    return a.t().contiguous().t()  # column-major (m, n) view
 
 
 def flops_full(m, n):
@@ -319,12 +294,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a design "
-              "note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
+              "described in the design notes, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
     import paper_2106_03138_amd as Q
+    from paper_2106_03138_amd import inputs as I
 
     Q.load()
     torch.cuda.set_device(0)
@@ -342,7 +318,7 @@ def main():
     if args.input_cache and os.path.exists(args.input_cache):
         a0 = torch.from_numpy(np.load(args.input_cache)).cuda().t()  # stored as the (n, m) row-major A^T
     else:
-        a0 = make_input(n, args.spectrum, args.seed, torch)
+        a0 = I.device_matrix(n, args.spectrum, args.seed, torch)
         if args.input_cache:
             np.save(args.input_cache, a0.t().contiguous().cpu().numpy())
     A = torch.empty_like(a0.t().contiguous()).t()

@@ -36,6 +36,19 @@ def apply_qt(qr: np.ndarray, tau: np.ndarray, x: np.ndarray, nref: int) -> np.nd
     return y
 
 
+def apply_qt_blocked(qr: np.ndarray, tau: np.ndarray, x: np.ndarray, nref: int) -> np.ndarray:
+    """Q^T x (x 2-D) by LAPACK dormqr: the blocked application of the same
+    reflectors, for large sizes; apply_qt is the plain definition."""
+    y = np.asfortranarray(x, dtype=np.float64)
+    if nref <= 0:
+        return np.array(y, copy=True)
+    v = np.asfortranarray(qr[:, :nref])
+    t = np.ascontiguousarray(tau[:nref], dtype=np.float64)
+    out, _, info = lapack.dormqr("L", "T", v, t, y, max(1, 64 * y.shape[1]))
+    assert info == 0
+    return out
+
+
 def apply_q(qr: np.ndarray, tau: np.ndarray, x: np.ndarray, nref: int) -> np.ndarray:
     """Q x."""
     y = np.array(x, dtype=np.float64, copy=True)
@@ -64,7 +77,7 @@ def sampled_residual(a: np.ndarray, qr: np.ndarray, tau: np.ndarray, perm: np.nd
     when cols lists every column once."""
     cols = np.asarray(cols, dtype=np.int64)
     n = a.shape[1]
-    qtap = apply_qt(qr, tau, a[:, np.asarray(perm)[cols]], nref)
+    qtap = apply_qt_blocked(qr, tau, a[:, np.asarray(perm)[cols]], nref)
     r = np.array(qr[:, cols], copy=True)
     for c, j in enumerate(cols):
         if j < nref:

@@ -216,3 +216,29 @@ def lstsq_factors(m: int, n: int, r: int, seed):
     tau = rng.uniform(0.5, 1.0, p)
     perm = rng.permutation(n).astype(np.int32)
     return np.asfortranarray(qr), tau, perm
+
+
+def device_matrix(n: int, spectrum: str, seed: int, torch):
+    """Seeded synthetic n x n matrix on the GPU (column-major float64), the benchmark workload.
+    geometric: sigma 1 -> 1e-16; stairs: steps of 512 dropping 10x; gaussian: N(0,1).
+    U, V are Haar: QR of seeded host Gaussians (signs fixed), formed on the GPU."""
+    rng = np.random.default_rng(seed)
+    if spectrum == "gaussian":
+        a = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+        return a.t().contiguous().t()
+    if spectrum == "geometric":
+        s = np.geomspace(1.0, 1e-16, n)
+    elif spectrum == "stairs":
+        s = 10.0 ** (-np.floor(np.arange(n) / 512))
+    else:
+        raise ValueError(spectrum)
+
+    def haar():
+        g = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+        q, r = torch.linalg.qr(g)
+        return q * torch.sign(torch.diagonal(r))[None, :]
+
+    u, v = haar(), haar()
+    a = (u * torch.from_numpy(s).cuda()[None, :]) @ v.t()
+    del u, v
+    return a.t().contiguous().t()  # column-major (m, n) view

@@ -41,7 +41,12 @@ def test_sampled_residual_matches_full(geo):
     a, res = geo
     n = a.shape[1]
     full = M.residual(a, res.qr, res.tau, res.perm, n)
-    assert M.sampled_residual(a, res.qr, res.tau, res.perm, n, np.arange(n)) == pytest.approx(full, rel=1e-12)
+    # LAPACK's blocked Q^T against the reflector-by-reflector definition
+    assert M.sampled_residual(a, res.qr, res.tau, res.perm, n, np.arange(n)) == pytest.approx(full, rel=1e-6)
+    x = np.random.default_rng(4).standard_normal((a.shape[0], 7))
+    d = M.apply_qt_blocked(res.qr, res.tau, x, n) - M.apply_qt(res.qr, res.tau, x, n)
+    assert np.max(np.abs(d)) <= 1e-13 * np.linalg.norm(x)
+    assert np.array_equal(M.apply_qt_blocked(res.qr, res.tau, x, 0), x)
     # a planted error x in one sampled column of R is seen at sqrt(n / |S|) x / ||A||_F
     qr = res.qr.copy()
     cols = np.array([3, 50, 200])
