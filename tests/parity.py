@@ -15,10 +15,12 @@ EPS = np.finfo(np.float64).eps
 ETA = 1e-10
 
 
-def compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=True, full=False, residual_cols=None):
+def compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=True, full=False, residual_cols=None,
+            norm2=None):
     """full: the factorization ran to min(m, n) reflectors (stop rule NONE).
     residual_cols: estimate the backward error from these columns of AP only (for
-    sizes where applying Q^T to all of AP is too slow on the host)."""
+    sizes where applying Q^T to all of AP is too slow on the host).
+    norm2: ||A||_2 when known by construction (an SVD of a large A is slow)."""
     m, n = a.shape
     k = ref.first_low_margin_block(ETA)
     ns_cut = ref.blocks[k].ns if k < len(ref.blocks) else min(m, n)
@@ -41,7 +43,7 @@ def compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=Tr
     else:
         assert M.sampled_residual(a, qr, tau, perm, nref, residual_cols) <= 1e-13
     # R agrees normwise with the oracle's on the common prefix
-    na = np.linalg.norm(a, 2)
+    na = np.linalg.norm(a, 2) if norm2 is None else norm2
     p = min(ns_cut, nref)
     if p == 0:
         return
