@@ -128,7 +128,7 @@ __device__ __forceinline__ void pn_update(double *S, int ksp, int r0, int nrows,
 }
 
 __global__ void __launch_bounds__(PN_THREADS)
-k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv) {
+k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv, int rows) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
@@ -141,7 +141,12 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
     const int64_t t = a.m - ns;
     const int P = gridDim.x;
     const int wg = blockIdx.x;
-    const int rp = (int)((t + P - 1) / P);
+    // the slabs depend on the trailing size t alone, whatever the grid, and so do
+    // the partial dots and the bits of the result: ceil(t / rows) slabs of equal
+    // height (the host sizes the grid from a bound on t; workgroups past the
+    // last slab hold no rows)
+    const int pact = (int)((t + rows - 1) / rows);  // slabs holding rows (<= P)
+    const int rp = (int)((t + pact - 1) / pact);    // <= rows
     const int64_t g0 = ns + (int64_t)wg * rp;  // first global row of this slab
     int64_t nr64 = a.m - g0;
     if (nr64 < 0) nr64 = 0;
@@ -236,12 +241,12 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
         const double *pb0 = part + (size_t)(round & 1) * P * (2 * QK_KM);
         {
             const int my_e = tid % nval, my_g = tid / nval;
-            const int wper = (P + gpv - 1) / gpv;
+            const int wper = (pact + gpv - 1) / gpv;
             if (my_g < gpv) {
                 const int seg = my_e / ks, jj = my_e - seg * ks;
                 const int o = seg * QK_KM + jj;
                 const int w0 = my_g * wper;
-                const int w1 = (w0 + wper < P) ? w0 + wper : P;
+                const int w1 = (w0 + wper < pact) ? w0 + wper : pact;
                 double s = 0.0;
                 for (int wb = w0; wb < w1; wb += 16) {
                     double v[16];
@@ -467,6 +472,6 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *V
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    void *args[] = {&a, &PB, &VV, &Vw, &Vw32, &ldv};
+    void *args[] = {&a, &PB, &VV, &Vw, &Vw32, &ldv, &rows_per_wg};
     return launch_resident((const void *)k_panel, dim3(P), dim3(PN_THREADS), args, (unsigned)lds, s);
 }

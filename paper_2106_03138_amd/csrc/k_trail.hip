@@ -67,12 +67,28 @@ __device__ __forceinline__ double ld_coh(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The split of GEMM1's row range, from the actual trailing sizes (t rows, w
+// columns) alone, so that the bits of the result do not depend on the launch
+// bounds the host passes: at most G1_TARGET_WGS workgroups (one wave over the
+// compute units: one more split past it would start a second wave), at most
+// QK_SPLIT_MAX splits of at least 256 rows, krows a multiple of G1_KC.  Both
+// GEMM1 and the partial sum in k_zsum take it from here.
+__device__ __forceinline__ int g1_krows(int64_t t, int64_t w) {
+    const int ntile = (int)((w + G1_NT - 1) / G1_NT);
+    int ns = G1_TARGET_WGS / ntile;
+    if (ns > QK_SPLIT_MAX) ns = QK_SPLIT_MAX;
+    const int64_t maxs = (t + 255) / 256;
+    if (ns > maxs) ns = (int)maxs;
+    if (ns < 1) ns = 1;
+    return (int)(((t + ns - 1) / ns + G1_KC - 1) / G1_KC * G1_KC);
+}
+
 // Split-K: workgroup (x, y, z) forms rows [64z, 64z+64) of the partial
 // Y_y = V^T A_tr over rows [y*krows, (y+1)*krows) of A_tr, for trailing columns
 // [256x, 256x+256), and writes it to Yp[y] (k_zsum, the next launch, sums them).
 template <typename T>
 __global__ void __launch_bounds__(G1_TH)
-k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ldz, int krows) {
+k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ldz) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
@@ -82,13 +98,16 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
     const int64_t w2 = a.n - c0;
     const int64_t jb = (int64_t)blockIdx.x * G1_NT;
     if (l <= 0 || jb >= w2 || t <= 0) return;
+    const int krows = g1_krows(t, w2);
     const int nsplit = (int)((t + krows - 1) / krows);
     const int lt = (l + 15) >> 4;
     const int nz = (lt + 3) >> 2;
     const int sp = blockIdx.y, zg = blockIdx.z;
-    if (sp >= nsplit || zg >= nz) return;
-    if (blockIdx.x == 0 && sp == 0 && zg == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && sp == 0 && zg == 0 && threadIdx.x == 0) {
         ctl->flop_gemm += 2.0 * (double)t * (double)l * (double)w2;
+        if (nsplit > (int)gridDim.y) atomicOr(&ctl->error, 4);  // a split without a workgroup
+    }
+    if (sp >= nsplit || zg >= nz) return;
     const int64_t rb = (int64_t)sp * krows;
     const int64_t re = (rb + krows < t) ? rb + krows : t;
     const int q0 = 64 * zg;                 // first reflector of this row group
@@ -281,8 +300,7 @@ __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int
 // Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
 template <typename T>
 __global__ void __launch_bounds__(G1_TH)
-k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz,
-       int krows) {
+k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) return;
     const int64_t ns = ctl->ns;
@@ -291,6 +309,7 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
     const int64_t w2 = a.n - (ns + ks);
     const int64_t cb = (int64_t)blockIdx.x * 64;
     if (l <= 0 || cb >= w2 || t <= 0) return;
+    const int krows = g1_krows(t, w2);
     const int nsplit = (int)((t + krows - 1) / krows);
     const int ncols = (int)((w2 - cb) < 64 ? (w2 - cb) : 64);
     const int tid = threadIdx.x;
@@ -505,18 +524,23 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
 }
 
 hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, hipStream_t s,
-                        hipEvent_t *ev) {
+                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, int64_t w_lo,
+                        hipStream_t s, hipEvent_t *ev) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     const int64_t ldz = a.n;
     const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
-    // splits: aim at ~G1_TARGET_WGS workgroups, at most QK_SPLIT_MAX, at least 256 rows each
-    int nsplit = (G1_TARGET_WGS + ntile - 1) / ntile;
+    // enough splits for any trailing size within the bounds: g1_krows picks the
+    // split on the device (at most 16, at most t/256, at most G1_TARGET_WGS over
+    // the column tiles of the narrowest possible w); workgroups past it return
+    int64_t nsplit = (t_bound + 255) / 256;
     if (nsplit > QK_SPLIT_MAX) nsplit = QK_SPLIT_MAX;
-    int64_t maxs = (t_bound + 255) / 256;
-    if (nsplit > maxs) nsplit = (int)maxs;
+    {
+        const int64_t wl = w_lo > 1 ? w_lo : 1;
+        const int64_t nt_lo = (wl + G1_NT - 1) / G1_NT;
+        const int64_t by_wgs = G1_TARGET_WGS / nt_lo;
+        if (nsplit > by_wgs) nsplit = by_wgs;
+    }
     if (nsplit < 1) nsplit = 1;
-    int krows = (int)(((t_bound + nsplit - 1) / nsplit + G1_KC - 1) / G1_KC * G1_KC);
     const int kk = a.kmax < QK_KM ? a.kmax : QK_KM;
     dim3 g1((unsigned)ntile, (unsigned)nsplit, (unsigned)((((kk + 15) >> 4) + 3) >> 2));
     dim3 g2((unsigned)((w_bound + G2_NT - 1) / G2_NT), (unsigned)((t_bound + G2_MT - 1) / G2_MT));
@@ -539,13 +563,11 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const dim3 gz((unsigned)((w_bound + 63) / 64));
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0) {
-        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz, krows);
-        hipLaunchKernelGGL(k_zsum<double>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz,
-                           krows);
+        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz);
+        hipLaunchKernelGGL(k_zsum<double>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
     } else {
-        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz, krows);
-        hipLaunchKernelGGL(k_zsum<float>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz,
-                           krows);
+        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz);
+        hipLaunchKernelGGL(k_zsum<float>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);

@@ -434,7 +434,11 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
         if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, s,
+        // the device is at most lag + 1 blocks of at most kmax columns ahead of
+        // ns_known, and the block's own k_s <= kmax columns leave the trailing
+        // part (one block more of slack; k_gemm1 flags a grid that is too small)
+        const int64_t wlo = wb - (int64_t)(lag + 3) * p.kmax;
+        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, wlo, s,
                              ev ? ev + 3 : nullptr));
         {
             QrdmArgs al = a;

@@ -178,9 +178,11 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *V
 // VV: v_a^T v_i (a < i) at VV[a * QK_KM + i], from the panel.
 // ev (may be null): 4 events recorded before GEMM1, after GEMM1, before GEMM2, after GEMM2
 // Yp: QK_SPLIT_MAX x QK_KM x n partials of V^T A (k_gemm1), summed by k_zsum
+// t_bound, w_bound: upper bounds on the trailing rows and columns; w_lo: a lower
+// bound on the trailing columns (sizes GEMM1's split grid)
 hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, hipStream_t s,
-                        hipEvent_t *ev);
+                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, int64_t w_lo,
+                        hipStream_t s, hipEvent_t *ev);
 hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s);
 
 // QP3 (LAPACK xgeqp3-style) column loop: either one block of up to nb steps

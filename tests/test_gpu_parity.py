@@ -170,3 +170,27 @@ def test_deterministic():
         o = Q.qrdm_factor(A, stop_rule=oracle.STOP_NONE)
         outs.append((Q.host_matrix(A), o.perm.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bits_independent_of_poll_lag(precision):
+    """The host polls the device's progress `poll_lag` steps behind and sizes the
+    launches from that bound; the kernels take every split from the actual sizes,
+    so the blocks of Algorithm 4 come out the same to the bit for any lag, with or
+    without the block log (which polls every step).  The scalar-pivoting tail
+    starts where the host sees the switch, up to poll_lag single-column steps
+    late, so its rounding may differ: the comparison stops at its first step."""
+    Q = _gpu()
+    a = I.from_spectrum(1500, 1300, np.geomspace(1.0, 1e-16, 1300), 9)
+    outs = []
+    fb = None
+    for lag, log in [(4, True), (0, False), (1, False), (4, False), (9, False)]:
+        A = Q.device_matrix(a)
+        o = Q.qrdm_factor(A, stop_rule=oracle.STOP_NONE, precision=precision, poll_lag=lag, log=log)
+        if log:
+            fb = next(x[0] for x in o.blocks if x[4])
+        outs.append((Q.host_matrix(A), o.tau_house.cpu().numpy(), o.perm.cpu().numpy()))
+    assert fb > 100
+    for qr, tau, perm in outs[1:]:
+        assert np.array_equal(qr[:, :fb], outs[0][0][:, :fb]) and np.array_equal(tau[:fb], outs[0][1][:fb])
+        assert np.array_equal(perm[:fb], outs[0][2][:fb])
