@@ -27,7 +27,10 @@
  *     rows/columns >= r hold the updated trailing block R22 (not triangular),
  *     so A_in[:, perm] = Q [R11 R12; 0 R22] exactly.
  *   - Return codes: 0 = success; -i = the i-th argument is invalid (checked
- *     before any launch; nothing is written); QRDM_ERR_* > 0 otherwise.
+ *     before any launch; nothing is written); QRDM_ERR_* > 0 otherwise.  A
+ *     failure the kernels detect themselves (a bounded grid-wide wait that
+ *     timed out, a launch grid smaller than a kernel's partition) returns
+ *     QRDM_ERR_HIP + hipErrorLaunchTimeOut; A then holds partial results.
  *   - Calls are not re-entrant: two concurrent calls on one device share the
  *     cached workspace and must be serialized by the caller.
  */

@@ -22,9 +22,10 @@ struct QrdmCtl {
     double sigma_bound;  // and the lower bound of their sigma_min (0 if the lemma does not apply)
     int32_t nswap;     // column moves of the current step
     int32_t nonfinite; // set by the norm sweep
-    int32_t error;     // bit 1: a grid barrier timed out
-    uint32_t bar;      // grid barrier counter of the cooperative panel
-    uint32_t bar2;     // second counter (QRP kernels)
+    int32_t error;     // 2: a grid barrier wait timed out; 4: a launch grid smaller
+                       // than the kernel's partition (host sizing); either fails the call
+    uint32_t bar;      // unused (the grid barriers count in the workspace's gbar sets)
+    uint32_t bar2;     // unused
     double amax;       // max initial column norm
     double umax;       // max partial norm of the current step
     double eps_s;      // panel break threshold tau*umax
