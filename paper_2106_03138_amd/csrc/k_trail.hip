@@ -272,14 +272,16 @@ __device__ __forceinline__ void zs_tmat(const double *VVf, double *Tm, double *M
     }
 }
 
-template <typename T>
+template <typename T, int CW>
 __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int l, int ncols, T *__restrict__ Z,
                                          int64_t ldz, int64_t cb) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // Z = T^T Y: wavefront w takes output tiles 2w and 2w + 1 of the 4 x 4 grid
+    // Z = T^T Y over 4 x (CW / 16) output tiles: wavefront w takes tiles
+    // CW/32 w .. CW/32 w + CW/32 - 1 (two for 64 columns, one for 32)
+    constexpr int TW = CW / 16, PER = CW / 32;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int q = 2 * wv + h, ta = q >> 2, tj = q & 3;
+    for (int h = 0; h < PER; ++h) {
+        const int q = PER * wv + h, ta = q / TW, tj = q % TW;
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
         const int i = lane & 15, k = lane >> 4;
         for (int kb = 0; kb < 16 * ta + 16; kb += 4) {  // T_{b,a} = 0 for b > a
@@ -298,7 +300,7 @@ __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int
 // Z for 64 trailing columns per workgroup: Y = the k_gemm1 partials summed in
 // split order, then Z = T^T Y (l <= 64, explicit T) or the recurrence
 // Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
-template <typename T>
+template <typename T, int CW>
 __global__ void __launch_bounds__(G1_TH)
 k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz) {
     QrdmCtl *ctl = a.ctl;
@@ -307,14 +309,18 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
     const int ks = ctl->ks, l = ctl->l;
     const int64_t t = a.m - ns;
     const int64_t w2 = a.n - (ns + ks);
-    const int64_t cb = (int64_t)blockIdx.x * 64;
+    const int64_t cb = (int64_t)blockIdx.x * CW;
     if (l <= 0 || cb >= w2 || t <= 0) return;
     const int krows = g1_krows(t, w2);
     const int nsplit = (int)((t + krows - 1) / krows);
-    const int ncols = (int)((w2 - cb) < 64 ? (w2 - cb) : 64);
+    const int ncols = (int)((w2 - cb) < CW ? (w2 - cb) : CW);
     const int tid = threadIdx.x;
     const int lp = ((l + 15) >> 4) * 16;
     const bool xt = l <= 64;  // explicit-T path
+    if (CW != 64 && !xt) {    // the recurrence takes 64 columns (the host picks CW from kmax)
+        if (blockIdx.x == 0 && tid == 0) atomicOr(&ctl->error, 4);
+        return;
+    }
     const int ldy = xt ? ZT_LD : ZS_LDY;
     extern __shared__ double zs_lds[];
     double *Ys = zs_lds;                           // [lp][ldy]
@@ -342,12 +348,13 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
     }
     // every split's partial of an element is loaded before any is summed
     // (QK_SPLIT_MAX loads in flight per element), then summed in split order
-    for (int e0 = 0; e0 < l * 64; e0 += G1_TH * 2) {
+    constexpr int CS = CW == 64 ? 6 : 5;  // log2 CW
+    for (int e0 = 0; e0 < l * CW; e0 += G1_TH * 2) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int e = e0 + u * G1_TH + tid;
-            const int aa = e >> 6, j = e & 63;
-            const bool ok = e < l * 64 && j < ncols;
+            const int aa = e >> CS, j = e & (CW - 1);
+            const bool ok = e < l * CW && j < ncols;
             double v[QK_SPLIT_MAX];
 #pragma unroll
             for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2)
@@ -355,13 +362,13 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
             double sum = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
-            if (e < l * 64) Ys[aa * ldy + j] = sum;
+            if (e < l * CW) Ys[aa * ldy + j] = sum;
         }
     }
     if (xt) {
-        for (int e = l * 64 + tid; e < 64 * 64; e += G1_TH) Ys[(e >> 6) * ldy + (e & 63)] = 0.0;  // rows a >= l
+        for (int e = l * CW + tid; e < 64 * CW; e += G1_TH) Ys[(e >> CS) * ldy + (e & (CW - 1))] = 0.0;  // rows a >= l
         __syncthreads();
-        zs_apply<T>(Ys, Tm, l, ncols, Z, ldz, cb);
+        zs_apply<T, CW>(Ys, Tm, l, ncols, Z, ldz, cb);
         return;
     }
     __syncthreads();
@@ -552,22 +559,28 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const size_t epi_b = epi_rec > epi_xt ? epi_rec : epi_xt;
     static bool attr = false;
     if (!attr) {
-        const void *fs[4] = {(const void *)k_gemm1<double>, (const void *)k_gemm1<float>, (const void *)k_zsum<double>,
-                             (const void *)k_zsum<float>};
+        const void *fs[6] = {(const void *)k_gemm1<double>,     (const void *)k_gemm1<float>,
+                             (const void *)k_zsum<double, 32>, (const void *)k_zsum<double, 64>,
+                             (const void *)k_zsum<float, 32>,  (const void *)k_zsum<float, 64>};
         for (const void *f : fs) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
             if (e != hipSuccess) return e;
         }
         attr = true;
     }
-    const dim3 gz((unsigned)((w_bound + 63) / 64));
+    // k_zsum: 32 columns per workgroup on the explicit-T path (l <= kmax <= 64),
+    // twice the workgroups for the partial sums; 64 for the recurrence
+    const bool z32 = a.kmax <= 64;
+    const dim3 gz((unsigned)((w_bound + (z32 ? 31 : 63)) / (z32 ? 32 : 64)));
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0) {
         hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz);
-        hipLaunchKernelGGL(k_zsum<double>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
+        if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
+        else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
     } else {
         hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz);
-        hipLaunchKernelGGL(k_zsum<float>, gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
+        if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
+        else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);
