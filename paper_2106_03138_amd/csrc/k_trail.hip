@@ -8,8 +8,8 @@
 // (Z_a = 0 when tau_a = 0, the identity reflector), with v_b^T v_a recorded by
 // the panel.  Two kernels on gfx950 MFMA:
 //   k_gemm1  Y = V^T A_tr, split over rows, partial products published;
-//   k_zsum   per 64 trailing columns: Y = sum of the partials in split order,
-//            then the recurrence -> Z;
+//   k_zsum   per 32 (explicit T) or 64 (recurrence) trailing columns: Y = sum
+//            of the partials in split order, then Z = T^T Y or the recurrence;
 //   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once.
 // Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode runs both products
 // on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and the
@@ -297,7 +297,7 @@ __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int
     }
 }
 
-// Z for 64 trailing columns per workgroup: Y = the k_gemm1 partials summed in
+// Z for CW trailing columns per workgroup: Y = the k_gemm1 partials summed in
 // split order, then Z = T^T Y (l <= 64, explicit T) or the recurrence
 // Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
 template <typename T, int CW>
