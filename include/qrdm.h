@@ -31,8 +31,18 @@
  *     failure the kernels detect themselves (a bounded grid-wide wait that
  *     timed out, a launch grid smaller than a kernel's partition) returns
  *     QRDM_ERR_HIP + hipErrorLaunchTimeOut; A then holds partial results.
- *   - Calls are not re-entrant: two concurrent calls on one device share the
- *     cached workspace and must be serialized by the caller.
+ *   - Workspace: the entry points without a workspace argument use one device
+ *     workspace that the library caches per device; concurrent calls to them
+ *     are serialized by a lock inside the library.  qrdm_factor_ws takes the
+ *     caller's workspace instead: calls with distinct workspaces (and
+ *     matrices) may run concurrently from several host threads on several
+ *     streams.  The Householder panel and the column-pivoting block kernel
+ *     synchronize their workgroups through memory and need them all resident
+ *     at once (at most one workgroup per compute unit each); concurrent calls
+ *     whose such kernels could together exceed the device should set
+ *     QRDM_COOPERATIVE=1 in the environment (cooperative launches, whose
+ *     co-residency the runtime guarantees).  Their waits are bounded: a wait
+ *     that times out fails the call with hipErrorLaunchTimeOut, never hangs.
  */
 #ifndef QRDM_H
 #define QRDM_H
@@ -48,6 +58,9 @@ extern "C" {
 #define QRDM_ERR_NONFINITE 1   /* NaN/Inf in A (or a column norm overflows); A unchanged */
 #define QRDM_ERR_NOMEM 2       /* workspace allocation failed; nothing written            */
 #define QRDM_ERR_UNSUPPORTED 3 /* size outside what the kernels support (see below)      */
+#define QRDM_ERR_INTERNAL 4    /* the host loop ran past its bound on the number of steps
+                                  (each step takes at least one column; a library fault)    */
+#define QRDM_ERR_WORKSPACE 5   /* ws_bytes < qrdm_workspace_size(m, n, p); nothing written  */
 #define QRDM_ERR_HIP 1000      /* QRDM_ERR_HIP + hipError_t of a failed runtime call      */
 
 /* Stopping criterion, Section 3.4, eq. (practical stopping criterion). */
@@ -68,11 +81,16 @@ typedef struct {
     int32_t kmax;       /* block size k_DM, eq. (candidate_set_limited_by_kDM); 1..128 (64) */
     int32_t stop_rule;  /* QRDM_STOP_* (default QRDM_STOP_PAPER)                          */
     double eps1_scale;  /* eps_1 = eps1_scale * eps_w; <= 0 selects n (eq. choice1), where
-                           eps_w = 2^-52 in FP64 mode and 2^-23 (FP32) in mixed mode; the
-                           switch to scalar pivoting uses max partial norm <= n eps_w amax */
+                           eps_w is the unit roundoff of the trailing data: 2^-52 in FP64
+                           mode, 2^-23 in mixed mode (its updates round to FP32, so the
+                           trailing block carries noise of about 2^-23 ||A||); the
+                           recompute tolerance of the norm downdate is sqrt(eps_w).  The
+                           switch to scalar pivoting, eq. (column_norm_bound_DM), is
+                           max partial norm <= n 2^-52 max ||a_j|| in both modes         */
     int32_t precision;  /* QRDM_PREC_* (default FP64)                                     */
     int32_t poll_lag;   /* host polls the device loop state this many blocks behind
-                           (0 = synchronize every block; default 4)                       */
+                           (0 = synchronize every block; default 4; at most 1024).  The
+                           factorization is the same to the bit for every value          */
     int32_t profile;    /* 1 = time the trailing GEMMs with HIP events on `stream`
                            (results in qrdm_stats; adds event overhead); default 0        */
     int32_t certified;  /* 1 = certified DM: per block, delta is lowered to
@@ -83,7 +101,8 @@ typedef struct {
 typedef struct {
     int64_t nblocks;     /* outer steps executed                                          */
     int64_t nbreaks;     /* blocks whose panel stopped early (l < k_s)                    */
-    int64_t nfallback;   /* scalar-pivoting steps, eq. (column_norm_bound_DM)             */
+    int64_t nfallback;   /* columns factored by scalar pivoting after the switch of eq.
+                            (column_norm_bound_DM)                                         */
     int64_t nrecompute;  /* partial norms recomputed from the data                        */
     int64_t ncols_factored; /* number of reflectors applied                               */
     /* filled when params.profile = 1 (zero otherwise):                                    */
@@ -105,16 +124,24 @@ typedef struct {
     double qp3_bytes;    /* algorithmic bytes: 8 (m-j)(n-j) per pivot step j (the trailing
                             matrix read once by the step's matrix-vector product)          */
     int64_t nqp3_launch; /* block-kernel launches (0 when the per-step kernels ran)        */
+    int64_t qp3_start;   /* first column of the column-pivoting loop: the column where the
+                            switch of eq. (column_norm_bound_DM) held (QRDM), 0 for QRP,
+                            -1 when the factorization never switched (always filled)       */
 } qrdm_stats;
 
-/* One record per outer step, for tests and tracing. */
+/* One record per outer step of the DM loop, for tests and tracing.  When the
+ * partial norms reach the noise level (eq. column_norm_bound_DM) the loop
+ * hands the remaining columns to the column-pivoting kernels: that is the last
+ * record, with fallback = 1, ns = the first column pivoted singly, and
+ * nL = ks = l = 0. */
 typedef struct {
     int64_t ns;       /* columns factored before this step */
     int32_t nL;       /* candidate list length             */
     int32_t ks;       /* accepted columns                  */
     int32_t l;        /* reflectors kept after the break   */
-    int32_t fallback; /* 1 = scalar pivoting step          */
-    double umax;      /* max partial norm at selection     */
+    int32_t fallback; /* 1 = the hand-over record (above)  */
+    double umax;      /* max partial norm at selection (the estimate the
+                         selection compared, after the downdates)       */
     /* Lemma 1 on C = the k_s accepted columns [A]_{ns:m, J} at this step, from
      * their Gram matrix: gamma = min_i (1 - sum_{j != i} |theta_ij|) and
      * sigma_bound = sqrt(gamma + tau_J^2 - 1) max_J ||c_j|| with
@@ -148,6 +175,37 @@ int qrdm_factor(double *A, int64_t m, int64_t n, int64_t lda, double tau, double
 int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p,
                    double *tau_house, int32_t *perm, int64_t *rank, qrdm_stats *stats,
                    qrdm_block *log, int64_t log_cap, int64_t *nlog, void *stream);
+
+/*
+ * Bytes of device workspace that qrdm_factor_ws needs for an m x n matrix with
+ * parameters *p (NULL = defaults; only p->kmax matters).  0 for m < 0 or n < 0.
+ */
+size_t qrdm_workspace_size(int64_t m, int64_t n, const qrdm_params *p);
+
+/*
+ * QRDM (Algorithm 4 with Algorithm 1; Section 3, A P = Q R) in a workspace the
+ * caller owns, with the rank written to device memory.
+ *   A, lda, p, tau_house, perm  as in qrdm_factor_ex (p->profile must be 0).
+ *   rank_dev   [out, DEVICE] one int64: the rank of eq. (practical stopping
+ *              criterion) (Section 5 uses it as the numerical rank), written in
+ *              stream order after the last kernel of the factorization; -1 if
+ *              the call fails on the device.
+ *   stats      [out, host, may be NULL] counters; asking for them synchronizes
+ *              the stream.
+ *   workspace  [DEVICE] at least qrdm_workspace_size(m, n, p) bytes, 256-byte
+ *              aligned; its contents on entry do not matter, and it must not be
+ *              used by any other work until the stream has passed this call.
+ * The call launches the factorization on `stream` and returns once the device
+ * has reported the end of the loop (the host waits on events of its own,
+ * never on the whole stream); it allocates no device memory and takes no lock
+ * shared with other calls, so calls with distinct workspaces run concurrently
+ * (see the conventions above for the kernels that need co-residency).
+ * Returns as qrdm_factor_ex; QRDM_ERR_WORKSPACE if ws_bytes is too small, -10
+ * for a NULL or misaligned workspace.
+ */
+int qrdm_factor_ws(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p, double *tau_house,
+                   int32_t *perm, int64_t *rank_dev, qrdm_stats *stats, void *workspace, size_t ws_bytes,
+                   void *stream);
 
 /*
  * QRP, Algorithm 2 (Section 3.1), blocked like LAPACK xgeqp3: one pivot per

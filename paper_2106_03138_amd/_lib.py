@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(HERE, "libqrdm.so")
 
 STOP_PAPER, STOP_MAXNORM, STOP_NONE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-ERR_NONFINITE, ERR_NOMEM, ERR_UNSUPPORTED, ERR_HIP = 1, 2, 3, 1000
+ERR_NONFINITE, ERR_NOMEM, ERR_UNSUPPORTED, ERR_INTERNAL, ERR_WORKSPACE, ERR_HIP = 1, 2, 3, 4, 5, 1000
 
 
 class Params(ctypes.Structure):
@@ -28,7 +28,8 @@ class Stats(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("dm_ms", ctypes.c_double), ("panel_ms", ctypes.c_double),
                 ("downdate_ms", ctypes.c_double), ("qp3_ms", ctypes.c_double), ("panel_flop", ctypes.c_double),
                 ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64),
-                ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64)]
+                ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64),
+                ("qp3_start", ctypes.c_int64)]
 
 
 class Block(ctypes.Structure):
@@ -64,6 +65,9 @@ SIGNATURES = {
     "qrdm_factor": (ctypes.c_int, [_vp, _i64, _i64, _i64, _d, _d, _i32, _vp, _vp, _P(_i64), _vp]),
     "qrdm_factor_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _vp, _vp, _P(_i64), _P(Stats),
                                       _P(Block), _i64, _P(_i64), _vp]),
+    "qrdm_workspace_size": (ctypes.c_size_t, [_i64, _i64, _P(Params)]),
+    "qrdm_factor_ws": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _vp, _vp, _vp, _P(Stats), _vp,
+                                      ctypes.c_size_t, _vp]),
     "qrp_factor": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp, _P(_i64), _vp]),
     "qrp_factor_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _i32, _vp, _vp, _P(_i64), _P(Stats), _vp]),
     "qrdm_colnorms": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),

@@ -39,7 +39,22 @@ def _check_matrix(A):
     if m > 1 and n > 0 and A.stride(0) != 1:
         raise ValueError("A must be column-major (stride(0) == 1)")
     lda = A.stride(1) if n > 1 else max(m, 1)
-    return m, n, max(lda, max(m, 1))
+    if lda < max(m, 1):
+        raise ValueError(f"A's column stride {lda} is below its {m} rows (columns would overlap)")
+    return m, n, lda
+
+
+def _out_vector(t, name, dtype, count, A):
+    """A caller-supplied output vector: the dtype, at least `count` contiguous
+    elements, on A's device."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype:
+        raise TypeError(f"{name} must be a {dtype} torch tensor")
+    if t.device != A.device:
+        raise ValueError(f"{name} must live on {A.device}")
+    if not t.is_contiguous() or t.numel() < max(count, 1):
+        raise ValueError(f"{name} must be contiguous with at least {max(count, 1)} elements")
+    return t
 
 
 def _stream_ptr(stream):
@@ -69,19 +84,62 @@ def _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profil
     return p
 
 
+def _outputs(A, m, n, tau_house, perm):
+    torch = _torch()
+    if tau_house is None:
+        tau_house = torch.empty(max(min(m, n), 1), dtype=torch.float64, device=A.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    return (_out_vector(tau_house, "tau_house", torch.float64, min(m, n), A),
+            _out_vector(perm, "perm", torch.int32, n, A))
+
+
+def workspace_size(m: int, n: int, kmax: int = 64) -> int:
+    """Bytes of device workspace qrdm_factor_ws needs (qrdm_workspace_size)."""
+    p = _lib.Params()
+    _lib.load().qrdm_default_params(ctypes.byref(p))
+    p.kmax = int(kmax)
+    return int(_lib.load().qrdm_workspace_size(int(m), int(n), ctypes.byref(p)))
+
+
+def qrdm_factor_ws(A, workspace, rank_out, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
+                   stop_rule: int = _lib.STOP_PAPER, precision: int = _lib.PREC_FP64, poll_lag: int = 4,
+                   eps1_scale: float = 0.0, stream=None, tau_house=None, perm=None, certified: bool = False,
+                   stats: bool = False) -> Factorization:
+    """QRDM of A in place in a caller-owned workspace (a uint8 device tensor of at
+    least workspace_size(m, n, kmax) bytes); the rank goes to rank_out (an int64
+    device tensor with one element) in stream order.  The returned
+    Factorization's rank is -1 (it stays on the device)."""
+    torch = _torch()
+    m, n, lda = _check_matrix(A)
+    p = _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, False, certified)
+    tau_house, perm = _outputs(A, m, n, tau_house, perm)
+    rank_out = _out_vector(rank_out, "rank_out", torch.int64, 1, A)
+    if not isinstance(workspace, torch.Tensor) or workspace.device != A.device or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous tensor on A's device")
+    nbytes = workspace.numel() * workspace.element_size()
+    st = _lib.Stats()
+    code = _lib.load().qrdm_factor_ws(
+        ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.byref(p), ctypes.c_void_p(tau_house.data_ptr()),
+        ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(rank_out.data_ptr()), ctypes.byref(st) if stats else None,
+        ctypes.c_void_p(workspace.data_ptr()), nbytes, _stream_ptr(stream))
+    _lib.check("qrdm_factor_ws", code)
+    sd = {k: getattr(st, k) for k, _ in _lib.Stats._fields_} if stats else {}
+    return Factorization(tau_house[: min(m, n)], perm[:n], -1, sd, [])
+
+
 def qrdm_factor(A, tau: float = 0.15, delta: float = 0.9, kmax: int = 64, stop_rule: int = _lib.STOP_PAPER,
                 precision: int = _lib.PREC_FP64, poll_lag: int = 4, eps1_scale: float = 0.0,
                 log: bool = False, profile: bool = False, stream=None, tau_house=None,
                 perm=None, certified: bool = False) -> Factorization:
     """QRDM (Algorithm 4 with Algorithm 1) of A in place.  With log=True,
-    blocks holds (ns, nL, ks, l, fallback, gamma, sigma_bound) per step."""
+    blocks holds (ns, nL, ks, l, fallback, gamma, sigma_bound, umax) per step of
+    the DM loop; a last record with fallback = 1 and l = 0 marks the hand-over
+    to column pivoting at column ns (eq. column_norm_bound_DM)."""
     torch = _torch()
     m, n, lda = _check_matrix(A)
     p = _params(tau, delta, kmax, stop_rule, precision, poll_lag, eps1_scale, profile, certified)
-    if tau_house is None:
-        tau_house = torch.empty(max(min(m, n), 1), dtype=torch.float64, device=A.device)
-    if perm is None:
-        perm = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    tau_house, perm = _outputs(A, m, n, tau_house, perm)
     rank = ctypes.c_int64(-1)
     st = _lib.Stats()
     cap = (min(m, n) + 2) if log else 0
@@ -93,7 +151,7 @@ def qrdm_factor(A, tau: float = 0.15, delta: float = 0.9, kmax: int = 64, stop_r
         blocks if log else None, cap, ctypes.byref(nlog), _stream_ptr(stream))
     _lib.check("qrdm_factor_ex", code)
     stats = {k: getattr(st, k) for k, _ in _lib.Stats._fields_}
-    bl = [(b.ns, b.nL, b.ks, b.l, b.fallback, b.gamma, b.sigma_bound)
+    bl = [(b.ns, b.nL, b.ks, b.l, b.fallback, b.gamma, b.sigma_bound, b.umax)
           for b in list(blocks)[: min(nlog.value, cap)]] if log else []
     return Factorization(tau_house[: min(m, n)], perm[:n], rank.value, stats, bl)
 
@@ -104,10 +162,7 @@ def qrp_factor(A, stop_rule: int = _lib.STOP_PAPER, nb: int = 32, poll_lag: int 
     torch = _torch()
     m, n, lda = _check_matrix(A)
     p = _params(0.15, 0.9, 64, stop_rule, 0, poll_lag, eps1_scale)
-    if tau_house is None:
-        tau_house = torch.empty(max(min(m, n), 1), dtype=torch.float64, device=A.device)
-    if perm is None:
-        perm = torch.empty(max(n, 1), dtype=torch.int32, device=A.device)
+    tau_house, perm = _outputs(A, m, n, tau_house, perm)
     rank = ctypes.c_int64(-1)
     st = _lib.Stats()
     code = _lib.load().qrp_factor_ex(ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.byref(p), int(nb),

@@ -78,12 +78,15 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
     __shared__ double s_umax;
 
     const int tid = threadIdx.x;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
+    if (ctl->nonfinite) {  // NaN/Inf in A (R15): nothing is written
+        if (tid == 0) ctl->done = 1;
+        return;
+    }
     const int64_t ns = ctl->ns + ctl->l;
     const int64_t nblk = ctl->nblocks;
     const double amax0 = ctl->amax;  // read with the rest of the state, before the keys
     const int64_t rank0 = ctl->rank;
-    const int64_t nfb0 = ctl->nfallback;
     __syncthreads();
     const int64_t p = p_of(a);
     if (tid == 0) {
@@ -92,9 +95,6 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         ctl->ks = 0;
         ctl->nL = 0;
         ctl->nswap = 0;
-        ctl->bar = 0;
-        ctl->bar2 = 0;
-        ctl->fallback = 0;
     }
     if (ns >= p) {
         if (tid == 0) {
@@ -147,11 +147,13 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         }
         int64_t cap = a.kmax < (p - ns) ? a.kmax : (p - ns);
         if (branch == 2) {
-            bool fb = uv <= a.fbeps * amax;
-            if (fb || cap == 1) {
+            if (uv <= a.fbeps * amax) {
+                // the rest is scalar pivoting: this step takes no block, and the
+                // column-pivoting kernels start at exactly this n_s
+                branch = 3;
+                ctl->fallback = 1;
+            } else if (cap == 1) {
                 branch = 1;
-                ctl->fallback = fb ? 1 : 0;
-                if (fb) ctl->nfallback = nfb0 + 1;
             }
         }
         if (branch == 0) {
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
             ctl->umax = uv;
             ctl->jmax = uj;
             ctl->eps_s = a.tau * uv;
-            ctl->nblocks = nblk + 1;
+            if (branch != 3) ctl->nblocks = nblk + 1;
         }
         if (branch == 1) {
             ctl->L[0] = uj;
@@ -317,6 +319,10 @@ hipError_t launch_select(QrdmArgs a, hipStream_t s) {
 
 // ================================================================ k_gram
 #define GR_ROWS 128   // rows of C per workgroup
+
+// Leading dimension of each partial Gram matrix: k_DM rounded up to the
+// 16-wide MFMA tiles.
+__host__ __device__ __forceinline__ int gram_ld(int kmax) { return ((kmax < QK_KM ? kmax : QK_KM) + 15) & ~15; }
 #define GR_CHUNK 64   // rows staged in LDS at a time
 #define GR_LD (GR_CHUNK + 1)
 
@@ -324,7 +330,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gram(QrdmArgs a, double *Gp) {
     const QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int nL = ctl->nL;
     if (nL <= 1) return;
     const int64_t ns = ctl->ns;
@@ -379,7 +385,8 @@ __global__ void __launch_bounds__(256) k_gram(QrdmArgs a, double *Gp) {
             }
         }
     }
-    double *out = Gp + (int64_t)blockIdx.x * QK_KM * QK_KM;
+    const int kp = gram_ld(a.kmax);
+    double *out = Gp + (int64_t)blockIdx.x * kp * kp;
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         const int tile = wv + 4 * u;
@@ -390,7 +397,7 @@ __global__ void __launch_bounds__(256) k_gram(QrdmArgs a, double *Gp) {
             for (int v = 0; v < 4; ++v) {
                 // f64 16x16x4 MFMA: register v of lane holds D[4v + lane/16][lane%16]
                 const int row = ti * 16 + 4 * v + (lane >> 4);
-                out[row * QK_KM + col] = acc[u][v];
+                out[row * kp + col] = acc[u][v];
             }
         }
     }
@@ -407,7 +414,7 @@ int gram_partials(int64_t t_bound) { return (int)((t_bound + GR_ROWS - 1) / GR_R
 
 __global__ void __launch_bounds__(256) k_gram_reduce(QrdmArgs a, const double *Gp, double *G) {
     const QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int nL = ctl->nL;
     if (nL <= 1) return;
     const int64_t t = a.m - ctl->ns;
@@ -416,11 +423,12 @@ __global__ void __launch_bounds__(256) k_gram_reduce(QrdmArgs a, const double *G
     if (e >= nL * nL) return;
     const int i = e / nL, j = e % nL;
     // fixed order over the partials, sixteen loads in flight
+    const int kp = gram_ld(a.kmax);
     double s = 0.0;
     for (int w0 = 0; w0 < np; w0 += 16) {
         double v[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = w0 + u < np ? Gp[(int64_t)(w0 + u) * QK_KM * QK_KM + i * QK_KM + j] : 0.0;
+        for (int u = 0; u < 16; ++u) v[u] = w0 + u < np ? Gp[(int64_t)(w0 + u) * kp * kp + i * kp + j] : 0.0;
 #pragma unroll
         for (int u = 0; u < 16; ++u) s += v[u];
     }
@@ -448,7 +456,7 @@ __device__ __forceinline__ unsigned long long dm_readlane64(unsigned long long v
 
 __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, double *theta_out) {
     QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     __shared__ double sd[QK_KM];
     __shared__ double sG[QK_KM * QK_KM];
     __shared__ int sJ[QK_KM];
@@ -696,7 +704,7 @@ hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipS
 __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
     if (blockIdx.x == 0 && threadIdx.x == 0) gbar_clear(a.gbar);  // for the panel launched next
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int nsw = ctl->nswap;
     if (nsw == 0) return;
     const int64_t r0 = (int64_t)blockIdx.x * SW_ROWS;

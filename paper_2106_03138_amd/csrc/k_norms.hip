@@ -41,8 +41,10 @@ hipError_t launch_colnorm(const double *A, int64_t m, int64_t n, int64_t lda, do
     return hipGetLastError();
 }
 
-// perm = identity, tau_house = 0; run only after the NaN/Inf check passed.
+// perm = identity, tau_house = 0, unless the norm sweep found NaN/Inf (then
+// nothing is written).
 __global__ void k_init(QrdmArgs a) {
+    if (a.ctl->nonfinite) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < a.n) a.perm[i] = (int32_t)i;
     if (i < p_of(a)) a.tau_house[i] = 0.0;
@@ -64,7 +66,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_WG) k_downdate(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
     // the step's state is final here (the next step's selection changes it)
     if (a.snap && blockIdx.x == 0 && threadIdx.x == 0) qrdm_write_snapshot(ctl, a.snap);
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
     const int l = ctl->l;
     const int lane = threadIdx.x & 63;
@@ -106,5 +108,41 @@ hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s) {
     if (w_bound <= 0) w_bound = 1;  // one workgroup still writes the snapshot
     dim3 grid((unsigned)((w_bound + WAVES_PER_WG - 1) / WAVES_PER_WG));
     hipLaunchKernelGGL(k_downdate, grid, dim3(64 * WAVES_PER_WG), 0, s, a);
+    return hipGetLastError();
+}
+
+// Start of a call: the control block zeroed with rank = -1 (no stopping test
+// has held yet), and the n recompute flags of the column-pivoting loop cleared.
+__global__ void k_ws_reset(QrdmCtl *ctl, int32_t *flag, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = 0;
+    if (blockIdx.x == 0) {
+        uint64_t *w = (uint64_t *)ctl;
+        const int nw = (int)(sizeof(QrdmCtl) / 8);
+        for (int k = threadIdx.x; k < nw; k += blockDim.x) w[k] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) ctl->rank = -1;
+    }
+}
+
+hipError_t launch_ws_reset(QrdmCtl *ctl, int32_t *flag, int64_t n, hipStream_t s) {
+    static_assert(sizeof(QrdmCtl) % 8 == 0, "the control block is cleared in 8-byte words");
+    const int64_t cnt = n > 1 ? n : 1;
+    hipLaunchKernelGGL(k_ws_reset, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, ctl, flag, n);
+    return hipGetLastError();
+}
+
+// End of a call: the rank in device memory (the first n_s where the stopping
+// test held, else the number of reflectors), or -1 after NaN/Inf or a failed
+// grid wait.
+__global__ void k_rank_out(const QrdmCtl *ctl, int64_t *rank) {
+    if (threadIdx.x != 0) return;
+    int64_t r = ctl->rank >= 0 ? ctl->rank : ctl->ns;
+    if (ctl->nonfinite || ctl->error) r = -1;
+    *rank = r;
+}
+
+hipError_t launch_rank_out(const QrdmCtl *ctl, int64_t *rank, hipStream_t s) {
+    hipLaunchKernelGGL(k_rank_out, dim3(1), dim3(64), 0, s, ctl, rank);
     return hipGetLastError();
 }

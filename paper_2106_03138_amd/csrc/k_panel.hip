@@ -130,7 +130,7 @@ __device__ __forceinline__ void pn_update(double *S, int ksp, int r0, int nrows,
 __global__ void __launch_bounds__(PN_THREADS)
 k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv, int rows) {
     QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks;
     const double eps_s = ctl->eps_s;

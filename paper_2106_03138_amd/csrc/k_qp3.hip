@@ -81,6 +81,7 @@ __global__ void k_qp_init(QrdmArgs a, int nb) {
         gbar_clear(a.gbar);
         gbar_clear(a.gbar + GBAR_GROUPS * GBAR_STRIDE);
     }
+    if (c->nonfinite) c->done = 1;  // NaN/Inf in A: nothing is written
     if (!c->done) c->ns += c->l;  // finish the advance of a preceding QRDM step
     c->qp_k0 = c->ns;
     c->qp3_start = c->ns;

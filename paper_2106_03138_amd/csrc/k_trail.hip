@@ -88,9 +88,9 @@ __device__ __forceinline__ int g1_krows(int64_t t, int64_t w) {
 // [256x, 256x+256), and writes it to Yp[y] (k_zsum, the next launch, sums them).
 template <typename T>
 __global__ void __launch_bounds__(G1_TH)
-k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ldz) {
+k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ldz, int64_t ysplit) {
     QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks, l = ctl->l;
     const int64_t t = a.m - ns;
@@ -167,7 +167,7 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
         }
     }
     // the partial: Yp[sp][q0 + row][jb + col] (double)
-    double *yp = Yp + ((int64_t)sp * QK_KM + q0) * ldz;
+    double *yp = Yp + (int64_t)sp * ysplit + (int64_t)q0 * ldz;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
         if (ti < ltz) {
@@ -302,9 +302,10 @@ __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int
 // Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
 template <typename T, int CW>
 __global__ void __launch_bounds__(G1_TH)
-k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz) {
+k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz,
+       int64_t ysplit) {
     QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks, l = ctl->l;
     const int64_t t = a.m - ns;
@@ -358,7 +359,7 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
             double v[QK_SPLIT_MAX];
 #pragma unroll
             for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2)
-                v[s2] = (ok && s2 < nsplit) ? Yp[((int64_t)s2 * QK_KM + aa) * ldz + cb + j] : 0.0;
+                v[s2] = (ok && s2 < nsplit) ? Yp[(int64_t)s2 * ysplit + (int64_t)aa * ldz + cb + j] : 0.0;
             double sum = 0.0;
 #pragma unroll
             for (int s2 = 0; s2 < QK_SPLIT_MAX; ++s2) sum += v[s2];
@@ -411,7 +412,9 @@ template <typename T, int MODE>
 __global__ void __launch_bounds__(512, sizeof(T) == 8 ? 4 : 1)
 k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ Z, int64_t ldz) {
     const QrdmCtl *ctl = a.ctl;
-    if (ctl->done) return;
+    // a DM step's update is idle after the switch to column pivoting; the QP3
+    // block end runs exactly then
+    if (MODE == 0 ? qrdm_dm_idle(ctl) : (bool)ctl->done) return;
     int64_t r0, c0;
     int l;
     double rpend = 1.0;  // mode 1: the block's last reflector is stored unscaled
@@ -530,11 +533,20 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
         }
 }
 
+// Rows of the V^T A partials per split (k_DM rounded up to the 16-row MFMA
+// tiles) times the n columns: the stride between the splits in Yp.
+int64_t trail_ysplit(int kmax, int64_t n) {
+    const int kp = ((kmax < QK_KM ? kmax : QK_KM) + 15) & ~15;
+    return (int64_t)kp * n;
+}
+int trail_splits_max() { return QK_SPLIT_MAX; }
+
 hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
                         int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, int64_t w_lo,
                         hipStream_t s, hipEvent_t *ev) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
     const int64_t ldz = a.n;
+    const int64_t ysplit = trail_ysplit(a.kmax, a.n);
     const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
     // enough splits for any trailing size within the bounds: g1_krows picks the
     // split on the device (at most 16, at most t/256, at most G1_TARGET_WGS over
@@ -574,13 +586,13 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const dim3 gz((unsigned)((w_bound + (z32 ? 31 : 63)) / (z32 ? 32 : 64)));
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0) {
-        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz);
-        if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
-        else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz);
+        hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz, ysplit);
+        if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz, ysplit);
+        else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz, ysplit);
     } else {
-        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz);
-        if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
-        else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz);
+        hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz, ysplit);
+        if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz, ysplit);
+        else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz, ysplit);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);

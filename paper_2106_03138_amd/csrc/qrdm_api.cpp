@@ -7,6 +7,13 @@
 // n_s that the host learns by polling a small snapshot of the control block
 // `poll_lag` blocks behind the launch front; kernels of blocks enqueued after
 // the loop has finished exit at once.
+//
+// Device state of one call lives in a workspace (the layout below): either the
+// library's cache for the current device (qrdm_factor, qrdm_factor_ex, ...;
+// calls on it are serialized by a lock) or the caller's (qrdm_factor_ws).
+// Host state of one call (the pinned snapshot ring and its events) comes from
+// a pool, one entry per call in flight, so calls with their own workspaces run
+// concurrently.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -15,43 +22,126 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/qrdm.h"
 #include "qrdm_internal.h"
 
 int gram_partials(int64_t t_bound);
-int panel_lds_bytes(int rows_per_wg, int kmax);
+int64_t trail_ysplit(int kmax, int64_t n);
+int trail_splits_max();
 
 namespace {
 
-struct Snapshot {  // first bytes of QrdmCtl copied back for polling
+struct Snapshot {  // the first QRDM_SNAP_WORDS words of QrdmCtl, polled by the host
     int64_t ns;
     int64_t rank;
     int32_t l, ks, nL, done, fallback, jmax;
-    double gamma, sigma_bound;
+    double gamma, sigma_bound, umax;
+    int32_t nonfinite, error;
 };
 static_assert(sizeof(Snapshot) == 8 * QRDM_SNAP_WORDS, "the snapshot is the words the kernels write");
 static_assert(offsetof(Snapshot, jmax) == offsetof(QrdmCtl, jmax) &&
                   offsetof(Snapshot, gamma) == offsetof(QrdmCtl, gamma) &&
-                  offsetof(Snapshot, sigma_bound) == offsetof(QrdmCtl, sigma_bound),
+                  offsetof(Snapshot, umax) == offsetof(QrdmCtl, umax) &&
+                  offsetof(Snapshot, error) == offsetof(QrdmCtl, error),
               "the polled snapshot is a prefix of the control block");
 
-struct Workspace {
+// ------------------------------------------------------------ host polling
+// Host resources of one call: a ring of snapshot slots in pinned host memory
+// (the kernels write them through their device address) with one event per
+// slot, and the timing events of the profiling mode.
+struct PollCtx {
     int device = -1;
-    size_t bytes = 0;
-    char *base = nullptr;
-    Snapshot *host_snap = nullptr;  // pinned ring
-    uint64_t *dev_snap = nullptr;   // its device address (written by the kernels)
     int ring = 0;
+    Snapshot *host_snap = nullptr;
+    uint64_t *dev_snap = nullptr;
     std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> prof_ev;  // profile mode: loop events and 8 per block
+    std::vector<hipEvent_t> qp_ev;    // profile mode: around each QP3 block-kernel launch
+    // recorded after the last launch of the call that used the context: kernels
+    // launched ahead of the loop's end still write snapshots into the ring, so
+    // the context is reused only once this event has completed
+    hipEvent_t release_ev = nullptr;
 };
 
-Workspace g_ws;
+std::mutex g_poll_mu;
+std::vector<PollCtx *> g_poll_free;
 
-// timing events of the profiling mode (grown on demand, kept for reuse)
-std::vector<hipEvent_t> g_prof_ev;
-std::vector<hipEvent_t> g_qp_ev;  // around each QP3 block-kernel launch
+void poll_destroy(PollCtx *pc) {
+    if (pc->release_ev) {
+        (void)hipEventSynchronize(pc->release_ev);
+        (void)hipEventDestroy(pc->release_ev);
+    }
+    if (pc->host_snap) (void)hipHostFree(pc->host_snap);
+    for (auto e : pc->events) (void)hipEventDestroy(e);
+    for (auto e : pc->prof_ev) (void)hipEventDestroy(e);
+    for (auto e : pc->qp_ev) (void)hipEventDestroy(e);
+    delete pc;
+}
+
+// A context of the current device with at least `ring` slots (taken from the
+// pool, or made).  Returns 0 or QRDM_ERR_NOMEM.
+int poll_acquire(int ring, PollCtx **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return QRDM_ERR_NOMEM;
+    {
+        std::lock_guard<std::mutex> g(g_poll_mu);
+        for (size_t i = 0; i < g_poll_free.size(); ++i) {
+            PollCtx *pc = g_poll_free[i];
+            if (pc->device == dev && pc->ring >= ring && hipEventQuery(pc->release_ev) == hipSuccess) {
+                g_poll_free.erase(g_poll_free.begin() + (long)i);
+                *out = pc;
+                return 0;
+            }
+        }
+    }
+    PollCtx *pc = new PollCtx();
+    pc->device = dev;
+    pc->ring = std::max(ring, 8);
+    if (hipHostMalloc((void **)&pc->host_snap, sizeof(Snapshot) * pc->ring, hipHostMallocDefault) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&pc->dev_snap, pc->host_snap, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        poll_destroy(pc);
+        return QRDM_ERR_NOMEM;
+    }
+    if (hipEventCreateWithFlags(&pc->release_ev, hipEventDisableTiming) != hipSuccess) {
+        pc->release_ev = nullptr;
+        poll_destroy(pc);
+        return QRDM_ERR_NOMEM;
+    }
+    pc->events.resize(pc->ring);
+    for (int i = 0; i < pc->ring; ++i) {
+        if (hipEventCreateWithFlags(&pc->events[i], hipEventDisableTiming) != hipSuccess) {
+            pc->events.resize(i);
+            poll_destroy(pc);
+            return QRDM_ERR_NOMEM;
+        }
+    }
+    *out = pc;
+    return 0;
+}
+
+void poll_release(PollCtx *pc, hipStream_t s) {
+    if (hipEventRecord(pc->release_ev, s) != hipSuccess) {
+        // the stream is unusable: wait for the device before the ring is reused
+        (void)hipGetLastError();
+        (void)hipDeviceSynchronize();
+        (void)hipEventRecord(pc->release_ev, nullptr);
+    }
+    std::lock_guard<std::mutex> g(g_poll_mu);
+    g_poll_free.push_back(pc);
+}
+
+struct PollGuard {  // returns the context to the pool on every exit path
+    PollCtx *pc = nullptr;
+    hipStream_t s = nullptr;
+    ~PollGuard() {
+        if (pc) poll_release(pc, s);
+    }
+};
+
 int grow_events(std::vector<hipEvent_t> &v, size_t count) {
     while (v.size() < count) {
         hipEvent_t e;
@@ -60,59 +150,40 @@ int grow_events(std::vector<hipEvent_t> &v, size_t count) {
     }
     return 0;
 }
-int prof_events(size_t count) { return grow_events(g_prof_ev, count); }
 
-// Timing of the QP3 loop's block-kernel launches (profile mode).
-struct Qp3Prof {
-    bool on = false;
-    int64_t launches = 0;
-};
-
-// Algorithmic bytes of the pivot steps j0 .. j1-1: 8 (m-j)(n-j) each.
-double qp3_bytes(int64_t m, int64_t n, int64_t j0, int64_t j1) {
-    double b = 0.0;
-    for (int64_t j = j0; j < j1; ++j) b += 8.0 * (double)(m - j) * (double)(n - j);
-    return b;
-}
-
-double qp3_run_ms(int64_t launches) {
-    double t = 0.0;
-    for (int64_t i = 0; i < launches; ++i) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g_qp_ev[2 * i], g_qp_ev[2 * i + 1]) == hipSuccess) t += ms;
-    }
-    return t;
-}
-
+// ------------------------------------------------------------ workspace
 struct Layout {
     size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, gbar, perm_dbg, total;
 };
 
-const int kMinRowsPerWg = 16;   // smallest panel slab (bounds the partial buffer)
+const int kMinRowsPerWg = 16;  // smallest panel slab (bounds the partial buffer)
+const int kQp3NbMax = 64;      // largest block of the column-pivoting update
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t m, int64_t n) {
+// Device workspace of one call for an m x n matrix and block size kmax.
+Layout make_layout(int64_t m, int64_t n, int kmax) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     const int64_t mm = std::max<int64_t>(m, 1), nn = std::max<int64_t>(n, 1);
+    const size_t kp = (size_t)((std::min(std::max(kmax, 1), QK_KM) + 15) & ~15);  // k_DM in 16-wide tiles
     L.ctl = take(sizeof(QrdmCtl));
     L.vn1 = take(sizeof(double) * nn);
     L.vn2 = take(sizeof(double) * nn);
-    L.gp = take(sizeof(double) * (size_t)gram_partials(mm) * QK_KM * QK_KM);
+    L.gp = take(sizeof(double) * (size_t)gram_partials(mm) * kp * kp);
     L.g = take(sizeof(double) * QK_KM * QK_KM);
     L.theta = take(sizeof(double) * QK_KM * QK_KM);
     const int64_t pmax = (mm + kMinRowsPerWg - 1) / kMinRowsPerWg;
-    // panel: 4096 arrival flags (16 KB), rows c and c+1 (2 x 2 QK_KM), partial dots (2 x pmax x 2 QK_KM)
+    // panel: 4096 reserved words (16 KB), rows c and c+1 (2 x 2 QK_KM), partial dots (2 x pmax x 2 QK_KM)
     L.pb = take(16384 + sizeof(double) * (4 * QK_KM + 2 * (size_t)pmax * 2 * QK_KM));
     L.tm = take(sizeof(double) * QK_KM * QK_KM);
-    L.vw = take(sizeof(double) * (size_t)QK_KM * mm);
-    L.vw32 = take(sizeof(float) * (size_t)QK_KM * mm);
-    L.z = take(sizeof(double) * (size_t)QK_KM * nn);
-    L.yp = take(sizeof(double) * 16 * (size_t)QK_KM * nn);
+    L.vw = take(sizeof(double) * kp * (size_t)mm);
+    L.vw32 = take(sizeof(float) * kp * (size_t)mm);
+    L.z = take(sizeof(double) * kp * (size_t)nn);
+    L.yp = take(sizeof(double) * (size_t)trail_splits_max() * (size_t)trail_ysplit((int)kp, nn));
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
-    L.fz = take(sizeof(double) * 64 * (size_t)nn);
+    L.fz = take(sizeof(double) * kQp3NbMax * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
     // QP3 block kernel: 4 doubles of arg-max partials per workgroup
     L.qrb = take(sizeof(double) * 4 * QP_RUN_MAXWG);
@@ -121,6 +192,16 @@ Layout make_layout(int64_t m, int64_t n) {
     L.total = off;
     return L;
 }
+
+// The library's workspace for the current device (entry points without a
+// workspace argument).  Held under g_ws_mu for the whole call.
+struct CachedWs {
+    int device = -1;
+    size_t bytes = 0;
+    char *base = nullptr;
+};
+std::mutex g_ws_mu;
+CachedWs g_ws;
 
 int hip_err(hipError_t e) { return e == hipSuccess ? 0 : QRDM_ERR_HIP + (int)e; }
 
@@ -144,45 +225,40 @@ namespace {
         if (_e != hipSuccess) return hip_err(_e);   \
     } while (0)
 
-int ensure_workspace(size_t bytes, int ring) {
+// Caller holds g_ws_mu.
+int ensure_workspace(size_t bytes) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    if (g_ws.base && g_ws.device == dev && g_ws.bytes >= bytes && g_ws.ring >= ring) return 0;
+    if (g_ws.base && g_ws.device == dev && g_ws.bytes >= bytes) return 0;
     if (g_ws.base) {
         (void)hipDeviceSynchronize();
         (void)hipFree(g_ws.base);
         g_ws.base = nullptr;
+        g_ws.bytes = 0;
     }
-    if (g_ws.host_snap) {
-        (void)hipHostFree(g_ws.host_snap);
-        g_ws.host_snap = nullptr;
-    }
-    for (auto e : g_ws.events) (void)hipEventDestroy(e);
-    g_ws.events.clear();
     const char *fault = getenv("QRDM_FAULT");
     if (fault && strcmp(fault, "alloc") == 0) return QRDM_ERR_NOMEM;
-    size_t want = std::max(bytes, g_ws.bytes);
+    size_t want = bytes;
     if (hipMalloc((void **)&g_ws.base, want) != hipSuccess) {
         g_ws.base = nullptr;
         g_ws.bytes = 0;
         (void)hipGetLastError();
         return QRDM_ERR_NOMEM;
     }
-    int r = std::max(ring, 8);
-    if (hipHostMalloc((void **)&g_ws.host_snap, sizeof(Snapshot) * r, hipHostMallocDefault) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&g_ws.dev_snap, g_ws.host_snap, 0) != hipSuccess) {
-        if (g_ws.host_snap) (void)hipHostFree(g_ws.host_snap);
-        g_ws.host_snap = nullptr;
-        (void)hipFree(g_ws.base);
-        g_ws.base = nullptr;
-        return QRDM_ERR_NOMEM;
-    }
-    if (hipMemset(g_ws.base, 0, want) != hipSuccess) return QRDM_ERR_NOMEM;
-    g_ws.events.resize(r);
-    for (int i = 0; i < r; ++i) HIP_TRY(hipEventCreateWithFlags(&g_ws.events[i], hipEventDisableTiming));
     g_ws.bytes = want;
     g_ws.device = dev;
-    g_ws.ring = r;
+    return 0;
+}
+
+int check_params(const qrdm_params *p) {
+    if (!(p->tau >= 0.0 && p->tau <= 1.0)) return -5;
+    if (!(p->delta >= 0.0 && p->delta <= 1.0)) return -5;
+    if (p->kmax < 1 || p->kmax > QRDM_KMAX_LIMIT) return -5;
+    if (p->stop_rule < 0 || p->stop_rule > 2) return -5;
+    if (p->precision < 0 || p->precision > 1) return -5;
+    if (p->poll_lag < 0 || p->poll_lag > 1024) return -5;
+    if (p->profile < 0 || p->profile > 1) return -5;
+    if (p->certified < 0 || p->certified > 1) return -5;
     return 0;
 }
 
@@ -191,38 +267,42 @@ int check_common(const double *A, int64_t m, int64_t n, int64_t lda, const qrdm_
     if (n < 0) return -3;
     if (lda < std::max<int64_t>(1, m)) return -4;
     if (p) {
-        if (!(p->tau >= 0.0 && p->tau <= 1.0)) return -5;
-        if (!(p->delta >= 0.0 && p->delta <= 1.0)) return -5;
-        if (p->kmax < 1 || p->kmax > QRDM_KMAX_LIMIT) return -5;
-        if (p->stop_rule < 0 || p->stop_rule > 2) return -5;
-        if (p->precision < 0 || p->precision > 1) return -5;
-        if (p->poll_lag < 0) return -5;
-        if (p->profile < 0 || p->profile > 1) return -5;
-        if (p->certified < 0 || p->certified > 1) return -5;
+        int rc = check_params(p);
+        if (rc) return rc;
     }
     if (m > 0 && n > 0 && !A) return -1;
     return 0;
 }
 
-QrdmCtl initial_ctl() {
-    QrdmCtl c;
-    memset(&c, 0, sizeof c);
-    c.rank = -1;
-    return c;
+const int kQp3Nb = 32;  // block size of the column-pivoting update
+const double kEps64 = 2.220446049250313e-16;
+const double kEps32 = 1.1920928955078125e-07;
+
+// Profiling record of one loop (events in the call's PollCtx).
+struct ProfRun {
+    bool on = false;
+    int64_t dm_iters = 0;     // DM steps with 8 events each
+    int64_t qp_launches = 0;  // QP3 block-kernel launches with 2 events each
+};
+const int kEv = 8;  // per DM step: select, panel, panel end, GEMM1/GEMM2 start/end, downdate end
+
+double qp3_bytes(int64_t m, int64_t n, int64_t j0, int64_t j1) {
+    double b = 0.0;
+    for (int64_t j = j0; j < j1; ++j) b += 8.0 * (double)(m - j) * (double)(n - j);
+    return b;
 }
 
-const int kQp3Nb = 32;  // block size of the column-pivoting update
-
 // Column pivoting steps from the device's current n_s until the loop is done.
+// *last receives the snapshot with done = 1.
 int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64_t ns_known, hipStream_t s,
-            Qp3Prof *prof) {
+            PollCtx &pc, ProfRun &prof, Snapshot *last) {
     Qp3Bufs bf;
     bf.PB2 = (double *)(ws + L.pb2);
     bf.Fz = (double *)(ws + L.fz);
     bf.flag = (int32_t *)(ws + L.flag);
     bf.amx = (double *)(ws + L.qrb);
     HIP_TRY(launch_qp3_init(a, nb, s));
-    const int ring = g_ws.ring;
+    const int ring = pc.ring;
     const int64_t pmin = std::min(a.m, a.n);
     const char *mode = getenv("QRDM_QP3_STEPS");  // "1": the per-step kernels (comparison runs)
     const int grid = (mode && strcmp(mode, "1") == 0) ? 0 : qp3_block_grid(a.m);
@@ -232,25 +312,28 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
         for (int64_t iter = 0;; ++iter) {
             const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
             hipEvent_t *ev = nullptr;
-            if (prof && prof->on) {
-                if (grow_events(g_qp_ev, 2 * (size_t)(iter + 1)) != 0) return QRDM_ERR_NOMEM;
-                ev = g_qp_ev.data() + 2 * iter;
-                prof->launches = iter + 1;
+            if (prof.on) {
+                if (grow_events(pc.qp_ev, 2 * (size_t)(iter + 1)) != 0) return QRDM_ERR_NOMEM;
+                ev = pc.qp_ev.data() + 2 * iter;
+                prof.qp_launches = iter + 1;
             }
             QrdmArgs al = a;
-            al.snap = g_ws.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block kernel
+            al.snap = pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block kernel
             HIP_TRY(launch_qp3_block(al, bf, nb, tb, wb, grid, (int)iter, s, ev));
-            HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
+            HIP_TRY(hipEventRecord(pc.events[iter % ring], s));
             if (iter >= lag) {
                 const int64_t k = iter - lag;
-                HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
-                const Snapshot sn = g_ws.host_snap[k % ring];
+                HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
+                const Snapshot sn = pc.host_snap[k % ring];
                 if (sn.ns > ns_known) ns_known = sn.ns;
-                if (sn.done) break;
+                if (sn.done) {
+                    *last = sn;
+                    return 0;
+                }
             }
-            if (iter > pmin + lag + 4) break;  // cannot happen: every launch takes at least one step
+            // every launch takes at least one step: more launches than steps is a fault
+            if (iter > pmin + lag + 4) return QRDM_ERR_INTERNAL;
         }
-        return 0;
     }
     // snapshots every kStride steps; the host waits on the one `lag` snapshots back
     const int kStride = 4;
@@ -259,19 +342,250 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
         const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
         HIP_TRY(launch_qp3_step(a, bf, nb, tb, wb, s));
         if ((iter + 1) % kStride != 0) continue;
-        Snapshot *hs = g_ws.host_snap + (nsnap % ring);
+        Snapshot *hs = pc.host_snap + (nsnap % ring);
         HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(g_ws.events[nsnap % ring], s));
+        HIP_TRY(hipEventRecord(pc.events[nsnap % ring], s));
         if (nsnap >= lag) {
             const int64_t k = nsnap - lag;
-            HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
-            const Snapshot sn = g_ws.host_snap[k % ring];
+            HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
+            const Snapshot sn = pc.host_snap[k % ring];
             if (sn.ns > ns_known) ns_known = sn.ns;
-            if (sn.done) break;
+            if (sn.done) {
+                *last = sn;
+                return 0;
+            }
         }
         ++nsnap;
-        if (iter > 2 * pmin + kStride * (lag + 4)) break;  // cannot happen: every step advances n_s
+        // every step advances n_s: more steps than columns is a fault
+        if (iter > 2 * pmin + kStride * (lag + 4)) return QRDM_ERR_INTERNAL;
     }
+}
+
+// What one factorization call needs besides the matrix arguments.
+struct CallEnv {
+    char *ws;             // device workspace (layout L)
+    Layout L;
+    PollCtx *pc;
+    hipStream_t s;
+    qrdm_block *log;      // may be null
+    int64_t log_cap;
+    int64_t *nlog;        // may be null
+    int64_t *rank_dev;    // may be null: the rank is also written to device memory
+};
+
+void prof_fill(const ProfRun &prof, PollCtx &pc, const QrdmCtl &cf, int64_t m, int64_t n, qrdm_stats *st) {
+    double t[kEv - 1] = {0};
+    for (int64_t k = 0; k < prof.dm_iters; ++k) {
+        hipEvent_t *ev = pc.prof_ev.data() + 3 + kEv * k;
+        for (int e = 0; e + 1 < kEv; ++e) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) == hipSuccess) t[e] += ms;
+        }
+    }
+    // intervals (e, e+1): 0 DM selection, 1 panel, 3 GEMM1 (with Z), 5 GEMM2, 6 downdate
+    st->dm_ms = t[0];
+    st->panel_ms = t[1];
+    st->gemm1_ms = t[3];
+    st->gemm2_ms = t[5];
+    st->downdate_ms = t[6];
+    st->gemm_flop = cf.flop_gemm;
+    st->panel_flop = cf.flop_panel;
+    st->panel_bytes = cf.bytes_panel;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pc.prof_ev[1], pc.prof_ev[2]) == hipSuccess) st->qp3_ms = ms;
+    if (hipEventElapsedTime(&ms, pc.prof_ev[0], pc.prof_ev[2]) == hipSuccess) st->total_ms = ms;
+    st->nqp3_launch = prof.qp_launches;
+    double q = 0.0;
+    for (int64_t i = 0; i < prof.qp_launches; ++i) {
+        float x = 0.f;
+        if (hipEventElapsedTime(&x, pc.qp_ev[2 * i], pc.qp_ev[2 * i + 1]) == hipSuccess) q += x;
+    }
+    st->qp3_run_ms = q;
+    st->qp3_bytes = prof.qp_launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
+}
+
+void stats_fill(const QrdmCtl &cf, qrdm_stats *st) {
+    st->nblocks = cf.nblocks;
+    st->nbreaks = cf.nbreaks;
+    st->nrecompute = cf.nrecompute;
+    st->ncols_factored = cf.ns;
+    st->npanel = cf.npanel;
+    st->qp3_start = cf.fallback ? cf.qp3_start : -1;
+    st->nfallback = cf.fallback ? cf.ns - cf.qp3_start : 0;
+}
+
+// The QRDM loop of one call (Algorithm 4 with Algorithm 1), from the
+// workspace reset to the last launch.  On success *final holds the snapshot in
+// which the device reported the loop done.  Nothing here waits for the whole
+// stream: the host waits on the events of its own snapshots.
+int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p, double *tau_house, int32_t *perm,
+             const CallEnv &env, ProfRun &prof, Snapshot *final) {
+    char *ws = env.ws;
+    const Layout &L = env.L;
+    PollCtx &pc = *env.pc;
+    hipStream_t s = env.s;
+    const int lag = env.log ? 0 : p.poll_lag;
+    QrdmArgs a;
+    a.A = A;
+    a.m = m;
+    a.n = n;
+    a.lda = lda;
+    a.tau = p.tau;
+    a.delta = p.delta;
+    a.kmax = p.kmax;
+    a.stop_rule = p.stop_rule;
+    a.certified = p.certified;
+    // eps_w, the unit roundoff of the trailing data: 2^-52 (FP64) or 2^-23 in
+    // mixed mode, where every trailing update rounds to FP32.  The stopping
+    // test (eps_1 = n eps_w) and the recompute tolerance sqrt(eps_w) follow the
+    // data; the switch to scalar pivoting stays at n 2^-52 max ||a_j||, which
+    // the FP32 rounding noise (about 2^-23 ||A||) never reaches, so mixed mode
+    // keeps taking DM blocks to the end.
+    const double eps_w = (p.precision == QRDM_PREC_MIXED) ? kEps32 : kEps64;
+    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * eps_w;
+    a.fbeps = (double)n * kEps64;
+    a.tol3z = sqrt(eps_w);
+    a.vn1 = (double *)(ws + L.vn1);
+    a.vn2 = (double *)(ws + L.vn2);
+    a.perm = perm;
+    a.tau_house = tau_house;
+    a.gbar = (uint32_t *)(ws + L.gbar);
+    a.ctl = (QrdmCtl *)(ws + L.ctl);
+    double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
+    double *VVb = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
+    float *Vw32 = (float *)(ws + L.vw32);
+    void *Z = ws + L.z;
+    const int64_t ldv = m;
+    const int64_t pmin = std::min(m, n);
+
+    HIP_TRY(launch_ws_reset(a.ctl, (int32_t *)(ws + L.flag), n, s));
+    // NaN/Inf raises the control block's flag: the loop then ends at its first
+    // selection with nothing written
+    HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
+    HIP_TRY(launch_init(a, s));
+
+    if (prof.on) {
+        if (grow_events(pc.prof_ev, 3) != 0) return QRDM_ERR_NOMEM;
+        HIP_TRY(hipEventRecord(pc.prof_ev[0], s));
+    }
+    const int rows_per_wg = panel_rows_for(m, std::min<int>(p.kmax, QK_KM));
+    bool switch_qp3 = false, finished = false;
+    int64_t ns_known = 0, nrec = 0, iter = 0;
+    const int ring = pc.ring;
+    Snapshot last;
+    memset(&last, 0, sizeof last);
+    while (!finished) {
+        const int64_t tb = m - ns_known, wb = n - ns_known;
+        hipEvent_t *ev = nullptr;
+        if (prof.on) {
+            if (grow_events(pc.prof_ev, kEv * (size_t)(iter + 1) + 3) != 0) return QRDM_ERR_NOMEM;
+            ev = pc.prof_ev.data() + 3 + kEv * iter;
+            prof.dm_iters = iter + 1;
+            HIP_TRY(hipEventRecord(ev[0], s));
+        }
+        HIP_TRY(launch_select(a, s));
+        HIP_TRY(launch_gram(a, Gp, tb, s));
+        HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
+        HIP_TRY(launch_dm_finish(a, G, nullptr, s));
+        HIP_TRY(launch_swap(a, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+        // the device is at most lag + 1 blocks of at most kmax columns ahead of
+        // ns_known, and the block's own k_s <= kmax columns leave the trailing
+        // part (one block more of slack; k_gemm1 flags a grid that is too small)
+        const int64_t wlo = wb - (int64_t)(lag + 3) * p.kmax;
+        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, wlo, s,
+                             ev ? ev + 3 : nullptr));
+        {
+            QrdmArgs al = a;
+            al.snap = pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the downdate kernel
+            HIP_TRY(launch_downdate(al, wb, s));
+        }
+        if (ev) HIP_TRY(hipEventRecord(ev[7], s));
+        HIP_TRY(hipEventRecord(pc.events[iter % ring], s));
+        if (iter >= lag) {
+            const int64_t k = iter - lag;
+            HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
+            const Snapshot sn = pc.host_snap[k % ring];
+            if (sn.ns > ns_known) ns_known = sn.ns;
+            // a step that took a block (not the one that ended the loop or passed it
+            // to the column-pivoting kernels)
+            if (env.log && !sn.done && sn.l > 0) {
+                if (nrec < env.log_cap) {
+                    qrdm_block b;
+                    b.ns = sn.ns;
+                    b.nL = sn.nL;
+                    b.ks = sn.ks;
+                    b.l = sn.l;
+                    b.fallback = 0;
+                    b.umax = sn.umax;
+                    b.gamma = sn.gamma;
+                    b.sigma_bound = sn.sigma_bound;
+                    env.log[nrec] = b;
+                }
+                ++nrec;
+            }
+            if (sn.done) {
+                finished = true;
+                last = sn;
+            } else if (sn.fallback) {
+                switch_qp3 = true;
+                if (env.log) {  // the hand-over: column pivoting from column sn.ns on
+                    if (nrec < env.log_cap) {
+                        qrdm_block b;
+                        memset(&b, 0, sizeof b);
+                        b.ns = sn.ns;
+                        b.fallback = 1;
+                        b.umax = sn.umax;
+                        env.log[nrec] = b;
+                    }
+                    ++nrec;
+                }
+            }
+        }
+        ++iter;
+        if (switch_qp3) break;
+        // every step that neither ends nor hands over takes >= 1 column
+        if (iter > pmin + lag + 4) return QRDM_ERR_INTERNAL;
+    }
+    if (prof.on) HIP_TRY(hipEventRecord(pc.prof_ev[1], s));
+    if (switch_qp3) {
+        // the partial norms reached the noise level (eq. column_norm_bound_DM):
+        // the rest is scalar pivoting, run in the blocked column-pivoting form
+        int rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s, pc, prof, &last);
+        if (rc) return rc;
+    }
+    if (prof.on) HIP_TRY(hipEventRecord(pc.prof_ev[2], s));
+    if (env.rank_dev) HIP_TRY(launch_rank_out(a.ctl, env.rank_dev, s));
+    if (env.nlog) *env.nlog = nrec;
+    *final = last;
+    return 0;
+}
+
+int snapshot_code(const Snapshot &sn) {
+    if (sn.nonfinite) return QRDM_ERR_NONFINITE;
+    if (sn.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
+    return 0;
+}
+
+// Trivial shapes (min(m, n) = 0): perm = identity, rank 0.
+__global__ void k_trivial(int32_t *perm, int64_t n, int64_t *rank_dev) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) perm[i] = (int32_t)i;
+    if (i == 0 && rank_dev) *rank_dev = 0;
+}
+int trivial(int32_t *perm, int64_t n, int64_t *rank_dev, hipStream_t s) {
+    const int64_t cnt = std::max<int64_t>(n, 1);
+    hipLaunchKernelGGL(k_trivial, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, perm, n, rank_dev);
+    HIP_TRY(hipGetLastError());
+    return 0;
+}
+
+// Arguments of the factorization entry points after the parameters: -6..-8.
+int check_outputs(int64_t m, int64_t n, const double *tau_house, const int32_t *perm) {
+    if (std::min(m, n) > 0 && !tau_house) return -6;
+    if (n > 0 && !perm) return -7;
     return 0;
 }
 
@@ -298,18 +612,31 @@ const char *qrdm_strerror(int code) {
     if (code == QRDM_ERR_NONFINITE) return "matrix contains NaN or Inf";
     if (code == QRDM_ERR_NOMEM) return "workspace allocation failed";
     if (code == QRDM_ERR_UNSUPPORTED) return "size not supported by the kernels";
+    if (code == QRDM_ERR_INTERNAL) return "internal error: the host loop exceeded its bound on the steps";
+    if (code == QRDM_ERR_WORKSPACE) return "workspace smaller than qrdm_workspace_size";
     if (code >= QRDM_ERR_HIP) return hipGetErrorString((hipError_t)(code - QRDM_ERR_HIP));
     return "unknown error";
 }
 
 void qrdm_release(void) {
-    if (g_ws.base) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(g_ws.base);
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        if (g_ws.base) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(g_ws.base);
+        }
+        g_ws = CachedWs();
     }
-    if (g_ws.host_snap) (void)hipHostFree(g_ws.host_snap);
-    for (auto e : g_ws.events) (void)hipEventDestroy(e);
-    g_ws = Workspace();
+    std::lock_guard<std::mutex> g(g_poll_mu);
+    for (PollCtx *pc : g_poll_free) poll_destroy(pc);
+    g_poll_free.clear();
+}
+
+size_t qrdm_workspace_size(int64_t m, int64_t n, const qrdm_params *p) {
+    if (m < 0 || n < 0) return 0;
+    qrdm_params q;
+    if (p) q = *p; else qrdm_default_params(&q);
+    return make_layout(m, n, q.kmax).total;
 }
 
 int qrdm_colnorms(const double *A, int64_t m, int64_t n, int64_t lda, double *out, void *stream) {
@@ -318,13 +645,13 @@ int qrdm_colnorms(const double *A, int64_t m, int64_t n, int64_t lda, double *ou
     if (n > 0 && !out) return -5;
     if (n == 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    Layout L = make_layout(m, n);
-    rc = ensure_workspace(L.total, 8);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Layout L = make_layout(m, n, 1);
+    rc = ensure_workspace(L.total);
     if (rc) return rc;
     QrdmCtl *ctl = (QrdmCtl *)(g_ws.base + L.ctl);
     double *vn2 = (double *)(g_ws.base + L.vn2);
-    QrdmCtl c0 = initial_ctl();
-    HIP_TRY(hipMemcpyAsync(ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_ws_reset(ctl, (int32_t *)(g_ws.base + L.flag), n, s));
     HIP_TRY(launch_colnorm(A, m, n, lda, out, vn2, ctl, s));
     int32_t nf = 0;
     HIP_TRY(hipMemcpyAsync(&nf, &ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
@@ -339,193 +666,101 @@ int qrdm_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
     if (pin) p = *pin; else qrdm_default_params(&p);
     int rc = check_common(A, m, n, lda, &p);
     if (rc) return rc;
-    const int64_t pmin = std::min(m, n);
-    if (pmin > 0 && !tau_house) return -6;
-    if (n > 0 && !perm) return -7;
+    rc = check_outputs(m, n, tau_house, perm);
+    if (rc) return rc;
     if (!rank) return -8;
     if (log && log_cap < 0) return -11;
     if (n > 32768 || m > 65536) return QRDM_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof *stats);
     if (nlog) *nlog = 0;
-    if (pmin == 0) {
-        if (n > 0) {
-            std::vector<int32_t> id(n);
-            for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
-            HIP_TRY(hipMemcpyAsync(perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
-        }
+    if (std::min(m, n) == 0) {
+        rc = trivial(perm, n, nullptr, s);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(s));
         *rank = 0;
+        if (stats) stats->qp3_start = -1;
         return 0;
     }
-    const int lag = log ? 0 : p.poll_lag;
-    Layout L = make_layout(m, n);
-    rc = ensure_workspace(L.total, lag + 2);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    CallEnv env;
+    env.L = make_layout(m, n, p.kmax);
+    rc = ensure_workspace(env.L.total);
     if (rc) return rc;
-    char *ws = g_ws.base;
-    QrdmArgs a;
-    a.A = A;
-    a.m = m;
-    a.n = n;
-    a.lda = lda;
-    a.tau = p.tau;
-    a.delta = p.delta;
-    a.kmax = p.kmax;
-    a.stop_rule = p.stop_rule;
-    a.certified = p.certified;
-    // working precision of the trailing data: 2^-52 (FP64) or 2^-23 (FP32 updates)
-    const double eps_w = (p.precision == QRDM_PREC_MIXED) ? 1.1920928955078125e-07 : 2.220446049250313e-16;
-    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * eps_w;
-    a.fbeps = (double)n * eps_w;
-    a.tol3z = sqrt(eps_w);
-    a.vn1 = (double *)(ws + L.vn1);
-    a.vn2 = (double *)(ws + L.vn2);
-    a.perm = perm;
-    a.tau_house = tau_house;
-    a.gbar = (uint32_t *)(ws + L.gbar);
-    a.ctl = (QrdmCtl *)(ws + L.ctl);
-    double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
-    double *VVb = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
-    float *Vw32 = (float *)(ws + L.vw32);
-    void *Z = ws + L.z;
-    const int64_t ldv = m;
-
-    QrdmCtl c0 = initial_ctl();
-    HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
-    // the GEMM tile counters self-reset, but their place in the cached workspace
-    // depends on (m, n): clear them for this call
-    HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
-    int32_t nf = 0;
-    HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (nf) return QRDM_ERR_NONFINITE;
-    HIP_TRY(launch_init(a, s));
-
-    if (p.profile) {
-        if (prof_events(3) != 0) return QRDM_ERR_NOMEM;
-        HIP_TRY(hipEventRecord(g_prof_ev[0], s));
-    }
-    const int rows_per_wg = panel_rows_for(m, std::min<int>(p.kmax, QK_KM));
-    bool switch_qp3 = false;
-    HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
-    int64_t ns_known = 0;
-    int64_t nrec = 0;
-    int64_t iter = 0;
-    bool finished = false;
-    const int ring = g_ws.ring;
-    const int64_t max_iter = pmin + 2;
-    // profile events per block: [0] select, [1] panel, [2] panel end, [3..6] the two
-    // GEMMs (start/end each), [7] downdate end; g_prof_ev[0..2] = loop start, QP3
-    // start, loop end
-    const int kEv = 8;
-    while (!finished) {
-        const int64_t tb = m - ns_known, wb = n - ns_known;
-        hipEvent_t *ev = nullptr;
-        if (p.profile) {
-            if (prof_events(kEv * (size_t)(iter + 1) + 3) != 0) return QRDM_ERR_NOMEM;
-            ev = g_prof_ev.data() + 3 + kEv * iter;
-            HIP_TRY(hipEventRecord(ev[0], s));
-        }
-        HIP_TRY(launch_select(a, s));
-        HIP_TRY(launch_gram(a, Gp, tb, s));
-        HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
-        HIP_TRY(launch_dm_finish(a, G, nullptr, s));
-        HIP_TRY(launch_swap(a, s));
-        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
-        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-        // the device is at most lag + 1 blocks of at most kmax columns ahead of
-        // ns_known, and the block's own k_s <= kmax columns leave the trailing
-        // part (one block more of slack; k_gemm1 flags a grid that is too small)
-        const int64_t wlo = wb - (int64_t)(lag + 3) * p.kmax;
-        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, wlo, s,
-                             ev ? ev + 3 : nullptr));
-        {
-            QrdmArgs al = a;
-            al.snap = g_ws.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the downdate kernel
-            HIP_TRY(launch_downdate(al, wb, s));
-        }
-        if (ev) HIP_TRY(hipEventRecord(ev[7], s));
-        HIP_TRY(hipEventRecord(g_ws.events[iter % ring], s));
-        if (iter >= lag) {
-            const int64_t k = iter - lag;
-            HIP_TRY(hipEventSynchronize(g_ws.events[k % ring]));
-            const Snapshot sn = g_ws.host_snap[k % ring];
-            if (sn.ns > ns_known) ns_known = sn.ns;
-            if (log && !sn.done) {
-                if (nrec < log_cap) {
-                    qrdm_block b;
-                    b.ns = sn.ns;
-                    b.nL = sn.nL;
-                    b.ks = sn.ks;
-                    b.l = sn.l;
-                    b.fallback = sn.fallback;
-                    b.umax = 0.0;
-                    b.gamma = sn.gamma;
-                    b.sigma_bound = sn.sigma_bound;
-                    log[nrec] = b;
-                }
-                ++nrec;
-            }
-            if (sn.done) finished = true;
-            if (sn.fallback && !sn.done) switch_qp3 = true;
-        }
-        ++iter;
-        if (switch_qp3) break;
-        if (iter > max_iter + lag + 1) break;  // cannot happen: every block advances n_s
-    }
-    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
-    Qp3Prof qprof;
-    qprof.on = p.profile != 0;
-    if (switch_qp3 && !finished) {
-        // the partial norms reached the noise level: the rest is scalar pivoting,
-        // run in the blocked column-pivoting form (deferred trailing update)
-        rc = run_qp3(a, ws, L, kQp3Nb, lag, ns_known, s, &qprof);
-        if (rc) return rc;
-    }
-    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[2], s));
+    PollGuard pg;
+    pg.s = s;
+    rc = poll_acquire((log ? 0 : p.poll_lag) + 2, &pg.pc);
+    if (rc) return rc;
+    env.ws = g_ws.base;
+    env.pc = pg.pc;
+    env.s = s;
+    env.log = log;
+    env.log_cap = log_cap;
+    env.nlog = nlog;
+    env.rank_dev = nullptr;
+    ProfRun prof;
+    prof.on = p.profile != 0;
+    Snapshot fin;
+    rc = qrdm_run(A, m, n, lda, p, tau_house, perm, env, prof, &fin);
+    if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;
-    HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
-    if (stats && p.profile) {
-        // intervals (e, e+1): 0 DM selection, 1 panel, 3 GEMM1 (with the fused
-        // recurrence), 5 GEMM2, 6 downdate; 2 and 4 are empty gaps
-        double t[kEv - 1] = {0};
-        for (int64_t k = 0; k < iter; ++k) {
-            hipEvent_t *ev = g_prof_ev.data() + 3 + kEv * k;
-            for (int e = 0; e + 1 < kEv; ++e) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) == hipSuccess) t[e] += ms;
-            }
-        }
-        stats->dm_ms = t[0];
-        stats->panel_ms = t[1];
-        stats->gemm1_ms = t[3];
-        stats->gemm2_ms = t[5];
-        stats->downdate_ms = t[6];
-        stats->gemm_flop = cf.flop_gemm;
-        stats->panel_flop = cf.flop_panel;
-        stats->panel_bytes = cf.bytes_panel;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, g_prof_ev[1], g_prof_ev[2]) == hipSuccess) stats->qp3_ms = ms;
-        if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[2]) == hipSuccess) stats->total_ms = ms;
-        stats->nqp3_launch = qprof.launches;
-        stats->qp3_run_ms = qp3_run_ms(qprof.launches);
-        stats->qp3_bytes = qprof.launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
-    }
+    HIP_TRY(hipMemcpy(&cf, env.ws + env.L.ctl, sizeof cf, hipMemcpyDeviceToHost));
+    if (cf.nonfinite) return QRDM_ERR_NONFINITE;
     if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     *rank = cf.rank >= 0 ? cf.rank : cf.ns;
     if (stats) {
-        stats->nblocks = cf.nblocks;
-        stats->nbreaks = cf.nbreaks;
-        stats->nfallback = cf.nfallback;
-        stats->nrecompute = cf.nrecompute;
-        stats->ncols_factored = cf.ns;
-        stats->npanel = cf.npanel;
+        stats_fill(cf, stats);
+        if (prof.on) prof_fill(prof, *pg.pc, cf, m, n, stats);
     }
-    if (nlog) *nlog = nrec;
-    if (log && lag == 0) {
-        // umax of every logged block is not in the snapshot; leave 0
+    return 0;
+}
+
+int qrdm_factor_ws(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *pin, double *tau_house,
+                   int32_t *perm, int64_t *rank_dev, qrdm_stats *stats, void *workspace, size_t ws_bytes,
+                   void *stream) {
+    qrdm_params p;
+    if (pin) p = *pin; else qrdm_default_params(&p);
+    int rc = check_common(A, m, n, lda, &p);
+    if (rc) return rc;
+    rc = check_outputs(m, n, tau_house, perm);
+    if (rc) return rc;
+    if (!rank_dev) return -8;
+    if (p.profile) return -5;  // timing events are for qrdm_factor_ex
+    if (n > 32768 || m > 65536) return QRDM_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (std::min(m, n) == 0) {
+        if (stats) stats->qp3_start = -1;
+        return trivial(perm, n, rank_dev, s);
+    }
+    CallEnv env;
+    env.L = make_layout(m, n, p.kmax);
+    if (!workspace) return -10;
+    if (ws_bytes < env.L.total) return QRDM_ERR_WORKSPACE;
+    if (((uintptr_t)workspace & 255) != 0) return -10;
+    PollGuard pg;
+    pg.s = s;
+    rc = poll_acquire(p.poll_lag + 2, &pg.pc);
+    if (rc) return rc;
+    env.ws = (char *)workspace;
+    env.pc = pg.pc;
+    env.s = s;
+    env.log = nullptr;
+    env.log_cap = 0;
+    env.nlog = nullptr;
+    env.rank_dev = rank_dev;
+    ProfRun prof;
+    Snapshot fin;
+    rc = qrdm_run(A, m, n, lda, p, tau_house, perm, env, prof, &fin);
+    if (rc) return rc;
+    rc = snapshot_code(fin);
+    if (rc) return rc;
+    if (stats) {
+        QrdmCtl cf;
+        HIP_TRY(hipMemcpyAsync(&cf, env.ws + env.L.ctl, sizeof cf, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        stats_fill(cf, stats);
     }
     return 0;
 }
@@ -555,8 +790,9 @@ int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
     if (!L || !nL || !J || !ks) return -10;
     if (n > 32768) return QRDM_ERR_UNSUPPORTED;
     hipStream_t s = (hipStream_t)stream;
-    Layout Ly = make_layout(m, n);
-    rc = ensure_workspace(Ly.total, 8);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Layout Ly = make_layout(m, n, kmax);
+    rc = ensure_workspace(Ly.total);
     if (rc) return rc;
     char *ws = g_ws.base;
     QrdmArgs a;
@@ -569,8 +805,8 @@ int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
     a.kmax = kmax;
     a.stop_rule = QRDM_STOP_NONE;
     a.eps1 = 0.0;
-    a.fbeps = (double)n * 2.220446049250313e-16;
-    a.tol3z = 1.4901161193847656e-08;
+    a.fbeps = (double)n * kEps64;
+    a.tol3z = sqrt(kEps64);
     a.vn1 = (double *)(ws + Ly.vn1);
     a.vn2 = (double *)(ws + Ly.vn2);
     a.perm = (int32_t *)(ws + Ly.perm_dbg);
@@ -581,11 +817,12 @@ int qrdm_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
     std::vector<int32_t> id(n);
     for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
     HIP_TRY(hipMemcpyAsync(a.perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-    QrdmCtl c0 = initial_ctl();
+    QrdmCtl c0;
+    memset(&c0, 0, sizeof c0);
     c0.ns = ns;
     c0.rank = 0;        // stopping test already decided: not applied here
     c0.nblocks = 1;     // keep amax as given
-    c0.amax = 2.2250738585072014e-308;  // fallback test never fires for a non-zero trailing block
+    c0.amax = 2.2250738585072014e-308;  // the switch to scalar pivoting never fires for a non-zero trailing block
     HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
     double *Gp = (double *)(ws + Ly.gp), *G = (double *)(ws + Ly.g), *th = (double *)(ws + Ly.theta);
     HIP_TRY(launch_select(a, s));
@@ -619,7 +856,7 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     p.precision = QRDM_PREC_FP64;
     int rc = check_common(A, m, n, lda, &p);
     if (rc) return rc;
-    if (nb < 1 || nb > 64) return -6;
+    if (nb < 1 || nb > kQp3NbMax) return -6;
     const int64_t pmin = std::min(m, n);
     if (pmin > 0 && !tau_house) return -7;
     if (n > 0 && !perm) return -8;
@@ -628,17 +865,20 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof *stats);
     if (pmin == 0) {
-        if (n > 0) {
-            std::vector<int32_t> id(n);
-            for (int64_t j = 0; j < n; ++j) id[j] = (int32_t)j;
-            HIP_TRY(hipMemcpyAsync(perm, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-            HIP_TRY(hipStreamSynchronize(s));
-        }
+        rc = trivial(perm, n, nullptr, s);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(s));
         *rank = 0;
+        if (stats) stats->qp3_start = -1;
         return 0;
     }
-    Layout L = make_layout(m, n);
-    rc = ensure_workspace(L.total, p.poll_lag + 2);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Layout L = make_layout(m, n, 1);
+    rc = ensure_workspace(L.total);
+    if (rc) return rc;
+    PollGuard pg;
+    pg.s = s;
+    rc = poll_acquire(p.poll_lag + 2, &pg.pc);
     if (rc) return rc;
     char *ws = g_ws.base;
     QrdmArgs a;
@@ -651,48 +891,51 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
     a.delta = 0.0;
     a.kmax = 1;
     a.stop_rule = p.stop_rule;
-    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * 2.220446049250313e-16;
-    a.fbeps = (double)n * 2.220446049250313e-16;
-    a.tol3z = 1.4901161193847656e-08;
+    a.eps1 = (p.eps1_scale > 0.0 ? p.eps1_scale : (double)n) * kEps64;
+    a.fbeps = (double)n * kEps64;
+    a.tol3z = sqrt(kEps64);
     a.vn1 = (double *)(ws + L.vn1);
     a.vn2 = (double *)(ws + L.vn2);
     a.perm = perm;
     a.tau_house = tau_house;
     a.gbar = (uint32_t *)(ws + L.gbar);
     a.ctl = (QrdmCtl *)(ws + L.ctl);
-    QrdmCtl c0 = initial_ctl();
-    HIP_TRY(hipMemcpyAsync(a.ctl, &c0, sizeof c0, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ws + L.flag, 0, sizeof(int32_t) * (size_t)n, s));
+    HIP_TRY(launch_ws_reset(a.ctl, (int32_t *)(ws + L.flag), n, s));
     HIP_TRY(launch_colnorm(A, m, n, lda, a.vn1, a.vn2, a.ctl, s));
-    int32_t nf = 0;
-    HIP_TRY(hipMemcpyAsync(&nf, &a.ctl->nonfinite, sizeof nf, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (nf) return QRDM_ERR_NONFINITE;
     HIP_TRY(launch_init(a, s));
-    Qp3Prof qprof;
-    qprof.on = p.profile != 0;
-    if (p.profile) {
-        if (prof_events(2) != 0) return QRDM_ERR_NOMEM;
-        HIP_TRY(hipEventRecord(g_prof_ev[0], s));
+    ProfRun prof;
+    prof.on = p.profile != 0;
+    if (prof.on) {
+        if (grow_events(pg.pc->prof_ev, 3) != 0) return QRDM_ERR_NOMEM;
+        HIP_TRY(hipEventRecord(pg.pc->prof_ev[0], s));
     }
-    rc = run_qp3(a, ws, L, nb, p.poll_lag, 0, s, &qprof);
+    Snapshot fin;
+    rc = run_qp3(a, ws, L, nb, p.poll_lag, 0, s, *pg.pc, prof, &fin);
     if (rc) return rc;
-    if (p.profile) HIP_TRY(hipEventRecord(g_prof_ev[1], s));
+    if (prof.on) HIP_TRY(hipEventRecord(pg.pc->prof_ev[1], s));
     HIP_TRY(hipStreamSynchronize(s));
     QrdmCtl cf;
     HIP_TRY(hipMemcpy(&cf, a.ctl, sizeof cf, hipMemcpyDeviceToHost));
+    if (cf.nonfinite) return QRDM_ERR_NONFINITE;
     if (cf.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     *rank = cf.rank >= 0 ? cf.rank : cf.ns;
     if (stats) {
         stats->nblocks = cf.nblocks;
         stats->nrecompute = cf.nrecompute;
         stats->ncols_factored = cf.ns;
-        if (p.profile) {
+        stats->qp3_start = 0;
+        if (prof.on) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, g_prof_ev[0], g_prof_ev[1]) == hipSuccess) stats->qp3_ms = stats->total_ms = ms;
-            stats->nqp3_launch = qprof.launches;
-            stats->qp3_run_ms = qp3_run_ms(qprof.launches);
-            stats->qp3_bytes = qprof.launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
+            if (hipEventElapsedTime(&ms, pg.pc->prof_ev[0], pg.pc->prof_ev[1]) == hipSuccess)
+                stats->qp3_ms = stats->total_ms = ms;
+            stats->nqp3_launch = prof.qp_launches;
+            double q = 0.0;
+            for (int64_t i = 0; i < prof.qp_launches; ++i) {
+                float x = 0.f;
+                if (hipEventElapsedTime(&x, pg.pc->qp_ev[2 * i], pg.pc->qp_ev[2 * i + 1]) == hipSuccess) q += x;
+            }
+            stats->qp3_run_ms = q;
+            stats->qp3_bytes = prof.qp_launches > 0 ? qp3_bytes(m, n, cf.qp3_start, cf.ns) : 0.0;
         }
     }
     return 0;

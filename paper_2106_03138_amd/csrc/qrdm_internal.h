@@ -16,18 +16,20 @@ struct QrdmCtl {
     int32_t ks;      // accepted columns of the current step (k_s)
     int32_t nL;      // candidate list length (0 when done)
     int32_t done;    // 1 = no further step
-    int32_t fallback;  // current step uses scalar pivoting
+    int32_t fallback;  // 1 = the partial norms reached the noise level (eq.
+                       // column_norm_bound_DM): the selection that found it took no
+                       // block, and every kernel of the DM loop is idle from then
+                       // on; the column-pivoting kernels continue from n_s (sticky)
     int32_t jmax;
     double gamma;        // Lemma 1 on the current step's accepted columns: diagonal-dominance gap
     double sigma_bound;  // and the lower bound of their sigma_min (0 if the lemma does not apply)
-    int32_t nswap;     // column moves of the current step
-    int32_t nonfinite; // set by the norm sweep
+    double umax;       // max partial norm of the current step
+    int32_t nonfinite; // set by the norm sweep: the loop ends before writing anything
     int32_t error;     // 2: a grid barrier wait timed out; 4: a launch grid smaller
                        // than the kernel's partition (host sizing); either fails the call
-    uint32_t bar;      // unused (the grid barriers count in the workspace's gbar sets)
-    uint32_t bar2;     // unused
+    int32_t nswap;     // column moves of the current step
+    int32_t pad0;
     double amax;       // max initial column norm
-    double umax;       // max partial norm of the current step
     double eps_s;      // panel break threshold tau*umax
     // statistics
     int64_t nblocks, nbreaks, nfallback, nrecompute;
@@ -75,9 +77,10 @@ struct QrdmArgs {
 
 // ------------------------------------------------------------------ helpers
 // The host polls the first QRDM_SNAP_WORDS 8-byte words of QrdmCtl (n_s, rank,
-// l, k_s, |L|, done, fallback, arg-max, gamma, bound).  The last kernel of a
-// step writes them into a slot of pinned host memory, so no copy is queued.
-#define QRDM_SNAP_WORDS 7
+// l, k_s, |L|, done, fallback, arg-max, gamma, bound, max partial norm, the
+// non-finite and error flags).  The last kernel of a step writes them into a
+// slot of pinned host memory, so no copy is queued.
+#define QRDM_SNAP_WORDS 9
 __device__ __forceinline__ void qrdm_write_snapshot(const QrdmCtl *c, uint64_t *dst) {
     const uint64_t *src = (const uint64_t *)c;
     for (int i = 0; i < QRDM_SNAP_WORDS; ++i) dst[i] = src[i];
@@ -90,6 +93,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ int64_t p_of(const QrdmArgs &a) { return a.m < a.n ? a.m : a.n; }
+
+// The kernels of a DM step (Algorithm 4) have nothing to do once the loop is
+// done or has passed to the column-pivoting kernels.
+__device__ __forceinline__ bool qrdm_dm_idle(const QrdmCtl *c) { return c->done || c->fallback; }
 
 // Grid barrier of the persistent kernels (all G workgroups resident): workgroup
 // w adds one to counter w % 16 (one counter per group of workgroups, 256 B
@@ -169,6 +176,8 @@ hipError_t launch_resident(const void *kernel, dim3 grid, dim3 block, void **arg
 hipError_t launch_colnorm(const double *A, int64_t m, int64_t n, int64_t lda, double *vn1, double *vn2,
                           QrdmCtl *ctl, hipStream_t s);
 hipError_t launch_init(QrdmArgs a, hipStream_t s);
+hipError_t launch_ws_reset(QrdmCtl *ctl, int32_t *flag, int64_t n, hipStream_t s);
+hipError_t launch_rank_out(const QrdmCtl *ctl, int64_t *rank, hipStream_t s);
 hipError_t launch_select(QrdmArgs a, hipStream_t s);
 hipError_t launch_gram(QrdmArgs a, double *Gp, int64_t t_bound, hipStream_t s);
 hipError_t launch_gram_reduce(QrdmArgs a, const double *Gp, double *G, int64_t t_bound, hipStream_t s);

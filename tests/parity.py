@@ -24,14 +24,20 @@ def compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=Tr
     m, n = a.shape
     k = ref.first_low_margin_block(ETA)
     ns_cut = ref.blocks[k].ns if k < len(ref.blocks) else min(m, n)
-    real = [b for b in ref.blocks if b.l > 0]  # the oracle also logs the stopping step
-    # block sequence identical up to the first low-margin decision
+    # the oracle also logs the stopping step (l = 0) and takes the scalar-pivoting
+    # steps of eq. (column_norm_bound_DM) in its own loop; the GPU's log holds the
+    # DM loop's blocks and, at the switch, one hand-over record (fallback, l = 0)
+    real = [b for b in ref.blocks[:k] if b.l > 0 and not b.fallback]
     if check_blocks:
-        for i in range(min(k, len(real))):
-            rb = real[i]
-            assert i < len(blocks), f"GPU log shorter than oracle at block {i}"
-            g = blocks[i]
+        dm = [g for g in blocks if g[3] > 0]
+        for i, rb in enumerate(real):
+            assert i < len(dm), f"GPU log shorter than oracle at block {i}"
+            g = dm[i]
             assert (g[0], g[1], g[2], g[3]) == (rb.ns, rb.nL, rb.ks, rb.l), f"block {i}: gpu {g} oracle {(rb.ns, rb.nL, rb.ks, rb.l)}"
+        fb_ref = next((b.ns for b in ref.blocks[:k] if b.fallback), None)
+        if fb_ref is not None:
+            hand = [g[0] for g in blocks if len(g) > 4 and g[4]]
+            assert hand == [fb_ref], f"switch to scalar pivoting: gpu {hand} oracle {fb_ref}"
     assert np.array_equal(perm[:ns_cut], ref.perm[:ns_cut])
     if k == len(ref.blocks):
         assert np.array_equal(perm, ref.perm)

@@ -34,6 +34,7 @@ int main(void) {
   printf("%zu %zu %zu\n", offsetof(qrdm_params, certified), offsetof(qrdm_block, gamma),
          offsetof(qrdm_block, sigma_bound));
   printf("%zu %zu %zu\n", sizeof(qrdm_batch_params), offsetof(qrdm_batch_params, kmax), sizeof(qrdm_batch_tune));
+  printf("%zu\n", offsetof(qrdm_stats, qp3_start));
   return 0;
 }
 """
@@ -50,7 +51,7 @@ def lib():
 
 def test_header_declares_the_expected_entry_points():
     names = _declared_functions()
-    for want in ["qrdm_factor", "qrdm_factor_ex", "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
+    for want in ["qrdm_factor", "qrdm_factor_ex", "qrdm_factor_ws", "qrdm_workspace_size", "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
                  "qrdm_dm_step", "qrdm_default_params", "qrdm_release", "qrdm_strerror", "qrdm_lstsq",
                  "qrdm_batch_lstsq", "qrdm_truncate_rank", "qrdm_batch_truncate_rank"]:
         assert want in names, names
@@ -78,7 +79,8 @@ def test_struct_layouts_match_the_header(tmp_path):
             _lib.Params.eps1_scale.offset, _lib.Params.profile.offset, _lib.Stats.total_ms.offset,
             _lib.Block.fallback.offset, _lib.Block.umax.offset,
             _lib.Params.certified.offset, _lib.Block.gamma.offset, _lib.Block.sigma_bound.offset,
-            ctypes.sizeof(_lib.BatchParams), _lib.BatchParams.kmax.offset, ctypes.sizeof(_lib.BatchTune)]
+            ctypes.sizeof(_lib.BatchParams), _lib.BatchParams.kmax.offset, ctypes.sizeof(_lib.BatchTune),
+            _lib.Stats.qp3_start.offset]
     assert got == want
 
 
@@ -90,7 +92,7 @@ def test_defaults_and_error_strings_without_a_device(lib):
     assert (p.tau, p.delta, p.kmax, p.stop_rule, p.precision, p.certified) == (0.15, 0.9, 64, 0, 0, 0)
     lib.qrdm_strerror.restype = ctypes.c_char_p
     lib.qrdm_strerror.argtypes = [ctypes.c_int]
-    for code in (0, 1, 2, 3, -1, 1001):
+    for code in (0, 1, 2, 3, 4, 5, -1, 1001):
         assert lib.qrdm_strerror(code)
 
 
@@ -161,3 +163,35 @@ def test_lstsq_and_truncation_reject_bad_arguments_on_the_host(lib):
     assert t(d, 8, 4, 4, 2, 0.0, d, None) == -4
     assert t(d, 8, 4, 8, 2, 0.0, None, None) == -7
     assert t(d, 8, 4, 8, 2, float("nan"), d, None) == -6
+
+
+def test_workspace_size_and_ws_arguments_on_the_host(lib):
+    """qrdm_workspace_size is a host computation; qrdm_factor_ws rejects a missing,
+    misaligned or short workspace before touching the device."""
+    from paper_2106_03138_amd import _lib
+    ws = lib.qrdm_workspace_size
+    ws.restype, ws.argtypes = _lib.SIGNATURES["qrdm_workspace_size"]
+    p = _lib.Params()
+    lib.qrdm_default_params(ctypes.byref(p))
+    assert ws(-1, 4, ctypes.byref(p)) == 0
+    small, big = ws(256, 256, ctypes.byref(p)), ws(8192, 8192, ctypes.byref(p))
+    assert 0 < small < big
+    assert ws(256, 256, None) == small  # NULL = the defaults (k_DM = 64)
+    # the largest parts grow with k_DM: partial products of V^T A and the Gram partials
+    p.kmax = 128
+    assert ws(4096, 4096, ctypes.byref(p)) > ws(4096, 4096, None)
+    p.kmax = 64
+    # 8192^2 with k_DM = 64 stays under 100 MB (about 0.03% of the device memory)
+    assert big < 100 * 2 ** 20
+    f = lib.qrdm_factor_ws
+    f.restype, f.argtypes = _lib.SIGNATURES["qrdm_factor_ws"]
+    d = ctypes.c_void_p(4096)
+    need = ws(64, 48, ctypes.byref(p))
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, d, None, None, need, None) == -10
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, ctypes.c_void_p(4096 + 8), None, ctypes.c_void_p(4104),
+             need, None) == -10  # misaligned workspace
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, d, None, d, need - 1, None) == _lib.ERR_WORKSPACE
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, None, None, d, need, None) == -8
+    assert f(d, 64, 48, 32, ctypes.byref(p), d, d, d, None, d, need, None) == -4
+    p.profile = 1
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, d, None, d, need, None) == -5

@@ -176,21 +176,77 @@ def test_deterministic():
 def test_bits_independent_of_poll_lag(precision):
     """The host polls the device's progress `poll_lag` steps behind and sizes the
     launches from that bound; the kernels take every split from the actual sizes,
-    so the blocks of Algorithm 4 come out the same to the bit for any lag, with or
-    without the block log (which polls every step).  The scalar-pivoting tail
-    starts where the host sees the switch, up to poll_lag single-column steps
-    late, so its rounding may differ: the comparison stops at its first step."""
+    so the factorization comes out the same to the bit for any lag, with or
+    without the block log (which polls every step).  The switch to scalar
+    pivoting is decided on the device, which idles the DM loop from that step on,
+    so the column-pivoting kernels start at the same column whatever the lag: the
+    comparison covers all n columns."""
     Q = _gpu()
     a = I.from_spectrum(1500, 1300, np.geomspace(1.0, 1e-16, 1300), 9)
     outs = []
     fb = None
+    starts = set()
     for lag, log in [(4, True), (0, False), (1, False), (4, False), (9, False)]:
         A = Q.device_matrix(a)
         o = Q.qrdm_factor(A, stop_rule=oracle.STOP_NONE, precision=precision, poll_lag=lag, log=log)
         if log:
-            fb = next(x[0] for x in o.blocks if x[4])
-        outs.append((Q.host_matrix(A), o.tau_house.cpu().numpy(), o.perm.cpu().numpy()))
-    assert fb > 100
-    for qr, tau, perm in outs[1:]:
-        assert np.array_equal(qr[:, :fb], outs[0][0][:, :fb]) and np.array_equal(tau[:fb], outs[0][1][:fb])
-        assert np.array_equal(perm[:fb], outs[0][2][:fb])
+            hand = [x for x in o.blocks if x[4]]
+            assert len(hand) <= 1 and all(x[3] == 0 for x in hand)
+            fb = hand[0][0] if hand else -1
+        starts.add(o.stats["qp3_start"])
+        outs.append((Q.host_matrix(A), o.tau_house.cpu().numpy(), o.perm.cpu().numpy(), o.rank))
+    assert starts == {fb}
+    if precision == 0:
+        assert fb > 100  # FP64: the geometric spectrum reaches n eps max||a_j|| before column n
+    else:
+        assert fb == -1  # FP32 rounding noise stays above the FP64 switch: DM blocks to the end
+    for qr, tau, perm, rank in outs[1:]:
+        assert np.array_equal(qr, outs[0][0]) and np.array_equal(tau, outs[0][1])
+        assert np.array_equal(perm, outs[0][2]) and rank == outs[0][3]
+
+
+def test_workspace_entry_two_streams():
+    """qrdm_factor_ws in caller-owned workspaces: two factorizations launched from
+    two host threads on two streams at once give the same bits and ranks as the
+    same calls run one after the other, and as qrdm_factor_ex."""
+    import threading
+
+    import torch
+    Q = _gpu()
+    mats = [I.from_spectrum(1100, 900, np.geomspace(1.0, 1e-9, 900), 21),
+            I.gaussian(1300, 700, 22)]
+    kw = dict(tau=0.15, delta=0.9, kmax=64, stop_rule=oracle.STOP_PAPER)
+    ref = []
+    for a in mats:
+        A = Q.device_matrix(a)
+        o = Q.qrdm_factor(A, **kw)
+        ref.append((Q.host_matrix(A), o.tau_house.cpu().numpy(), o.perm.cpu().numpy(), o.rank))
+    dev = torch.device("cuda")
+    wss = [torch.empty(Q.api.workspace_size(*a.shape, 64), dtype=torch.uint8, device=dev) for a in mats]
+    ranks = [torch.full((1,), -7, dtype=torch.int64, device=dev) for _ in mats]
+
+    def run(i, stream, out):
+        with torch.cuda.stream(stream):
+            A = Q.device_matrix(mats[i])
+            stream.synchronize()
+            o = Q.api.qrdm_factor_ws(A, wss[i], ranks[i], stream=stream, **kw)
+            stream.synchronize()
+            out[i] = (Q.host_matrix(A), o.tau_house.cpu().numpy(), o.perm.cpu().numpy(), int(ranks[i].item()))
+
+    for concurrent in (False, True):
+        out = [None, None]
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        if concurrent:
+            th = [threading.Thread(target=run, args=(i, streams[i], out)) for i in range(2)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+        else:
+            for i in range(2):
+                run(i, streams[i], out)
+        for i in range(2):
+            assert out[i] is not None, f"thread {i} failed"
+            qr, tau, perm, rank = out[i]
+            assert rank == ref[i][3]
+            assert np.array_equal(qr, ref[i][0]) and np.array_equal(tau, ref[i][1]) and np.array_equal(perm, ref[i][2])
