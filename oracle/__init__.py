@@ -15,6 +15,8 @@ import numpy as np
 from . import build_oracle
 
 STOP_PAPER, STOP_MAXNORM, STOP_NONE = 0, 1, 2
+# deliberate mistakes for the tests of the checks (oracle_params.plant)
+PLANT_SINGLE, PLANT_TRUNC, PLANT_ACCEPT, PLANT_NOBREAK, PLANT_FBSCALE, PLANT_DNORM, PLANT_REJECT = range(1, 8)
 
 _LIB = None
 
@@ -33,7 +35,7 @@ class OracleBlock(ctypes.Structure):
 class OracleParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("delta", ctypes.c_double), ("kmax", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("eps1_scale", ctypes.c_double),
-                ("max_ns", ctypes.c_int64), ("certified", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("max_ns", ctypes.c_int64), ("certified", ctypes.c_int32), ("plant", ctypes.c_int32)]
 
 
 def lib():
@@ -51,7 +53,7 @@ def lib():
         L.oracle_dm_step.argtypes = [dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                      dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), dp,
-                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
         L.oracle_block_size.restype = ctypes.c_size_t
         assert L.oracle_block_size() == ctypes.sizeof(OracleBlock)
         _LIB = L
@@ -82,8 +84,9 @@ class Result:
 
 def qrdm(a: np.ndarray, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
          stop_rule: int = STOP_PAPER, eps1_scale: float = 0.0, max_ns: int = -1,
-         log_cap: int | None = None, certified: bool = False) -> Result:
-    """Oracle QRDM2 (Algorithm 4) on a copy of a (m x n float64)."""
+         log_cap: int | None = None, certified: bool = False, plant: int = 0) -> Result:
+    """Oracle QRDM2 (Algorithm 4) on a copy of a (m x n float64).  plant != 0
+    (tests of the checks only) runs one of the deliberate mistakes PLANT_*."""
     a = np.array(a, dtype=np.float64, order="F", copy=True)
     m, n = a.shape
     p = min(m, n)
@@ -93,7 +96,7 @@ def qrdm(a: np.ndarray, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
     cap = log_cap if log_cap is not None else max(n, 1) + 2
     blocks = (OracleBlock * cap)()
     nb = ctypes.c_int64(0)
-    prm = OracleParams(tau, delta, kmax, stop_rule, eps1_scale, max_ns, 1 if certified else 0, 0)
+    prm = OracleParams(tau, delta, kmax, stop_rule, eps1_scale, max_ns, 1 if certified else 0, int(plant))
     code = lib().oracle_qrdm(_dp(a), m, n, max(m, 1), ctypes.byref(prm), _dp(tau_h),
                              perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(rank),
                              blocks, cap, ctypes.byref(nb))
@@ -106,7 +109,7 @@ def qrp(a: np.ndarray, stop_rule: int = STOP_PAPER, eps1_scale: float = 0.0, max
     return qrdm(a, tau=1.0, delta=0.0, kmax=1, stop_rule=stop_rule, eps1_scale=eps1_scale, max_ns=max_ns)
 
 
-def dm_step(a: np.ndarray, vn1: np.ndarray, ns: int, tau: float, delta: float, cap: int):
+def dm_step(a: np.ndarray, vn1: np.ndarray, ns: int, tau: float, delta: float, cap: int, plant: int = 0):
     """One DM selection (Algorithm 1) on [A]_{ns:m, ns:n}: returns (L, theta, J)."""
     a = np.asfortranarray(a, dtype=np.float64)
     m, n = a.shape
@@ -118,7 +121,7 @@ def dm_step(a: np.ndarray, vn1: np.ndarray, ns: int, tau: float, delta: float, c
     ks = ctypes.c_int32(0)
     code = lib().oracle_dm_step(_dp(a), m, n, m, ns, _dp(vn1), tau, delta, cap,
                                 L.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(nl), _dp(th),
-                                J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(ks))
+                                J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(ks), int(plant))
     if code != 0:
         raise RuntimeError(f"oracle_dm_step failed: {code}")
     k = nl.value

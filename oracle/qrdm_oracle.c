@@ -101,8 +101,18 @@ typedef struct {
     double eps1_scale; /* eps_1 = eps1_scale * eps; <= 0 means n */
     int64_t max_ns;    /* stop after ns >= max_ns (bounded runs); <0 = off */
     int32_t certified; /* 1 = delta <= tau^2 / (|L| - 1) per block, eq. (delta_max) */
-    int32_t pad;
+    int32_t plant;     /* 0 in every real use.  The tests set one of the O_PLANT_*
+                          mistakes below to show that their checks catch it.      */
 } oracle_params;
+
+/* Deliberate mistakes, for the tests of the checks only (never a reading):   */
+#define O_PLANT_SINGLE 1   /* every DM step keeps only the arg-max column         */
+#define O_PLANT_TRUNC 2    /* the panel stops after half of the accepted columns  */
+#define O_PLANT_ACCEPT 3   /* greedy acceptance skips the |theta| < delta test    */
+#define O_PLANT_NOBREAK 4  /* the panel never breaks (eq. lenght_check ignored)   */
+#define O_PLANT_FBSCALE 5  /* scalar-pivoting switch at eps*amax, without the n   */
+#define O_PLANT_DNORM 6    /* cosines scaled by the downdated norms, not sqrt(G_ii) */
+#define O_PLANT_REJECT 7   /* the last candidate that passes the test is dropped  */
 
 static double sq(double x) { return x * x; }
 
@@ -148,7 +158,7 @@ static int cand_cmp(const void *pa, const void *pb) {
 static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
                       const double *vn1, double tau, double delta, int64_t cap, int certified,
                       int64_t *L, int *nL, double *theta, int64_t *J, int *ks,
-                      oracle_block *rec, cand_t *work, double *G, double nu) {
+                      oracle_block *rec, cand_t *work, double *G, double nu, int plant) {
     int64_t t = m - ns;
     /* step 1: J = { argmax u }, lowest position on ties (R2) */
     int64_t jmax = ns;
@@ -181,6 +191,12 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
             G[a * nl + b] = s;
         }
     }
+    if (plant == O_PLANT_DNORM) {
+        /* the planted mistake: D from the partial-norm estimates */
+        for (int64_t a = 0; a < nl; ++a)
+            for (int64_t b = 0; b < nl; ++b)
+                if (a != b) G[a * nl + b] *= sqrt(G[a * nl + a] * G[b * nl + b]) / (vn1[L[a]] * vn1[L[b]]);
+    }
     for (int64_t a = 0; a < nl; ++a) {
         for (int64_t b = 0; b < nl; ++b) {
             double da = sqrt(G[a * nl + a]), db = sqrt(G[b * nl + b]);
@@ -198,6 +214,7 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
     J[0] = L[0];
     int k = 1;
     double mcos = INFINITY;
+    int64_t last_ok = -1; /* O_PLANT_REJECT: list index of the last accepted candidate */
     for (int64_t a = 1; a < nl; ++a) {
         double worst = 0.0;
         int ok = 1;
@@ -223,8 +240,11 @@ static void dm_select(const double *A, int64_t m, int64_t n, int64_t lda, int64_
             double mc = fabs(worst - delta);
             mcos = fmin(mcos, (mc <= nu / dmin) ? 0.0 : mc);
         }
-        if (ok) J[k++] = L[a];
+        if (plant == O_PLANT_ACCEPT && da > 0.0) ok = 1;
+        if (ok) { J[k++] = L[a]; last_ok = a; }
     }
+    if (plant == O_PLANT_REJECT && last_ok > 0) --k; /* drop the last accepted candidate */
+    if (plant == O_PLANT_SINGLE) k = 1;
     *ks = k;
     /* Lemma 1 on C = [A]_{ns:m, J}: gamma of the cosine matrix of J and the
      * lower bound of sigma_min(C), with tau_J the actual norm ratio inside J */
@@ -375,6 +395,7 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
         }
         /* eq. (column_norm_bound_DM): scalar pivoting near the noise level (R13) */
         double fb_thr = O_EPS * (double)n * amax;
+        if (prm->plant == O_PLANT_FBSCALE) fb_thr = O_EPS * amax;
         rec.m_fb = noise_margin(umax, fb_thr, nu);
         int64_t cap = kcap < (p - ns) ? kcap : (p - ns);
         int ks = 1, nl = 1;
@@ -393,7 +414,7 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
             rec.sigma_bound = norm2(A + jmax * lda + ns, m - ns);
         } else {
             dm_select(A, m, n, lda, ns, vn1, prm->tau, prm->delta, cap, prm->certified, L, &nl, NULL, J, &ks, &rec,
-                      work, G, nu);
+                      work, G, nu, prm->plant);
         }
         /* eq. (lenght_check): eps_s = tau * max u (R12) */
         double eps_s = prm->tau * umax;
@@ -422,7 +443,8 @@ int oracle_qrdm(double *A, int64_t m, int64_t n, int64_t lda, const oracle_param
             double nrm = sqrt(alpha * alpha + sp);
             if (i >= 1) {
                 mbreak = fmin(mbreak, noise_margin(nrm, eps_s, nu));
-                if (nrm < eps_s) break;
+                if (nrm < eps_s && prm->plant != O_PLANT_NOBREAK) break;
+                if (prm->plant == O_PLANT_TRUNC && 2 * i >= ks) break;
             }
             double beta, ti;
             if (sp == 0.0) {
@@ -554,17 +576,18 @@ int oracle_qrp(double *A, int64_t m, int64_t n, int64_t lda, int32_t stop_rule, 
 /*
  * One DM step (Algorithm 1) on the trailing part [A]_{ns:m, ns:n} with given
  * partial norms vn1[0..n) (only entries >= ns are read).  Exposed for unit
- * tests of the selection alone.  L, J: int64[cap]; theta: double[cap*cap].
+ * tests of the selection alone.  L, J: int64[cap]; theta: double[cap*cap];
+ * plant: 0, or an O_PLANT_* mistake (tests of the checks only).
  */
 int oracle_dm_step(const double *A, int64_t m, int64_t n, int64_t lda, int64_t ns,
                    const double *vn1, double tau, double delta, int64_t cap,
-                   int64_t *L, int32_t *nL, double *theta, int64_t *J, int32_t *ks) {
+                   int64_t *L, int32_t *nL, double *theta, int64_t *J, int32_t *ks, int32_t plant) {
     if (ns < 0 || ns >= n || ns >= m || cap < 1) return -5;
     cand_t *work = malloc(sizeof(cand_t) * (size_t)n);
     double *G = malloc(sizeof(double) * (size_t)(cap * cap));
     if (!work || !G) { free(work); free(G); return O_ERR_NOMEM; }
     int nl = 0, k = 0;
-    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, 0, L, &nl, theta, J, &k, NULL, work, G, 0.0);
+    dm_select(A, m, n, lda, ns, vn1, tau, delta, cap, 0, L, &nl, theta, J, &k, NULL, work, G, 0.0, plant);
     *nL = nl;
     *ks = k;
     free(work);

@@ -38,7 +38,9 @@ def _check_matrix(A):
     m, n = A.shape
     if m > 1 and n > 0 and A.stride(0) != 1:
         raise ValueError("A must be column-major (stride(0) == 1)")
-    lda = A.stride(1) if n > 1 else max(m, 1)
+    if m == 0 or n <= 1:
+        return m, n, max(m, 1)  # no second column: the stride is never used
+    lda = A.stride(1)
     if lda < max(m, 1):
         raise ValueError(f"A's column stride {lda} is below its {m} rows (columns would overlap)")
     return m, n, lda

@@ -104,6 +104,33 @@ def orthogonal_columns(m: int, norms: np.ndarray, seed: int = 0) -> tuple[np.nda
     return np.asfortranarray(a), order
 
 
+def paired_columns(m: int, npair: int, cos: float, seed: int = 0) -> np.ndarray:
+    """2*npair columns in pairs: column 2k is Gaussian, column 2k+1 is a unit
+    vector at angle arccos(cos) to it inside the plane of column 2k and a fresh
+    Gaussian direction, scaled to 0.999 of its norm.  Pairs are nearly
+    orthogonal to each other (m >> npair); the pair's cosine is `cos`, so the DM
+    cosine test separates the members of a pair when cos >= delta."""
+    rng = np.random.default_rng(seed)
+    q = haar_cols(m, 2 * npair, rng)
+    norms = np.exp(rng.uniform(-1.0, 1.0, npair))
+    a = np.empty((m, 2 * npair))
+    sn = np.sqrt(1.0 - cos * cos)
+    for k in range(npair):
+        a[:, 2 * k] = norms[k] * q[:, 2 * k]
+        a[:, 2 * k + 1] = 0.999 * norms[k] * (cos * q[:, 2 * k] + sn * q[:, 2 * k + 1])
+    return np.asfortranarray(a)
+
+
+def angles_in_plane(m: int, angles: np.ndarray, norms: np.ndarray, seed: int = 0) -> np.ndarray:
+    """Columns norms[i] * (cos(angles[i]) e + sin(angles[i]) f) for two orthonormal
+    vectors e, f of R^m (Haar), so the cosine of columns i and j is exactly
+    cos(angles[i] - angles[j])."""
+    rng = np.random.default_rng(seed)
+    q = haar_cols(m, 2, rng)
+    a = q[:, :1] * (norms * np.cos(angles))[None, :] + q[:, 1:2] * (norms * np.sin(angles))[None, :]
+    return np.asfortranarray(a)
+
+
 def three_directions(m: int = 16, seed: int = 0) -> np.ndarray:
     """Three unit columns at 0, 120 and 240 degrees in a random plane of R^m."""
     rng = np.random.default_rng(seed)

@@ -100,3 +100,54 @@ def test_planted_reflector_fails(geo):
     tau[7] *= 1 + 1e-8
     with pytest.raises(AssertionError, match="orthogonal"):
         V.check_reflectors(res.qr, tau, n)
+
+
+# ------------------------------------------- Algorithm 1 replayed from R alone
+def _log(res):
+    return [(b.ns, b.nL, b.ks, b.l, b.fallback) for b in res.blocks]
+
+
+def _case(name):
+    if name == "geo":
+        return I.from_spectrum(448, 384, np.geomspace(1.0, 1e-16, 384), 5), dict(tau=0.15, delta=0.9, kmax=32)
+    if name == "gauss":
+        return I.gaussian(300, 200, 3), dict(tau=0.15, delta=0.9, kmax=32)
+    if name == "rank64":
+        return I.small_rank64(1), dict(tau=0.9, delta=0.9, kmax=32)
+    if name == "paired":
+        return I.paired_columns(200, 40, 0.95, 4), dict(tau=0.15, delta=0.9, kmax=32)
+    raise KeyError(name)
+
+
+def _replay(a, res, kw):
+    amax = np.linalg.norm(a, axis=0).max()
+    nu = 4 * V.EPS * np.linalg.norm(a)
+    return V.check_dm_replay(res.qr, _log(res), kw["tau"], kw["delta"], kw["kmax"], amax, nu)
+
+
+@pytest.mark.parametrize("name", ["geo", "gauss", "rank64", "paired"])
+def test_replay_holds_on_oracle(name):
+    a, kw = _case(name)
+    res = oracle.qrdm(a, stop_rule=oracle.STOP_NONE, **kw)
+    out = _replay(a, res, kw)
+    assert out["blocks"] > 0
+    if name == "paired":  # candidates rejected by the cosine test
+        assert out["greedy_checked"] + out["maximal_no_break"] > 0
+    if name in ("geo", "rank64"):
+        assert out["breaks"] > 0 and out["switch"] is not None
+
+
+@pytest.mark.parametrize("plant,name,msg", [
+    (oracle.PLANT_SINGLE, "gauss", "not maximal"),        # a run of single pivots
+    (oracle.PLANT_TRUNC, "gauss", "break after"),          # blocks cut short without the break test
+    (oracle.PLANT_ACCEPT, "paired", "cos"),                # a block with a conflicting pair
+    (oracle.PLANT_REJECT, "gauss", "not maximal"),         # a conflict-free candidate dropped
+    (oracle.PLANT_NOBREAK, "rank64", "missed break"),      # the length check of Algorithm 4 ignored
+    (oracle.PLANT_FBSCALE, "geo", "switch level"),         # the scalar-pivoting switch at eps, not n eps
+])
+def test_replay_catches_planted_mistakes(plant, name, msg):
+    a, kw = _case(name)
+    res = oracle.qrdm(a, stop_rule=oracle.STOP_NONE, plant=plant, **kw)
+    with pytest.raises(AssertionError, match=msg):
+        V.check_blocks(res.qr, _log(res), kw["tau"], kw["delta"], a.shape[1], tail_single=False)
+        _replay(a, res, kw)

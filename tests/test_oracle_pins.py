@@ -365,3 +365,65 @@ def test_invalid_arguments():
     assert oracle.qrdm(a, tau=1.5).code == -5
     assert oracle.qrdm(a, delta=-0.1).code == -5
     assert oracle.qrdm(a, kmax=0).code == -5
+
+
+# -------------------------------- the switch to scalar pivoting (closed form)
+def test_switch_to_scalar_pivoting_closed_form():
+    """Section 4 switches to one pivot per step once max ||c_i|| is of the order of
+    the rounding error (eq. column_norm_bound_DM); the paper gives no constant.  The
+    reading is umax <= n eps max_j ||a_j|| (the eps n scale of the stopping
+    criterion).  With orthogonal columns the partial norms stay the column norms s_j
+    (every off-diagonal of R is rounding noise), so the first switched step is the
+    first block start with s_j <= n eps max s.  The norms fall by 10^(1/4) per
+    column: the thresholds eps, eps sqrt(n), eps n and 10 eps n then fall at four
+    different columns, so a wrong constant or scale moves the switch."""
+    n, m = 64, 96
+    s = 10.0 ** (-np.arange(n) / 4.0)
+    a, _ = I.orthogonal_columns(m, s, seed=3)
+    res = oracle.qrdm(a, tau=0.15, delta=0.9, kmax=32, stop_rule=oracle.STOP_NONE)
+    thr = n * EPS * s.max()
+    first = next(j for j in range(n) if s[j] <= thr)
+    # eps n puts the switch at column 56, between 10^-13.75 (above) and 10^-14 (below)
+    assert first == 56 and s[55] > 1.2 * thr and s[56] < 0.8 * thr
+    starts = [b.ns for b in res.blocks if b.l > 0]
+    expect = next(ns for ns in starts if s[ns] <= thr)  # the first block start at or below it
+    fb = [b.ns for b in res.blocks if b.fallback]
+    assert fb and fb[0] == expect and all(b.l == 1 for b in res.blocks if b.fallback)
+    assert all(not b.fallback for b in res.blocks if b.ns < expect)
+    # the other scales would have switched elsewhere
+    for alt in (EPS, EPS * np.sqrt(n), 10 * n * EPS):
+        assert next(j for j in range(n) if s[j] <= alt) != first
+    # a mistake in the scale (eps amax instead of n eps amax) is caught
+    bad = oracle.qrdm(a, tau=0.15, delta=0.9, kmax=32, stop_rule=oracle.STOP_NONE, plant=oracle.PLANT_FBSCALE)
+    fbb = [b.ns for b in bad.blocks if b.fallback]
+    assert not fbb or fbb[0] != expect
+
+
+# ----------------------------------- the cosine matrix of Algorithm 1 (closed form)
+def test_cosines_use_the_true_norms_closed_form():
+    """Theta = D^-1 C^T C D^-1 with D the norms of the candidate columns (Section 2;
+    Section 4 forms it from the Gram matrix).  Columns in a plane at angles phi_i
+    have cosines cos(phi_i - phi_j) exactly, whatever their norms.  The partial
+    norms handed to the selection are deliberately not the column norms (they are
+    the downdated estimates in a factorization), so a D taken from them would
+    change Theta; the candidate list order follows them (eq. def_candidate_set)."""
+    rng = np.random.default_rng(7)
+    k = 12
+    phi = rng.uniform(0.0, np.pi, k)
+    norms = np.exp(rng.uniform(-1.0, 1.0, k))
+    a = I.angles_in_plane(40, phi, norms, seed=8)
+    vn1 = norms * rng.uniform(0.6, 1.4, k)  # estimates, not the norms
+    L, th, J = oracle.dm_step(a, vn1, 0, 0.05, 0.9, 16)
+    assert len(L) == k
+    assert np.array_equal(L, np.argsort(-vn1, kind="stable"))
+    want = np.cos(phi[L][:, None] - phi[L][None, :])
+    assert np.max(np.abs(th - want)) <= 1e-13
+    # a D from the estimates is caught
+    _, th_bad, _ = oracle.dm_step(a, vn1, 0, 0.05, 0.9, 16, plant=oracle.PLANT_DNORM)
+    assert np.max(np.abs(th_bad - want)) > 1e-3
+    # the greedy pick of Algorithm 1 on these cosines, by brute force over the list
+    acc = [0]
+    for i in range(1, k):
+        if all(abs(want[i, j]) < 0.9 for j in acc):
+            acc.append(i)
+    assert np.array_equal(J, L[acc])
