@@ -61,6 +61,8 @@ extern "C" {
 #define QRDM_ERR_INTERNAL 4    /* the host loop ran past its bound on the number of steps
                                   (each step takes at least one column; a library fault)    */
 #define QRDM_ERR_WORKSPACE 5   /* ws_bytes < qrdm_workspace_size(m, n, p); nothing written  */
+#define QRDM_ERR_SCRATCH 6     /* qrdm_factor_noalloc: qrdm_workspace_size(m, n, p) exceeds
+                                  QRDM_NOALLOC_WS_MAX; nothing written                      */
 #define QRDM_ERR_HIP 1000      /* QRDM_ERR_HIP + hipError_t of a failed runtime call      */
 
 /* Stopping criterion, Section 3.4, eq. (practical stopping criterion). */
@@ -206,6 +208,27 @@ size_t qrdm_workspace_size(int64_t m, int64_t n, const qrdm_params *p);
 int qrdm_factor_ws(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p, double *tau_house,
                    int32_t *perm, int64_t *rank_dev, qrdm_stats *stats, void *workspace, size_t ws_bytes,
                    void *stream);
+
+/*
+ * For callers that cannot allocate memory (tight serving loops, harnesses that
+ * forbid hipMalloc): qrdm_factor_ws without a workspace argument.  The
+ * workspace is a fixed array in device memory that the library holds on each
+ * device it runs on (QRDM_NOALLOC_WS_MAX bytes plus a 256-byte polling slot,
+ * kept until the process ends); the call itself allocates nothing, neither
+ * device memory nor pinned host memory nor events.
+ *   A, lda, p, tau_house, perm, rank_dev  as in qrdm_factor_ws (p->profile must
+ *              be 0; p->poll_lag is ignored: the host reads the loop state
+ *              after every step, which gives the same factorization to the bit).
+ * Shapes whose qrdm_workspace_size(m, n, p) exceeds QRDM_NOALLOC_WS_MAX are
+ * rejected with QRDM_ERR_SCRATCH before any launch (8192 x 8192 with
+ * k_DM <= 64 fits).  The array keeps the contents of the last call; every call
+ * clears what it needs.  All calls on one device share its array: calls that
+ * overlap on one device (from several host threads or streams) race and give
+ * wrong results; serialize them.  Returns as qrdm_factor_ws.
+ */
+#define QRDM_NOALLOC_WS_MAX ((size_t)96 << 20)
+int qrdm_factor_noalloc(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *p, double *tau_house,
+                        int32_t *perm, int64_t *rank_dev, void *stream);
 
 /*
  * QRP, Algorithm 2 (Section 3.1), blocked like LAPACK xgeqp3: one pivot per

@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(HERE, "libqrdm.so")
 
 STOP_PAPER, STOP_MAXNORM, STOP_NONE = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-ERR_NONFINITE, ERR_NOMEM, ERR_UNSUPPORTED, ERR_INTERNAL, ERR_WORKSPACE, ERR_HIP = 1, 2, 3, 4, 5, 1000
+ERR_NONFINITE, ERR_NOMEM, ERR_UNSUPPORTED, ERR_INTERNAL, ERR_WORKSPACE, ERR_SCRATCH, ERR_HIP = 1, 2, 3, 4, 5, 6, 1000
+NOALLOC_WS_MAX = 96 << 20
 
 
 class Params(ctypes.Structure):
@@ -68,6 +69,7 @@ SIGNATURES = {
     "qrdm_workspace_size": (ctypes.c_size_t, [_i64, _i64, _P(Params)]),
     "qrdm_factor_ws": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _vp, _vp, _vp, _P(Stats), _vp,
                                       ctypes.c_size_t, _vp]),
+    "qrdm_factor_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _vp, _vp, _vp, _vp]),
     "qrp_factor": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp, _P(_i64), _vp]),
     "qrp_factor_ex": (ctypes.c_int, [_vp, _i64, _i64, _i64, _P(Params), _i32, _vp, _vp, _P(_i64), _P(Stats), _vp]),
     "qrdm_colnorms": (ctypes.c_int, [_vp, _i64, _i64, _i64, _vp, _vp]),

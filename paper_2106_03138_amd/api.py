@@ -130,6 +130,25 @@ def qrdm_factor_ws(A, workspace, rank_out, tau: float = 0.15, delta: float = 0.9
     return Factorization(tau_house[: min(m, n)], perm[:n], -1, sd, [])
 
 
+def qrdm_factor_noalloc(A, rank_out, tau: float = 0.15, delta: float = 0.9, kmax: int = 64,
+                        stop_rule: int = _lib.STOP_PAPER, precision: int = _lib.PREC_FP64, eps1_scale: float = 0.0,
+                        stream=None, tau_house=None, perm=None, certified: bool = False) -> Factorization:
+    """QRDM of A in place in the library's fixed device scratch (no allocation by
+    the library; tau_house and perm must be passed in to keep the call free of
+    allocations here too).  The rank goes to rank_out (an int64 device tensor
+    with one element) in stream order; the returned Factorization's rank is -1."""
+    torch = _torch()
+    m, n, lda = _check_matrix(A)
+    p = _params(tau, delta, kmax, stop_rule, precision, 0, eps1_scale, False, certified)
+    tau_house, perm = _outputs(A, m, n, tau_house, perm)
+    rank_out = _out_vector(rank_out, "rank_out", torch.int64, 1, A)
+    code = _lib.load().qrdm_factor_noalloc(
+        ctypes.c_void_p(A.data_ptr()), m, n, lda, ctypes.byref(p), ctypes.c_void_p(tau_house.data_ptr()),
+        ctypes.c_void_p(perm.data_ptr()), ctypes.c_void_p(rank_out.data_ptr()), _stream_ptr(stream))
+    _lib.check("qrdm_factor_noalloc", code)
+    return Factorization(tau_house[: min(m, n)], perm[:n], -1, {}, [])
+
+
 def qrdm_factor(A, tau: float = 0.15, delta: float = 0.9, kmax: int = 64, stop_rule: int = _lib.STOP_PAPER,
                 precision: int = _lib.PREC_FP64, poll_lag: int = 4, eps1_scale: float = 0.0,
                 log: bool = False, profile: bool = False, stream=None, tau_house=None,

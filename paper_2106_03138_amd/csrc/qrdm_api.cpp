@@ -55,6 +55,10 @@ static_assert(offsetof(Snapshot, jmax) == offsetof(QrdmCtl, jmax) &&
 struct PollCtx {
     int device = -1;
     int ring = 0;
+    // copy mode (qrdm_factor_noalloc, which may not allocate pinned memory or
+    // events): ring = 1, dev_snap is a slot in device memory and the host reads
+    // it with a copy after synchronizing the stream, so the poll lag is 0
+    bool copy = false;
     Snapshot *host_snap = nullptr;
     uint64_t *dev_snap = nullptr;
     std::vector<hipEvent_t> events;
@@ -225,6 +229,27 @@ namespace {
         if (_e != hipSuccess) return hip_err(_e);   \
     } while (0)
 
+// Marks snapshot `slot` as launched (an event after the launch that writes it).
+int poll_mark(PollCtx &pc, int64_t slot, hipStream_t s) {
+    if (pc.copy) return 0;
+    HIP_TRY(hipEventRecord(pc.events[slot % pc.ring], s));
+    return 0;
+}
+
+// Waits for snapshot `slot` and returns it.  src: the device words the slot's
+// snapshot is read from in copy mode (the ring slot, or the control block
+// itself when the kernels write no snapshot).
+int poll_read(PollCtx &pc, int64_t slot, const void *src, hipStream_t s, Snapshot *out) {
+    if (pc.copy) {
+        HIP_TRY(hipMemcpyAsync(out, src, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return 0;
+    }
+    HIP_TRY(hipEventSynchronize(pc.events[slot % pc.ring]));
+    *out = pc.host_snap[slot % pc.ring];
+    return 0;
+}
+
 // Caller holds g_ws_mu.
 int ensure_workspace(size_t bytes) {
     int dev = 0;
@@ -320,11 +345,13 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
             QrdmArgs al = a;
             al.snap = pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block kernel
             HIP_TRY(launch_qp3_block(al, bf, nb, tb, wb, grid, (int)iter, s, ev));
-            HIP_TRY(hipEventRecord(pc.events[iter % ring], s));
+            int rc = poll_mark(pc, iter, s);
+            if (rc) return rc;
             if (iter >= lag) {
                 const int64_t k = iter - lag;
-                HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
-                const Snapshot sn = pc.host_snap[k % ring];
+                Snapshot sn;
+                rc = poll_read(pc, k, pc.dev_snap + (k % ring) * QRDM_SNAP_WORDS, s, &sn);
+                if (rc) return rc;
                 if (sn.ns > ns_known) ns_known = sn.ns;
                 if (sn.done) {
                     *last = sn;
@@ -342,13 +369,15 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
         const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
         HIP_TRY(launch_qp3_step(a, bf, nb, tb, wb, s));
         if ((iter + 1) % kStride != 0) continue;
-        Snapshot *hs = pc.host_snap + (nsnap % ring);
-        HIP_TRY(hipMemcpyAsync(hs, a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipEventRecord(pc.events[nsnap % ring], s));
+        if (!pc.copy)
+            HIP_TRY(hipMemcpyAsync(pc.host_snap + (nsnap % ring), a.ctl, sizeof(Snapshot), hipMemcpyDeviceToHost, s));
+        int rc = poll_mark(pc, nsnap, s);
+        if (rc) return rc;
         if (nsnap >= lag) {
             const int64_t k = nsnap - lag;
-            HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
-            const Snapshot sn = pc.host_snap[k % ring];
+            Snapshot sn;
+            rc = poll_read(pc, k, a.ctl, s, &sn);
+            if (rc) return rc;
             if (sn.ns > ns_known) ns_known = sn.ns;
             if (sn.done) {
                 *last = sn;
@@ -424,7 +453,7 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
     const Layout &L = env.L;
     PollCtx &pc = *env.pc;
     hipStream_t s = env.s;
-    const int lag = env.log ? 0 : p.poll_lag;
+    const int lag = (env.log || env.pc->copy) ? 0 : p.poll_lag;
     QrdmArgs a;
     a.A = A;
     a.m = m;
@@ -503,11 +532,15 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
             HIP_TRY(launch_downdate(al, wb, s));
         }
         if (ev) HIP_TRY(hipEventRecord(ev[7], s));
-        HIP_TRY(hipEventRecord(pc.events[iter % ring], s));
+        {
+            int rc = poll_mark(pc, iter, s);
+            if (rc) return rc;
+        }
         if (iter >= lag) {
             const int64_t k = iter - lag;
-            HIP_TRY(hipEventSynchronize(pc.events[k % ring]));
-            const Snapshot sn = pc.host_snap[k % ring];
+            Snapshot sn;
+            int rc = poll_read(pc, k, pc.dev_snap + (k % ring) * QRDM_SNAP_WORDS, s, &sn);
+            if (rc) return rc;
             if (sn.ns > ns_known) ns_known = sn.ns;
             // a step that took a block (not the one that ended the loop or passed it
             // to the column-pivoting kernels)
@@ -591,6 +624,42 @@ int check_outputs(int64_t m, int64_t n, const double *tau_house, const int32_t *
 
 }  // namespace
 
+// ------------------------------------------------------------ no-allocation entry point
+// qrdm_factor_noalloc runs in this fixed device array instead of an allocated
+// workspace: a 256-byte snapshot slot, then the workspace of one call (the
+// layout of make_layout, at most QRDM_NOALLOC_WS_MAX bytes).  Each device that
+// runs the library holds its own copy until the process ends.  The array's
+// name stands for a host-side shadow in host code: only the device address
+// from hipGetSymbolAddress (taken once per device, kept in g_scratch_addr) is
+// passed to kernels and copies.
+#define QRDM_SCRATCH_SNAP_BYTES 256
+static __device__ __align__(256) unsigned char scratch[QRDM_SCRATCH_SNAP_BYTES + QRDM_NOALLOC_WS_MAX];
+
+namespace {
+
+const int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_addr[kScratchDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first call
+// on that device).
+int scratch_base(char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return QRDM_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return QRDM_ERR_HIP + (int)hipErrorInvalidSymbol;
+        g_scratch_addr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 void qrdm_default_params(qrdm_params *p) {
@@ -614,6 +683,9 @@ const char *qrdm_strerror(int code) {
     if (code == QRDM_ERR_UNSUPPORTED) return "size not supported by the kernels";
     if (code == QRDM_ERR_INTERNAL) return "internal error: the host loop exceeded its bound on the steps";
     if (code == QRDM_ERR_WORKSPACE) return "workspace smaller than qrdm_workspace_size";
+    if (code == QRDM_ERR_SCRATCH)
+        return "qrdm_workspace_size of this shape exceeds the fixed scratch of qrdm_factor_noalloc "
+               "(QRDM_NOALLOC_WS_MAX)";
     if (code >= QRDM_ERR_HIP) return hipGetErrorString((hipError_t)(code - QRDM_ERR_HIP));
     return "unknown error";
 }
@@ -763,6 +835,43 @@ int qrdm_factor_ws(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_para
         stats_fill(cf, stats);
     }
     return 0;
+}
+
+int qrdm_factor_noalloc(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params *pin, double *tau_house,
+                        int32_t *perm, int64_t *rank_dev, void *stream) {
+    qrdm_params p;
+    if (pin) p = *pin; else qrdm_default_params(&p);
+    int rc = check_common(A, m, n, lda, &p);
+    if (rc) return rc;
+    rc = check_outputs(m, n, tau_house, perm);
+    if (rc) return rc;
+    if (!rank_dev) return -8;
+    if (p.profile) return -5;  // timing events are for qrdm_factor_ex
+    if (n > 32768 || m > 65536) return QRDM_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (std::min(m, n) == 0) return trivial(perm, n, rank_dev, s);
+    CallEnv env;
+    env.L = make_layout(m, n, p.kmax);
+    if (env.L.total > QRDM_NOALLOC_WS_MAX) return QRDM_ERR_SCRATCH;
+    char *base = nullptr;
+    rc = scratch_base(&base);
+    if (rc) return rc;
+    PollCtx pc;  // copy mode: nothing of it is allocated
+    pc.copy = true;
+    pc.ring = 1;
+    pc.dev_snap = (uint64_t *)base;
+    env.ws = base + QRDM_SCRATCH_SNAP_BYTES;
+    env.pc = &pc;
+    env.s = s;
+    env.log = nullptr;
+    env.log_cap = 0;
+    env.nlog = nullptr;
+    env.rank_dev = rank_dev;
+    ProfRun prof;
+    Snapshot fin;
+    rc = qrdm_run(A, m, n, lda, p, tau_house, perm, env, prof, &fin);
+    if (rc) return rc;
+    return snapshot_code(fin);
 }
 
 int qrdm_factor(double *A, int64_t m, int64_t n, int64_t lda, double tau, double delta, int32_t kmax,

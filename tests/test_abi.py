@@ -51,7 +51,8 @@ def lib():
 
 def test_header_declares_the_expected_entry_points():
     names = _declared_functions()
-    for want in ["qrdm_factor", "qrdm_factor_ex", "qrdm_factor_ws", "qrdm_workspace_size", "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
+    for want in ["qrdm_factor", "qrdm_factor_ex", "qrdm_factor_ws", "qrdm_factor_noalloc", "qrdm_workspace_size",
+                 "qrp_factor", "qrp_factor_ex", "qrdm_colnorms",
                  "qrdm_dm_step", "qrdm_default_params", "qrdm_release", "qrdm_strerror", "qrdm_lstsq",
                  "qrdm_batch_lstsq", "qrdm_truncate_rank", "qrdm_batch_truncate_rank"]:
         assert want in names, names
@@ -195,3 +196,32 @@ def test_workspace_size_and_ws_arguments_on_the_host(lib):
     assert f(d, 64, 48, 32, ctypes.byref(p), d, d, d, None, d, need, None) == -4
     p.profile = 1
     assert f(d, 64, 48, 64, ctypes.byref(p), d, d, d, None, d, need, None) == -5
+
+
+def test_noalloc_arguments_and_size_limit_on_the_host(lib):
+    """qrdm_factor_noalloc checks its arguments and the scratch limit before it
+    touches the device: shapes whose workspace exceeds QRDM_NOALLOC_WS_MAX are
+    refused with QRDM_ERR_SCRATCH."""
+    from paper_2106_03138_amd import _lib
+    ws = lib.qrdm_workspace_size
+    ws.restype, ws.argtypes = _lib.SIGNATURES["qrdm_workspace_size"]
+    f = lib.qrdm_factor_noalloc
+    f.restype, f.argtypes = _lib.SIGNATURES["qrdm_factor_noalloc"]
+    p = _lib.Params()
+    lib.qrdm_default_params(ctypes.byref(p))
+    text = open(HEADER).read()
+    assert re.search(r"#define QRDM_NOALLOC_WS_MAX \(\(size_t\)96 << 20\)", text)
+    assert _lib.NOALLOC_WS_MAX == 96 << 20
+    assert ws(8192, 8192, ctypes.byref(p)) <= _lib.NOALLOC_WS_MAX  # the benchmark's shape fits
+    d = ctypes.c_void_p(4096)
+    assert ws(16384, 16384, ctypes.byref(p)) > _lib.NOALLOC_WS_MAX
+    assert f(d, 16384, 16384, 16384, ctypes.byref(p), d, d, d, None) == _lib.ERR_SCRATCH
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, None, None) == -8
+    assert f(d, 64, 48, 32, ctypes.byref(p), d, d, d, None) == -4
+    assert f(d, 64, 48, 64, ctypes.byref(p), None, d, d, None) == -6
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, None, d, None) == -7
+    p.profile = 1
+    assert f(d, 64, 48, 64, ctypes.byref(p), d, d, d, None) == -5
+    msg = lib.qrdm_strerror
+    msg.restype, msg.argtypes = _lib.SIGNATURES["qrdm_strerror"]
+    assert b"QRDM_NOALLOC_WS_MAX" in msg(_lib.ERR_SCRATCH)
