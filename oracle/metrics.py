@@ -132,6 +132,15 @@ def r11_ratios(r: np.ndarray, sigma: np.ndarray, nr: int) -> np.ndarray:
     return s11 / sigma[:nr]
 
 
+def sigma_min_r11(r: np.ndarray, k: int) -> float:
+    """sigma_min(R11), R11 = the leading k x k upper triangle of r (LAPACK dgesdd,
+    values only)."""
+    if k <= 0:
+        return 0.0
+    from scipy.linalg import svdvals
+    return float(svdvals(np.triu(r[:k, :k]), check_finite=False)[-1])
+
+
 def flops(m: int, n: int, r: int) -> float:
     """Algorithmic flop count of r Householder steps: sum_{s<r} 4 (m-s)(n-s)."""
     s = np.arange(r, dtype=np.float64)

@@ -98,6 +98,44 @@ def paper_rule_rank(qr: np.ndarray, a_colnorm_max: float, starts) -> tuple[int, 
     return min(m, n), margin
 
 
+def stop_band(qr: np.ndarray, amax: float, eps1: float, nu: float, upto: int, maxnorm: bool = False,
+              rtol: float = RTOL, nref: int | None = None) -> tuple[int, int | None]:
+    """Where the practical stopping criterion (Section 4) first holds on a
+    factorization's exact partial norms, with the rounding noise of two correct
+    implementations taken into account.
+
+    For every column j < upto (the rows of R above `upto` must be final), lhs_j =
+    sqrt(n - j) * max_{q >= j} ||R[j:, q]|| (MAXNORM: without sqrt(n - j)) against
+    rhs = eps1 * amax; slack_j = sqrt(n - j) * nu + rtol * lhs_j (MAXNORM: nu +
+    rtol * lhs_j).  Returns (lo, hi): lo = the first j with lhs_j <= rhs + slack_j
+    (the test may hold there on another implementation's data), hi = the first j
+    with lhs_j < rhs - slack_j (it surely holds), None when no j < upto is that
+    clear.  lo = upto when the test cannot hold before upto.
+    nref: the number of reflectors of a factorization that stopped early (its
+    columns >= nref hold the trailing block in all rows >= nref); None = full."""
+    m, n = qr.shape
+    upto = min(upto, min(m, n))
+    if upto <= 0:
+        return upto, None
+    if nref is None:
+        c2 = suffix_norms2(qr)
+    else:
+        r = np.array(qr, copy=True)
+        for j in range(min(nref, n)):
+            r[j + 1:, j] = 0.0
+        c2 = np.cumsum((r ** 2)[::-1, :], axis=0)[::-1, :]
+    # row j of the suffix norms is zero left of column j (R is upper triangular)
+    u = np.sqrt(np.maximum(c2[:upto].max(axis=1), 0.0))
+    f = np.ones(upto) if maxnorm else np.sqrt(n - np.arange(upto, dtype=np.float64))
+    lhs = f * u
+    sl = f * nu + rtol * lhs
+    rhs = eps1 * amax
+    may, sure = lhs <= rhs + sl, lhs < rhs - sl
+    lo = int(np.argmax(may)) if may.any() else upto
+    hi = int(np.argmax(sure)) if sure.any() else None
+    return lo, hi
+
+
 def check_dm_replay(qr: np.ndarray, blocks, tau: float, delta: float, kmax: int, amax: float,
                     nu: float = 0.0, rtol: float = RTOL, ctol: float = CTOL) -> dict:
     """Algorithm 1 and the check step of Algorithm 4 replayed at every logged block

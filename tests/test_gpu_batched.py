@@ -69,7 +69,7 @@ def _check_all(mats, b, tau, delta, kmax, stop_rule, per=None):
             continue
         try:
             compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [], check_blocks=False,
-                    full=(stop_rule == oracle.STOP_NONE))
+                    full=(stop_rule == oracle.STOP_NONE), stop_rule=stop_rule, kmax=k)
         except AssertionError as e:
             raise AssertionError(f"matrix {i} shape {a.shape} (tau {t}, delta {d}, kmax {k}, stop {stop_rule}): "
                                  f"rank {rank[i]} vs oracle {ref.rank}; {e}") from e
@@ -171,7 +171,7 @@ def test_batched_nonfinite_and_empty():
         assert np.array_equal(np.isnan(before[s0:s1]), np.isnan(after[s0:s1]))
         assert np.array_equal(np.nan_to_num(before[s0:s1]), np.nan_to_num(after[s0:s1]))
     ref = oracle.qrdm(good)
-    compare(good, ref, b.matrix(0), b.tau_house(0), b.permutation(0), int(rk[0]), [], check_blocks=False)
+    compare(good, ref, b.matrix(0), b.tau_house(0), b.permutation(0), int(rk[0]), [], check_blocks=False, kmax=64)
 
 
 def test_batched_full_size_sampled():
@@ -191,7 +191,7 @@ def test_batched_full_size_sampled():
     for i in rng.choice(len(mats), 10, replace=False):
         ref = oracle.qrdm(mats[i])
         compare(mats[i], ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [],
-                check_blocks=False)
+                check_blocks=False, kmax=64)
     # backward error on a wider sample
     for i in rng.choice(len(mats), 40, replace=False):
         m, n = shapes[i][:2]

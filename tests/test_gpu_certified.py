@@ -36,7 +36,8 @@ def test_block_records_match_oracle(name, certified):
     ref = oracle.qrdm(a, certified=certified, **kw)
     A = Q.device_matrix(a)
     out = Q.qrdm_factor(A, certified=certified, log=True, poll_lag=0, **kw)
-    compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.blocks)
+    compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.blocks,
+            kmax=kw.get("kmax", 64))
     k = ref.first_low_margin_block(ETA)
     real = [b for b in ref.blocks if b.l > 0]
     tau = kw.get("tau", 0.15)

@@ -39,7 +39,7 @@ def test_small_grid_matches_oracle():
             for i, a in enumerate(mats):
                 ref = oracle.qrdm(a, tau=t, delta=d, stop_rule=oracle.STOP_NONE)
                 compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rk[i]), [],
-                        check_blocks=False, full=True)
+                        check_blocks=False, full=True, stop_rule=oracle.STOP_NONE, kmax=64)
                 got.append(G.min_ratio(np.diag(b.matrix(i)), sigmas[i], a.shape[1]))
             assert ratio[jt, idl] == min(got), (t, d)
             plan.close()
@@ -53,4 +53,4 @@ def test_tau_zero_single_matches_oracle():
         A = Q.device_matrix(a)
         out = Q.qrdm_factor(A, tau=0.0, delta=d, stop_rule=oracle.STOP_NONE, log=True, poll_lag=0)
         compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank,
-                out.blocks, full=True)
+                out.blocks, full=True, stop_rule=oracle.STOP_NONE, kmax=64)

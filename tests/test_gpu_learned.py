@@ -168,7 +168,8 @@ def test_predicted_parameters_match_oracle_factorization():
         if min(a.shape) == 0 or not np.any(a):
             continue
         ref = oracle.qrdm(a, tau=float(rec["tau"][i]), delta=float(rec["delta"][i]), kmax=int(rec["kmax"][i]))
-        compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [], check_blocks=False)
+        compare(a, ref, b.matrix(i), b.tau_house(i), b.permutation(i), int(rank[i]), [], check_blocks=False,
+                kmax=int(rec["kmax"][i]))
 
 
 def test_training_steps_follow_the_oracle():

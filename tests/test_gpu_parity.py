@@ -66,7 +66,7 @@ def test_rank64_256(seed, rule):
     a = I.small_rank64(seed)
     ref = oracle.qrdm(a, tau=0.9, delta=0.9, kmax=32, stop_rule=rule)
     qr, tau, perm, rank, out = _run_gpu(a, tau=0.9, delta=0.9, kmax=32, stop_rule=rule)
-    _compare(a, ref, qr, tau, perm, rank, out.blocks, full=(rule == oracle.STOP_NONE))
+    _compare(a, ref, qr, tau, perm, rank, out.blocks, full=(rule == oracle.STOP_NONE), stop_rule=rule, kmax=32)
     if rule == oracle.STOP_MAXNORM:
         assert rank == 64
 

@@ -9,7 +9,7 @@ import oracle
 from oracle import learned as Lr
 from oracle import truncate as Tr
 from paper_2106_03138_amd import inputs as I
-from parity import compare
+from parity import EPS, compare
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,8 @@ def test_eps_sqrt_n_stop_matches_oracle(kind):
     ref = oracle.qrdm(a, eps1_scale=np.sqrt(n))
     A = Q.device_matrix(a)
     out = Q.qrdm_factor(A, eps1_scale=float(np.sqrt(n)), log=True)
-    compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.blocks)
+    compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.blocks,
+            eps1=float(np.sqrt(n)) * EPS, kmax=64)
 
 
 @pytest.mark.parametrize("rule", [oracle.STOP_PAPER, oracle.STOP_MAXNORM])
@@ -46,7 +47,7 @@ def test_qrp_with_the_qrdm_stopping_criterion(rule):
         A = Q.device_matrix(a)
         out = Q.qrp_factor(A, stop_rule=rule)
         compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, [],
-                check_blocks=False)
+                check_blocks=False, stop_rule=rule, kmax=1)
 
 
 def test_truncation_recovers_the_numerical_rank_single():

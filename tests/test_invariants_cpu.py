@@ -151,3 +151,75 @@ def test_replay_catches_planted_mistakes(plant, name, msg):
     with pytest.raises(AssertionError, match=msg):
         V.check_blocks(res.qr, _log(res), kw["tau"], kw["delta"], a.shape[1], tail_single=False)
         _replay(a, res, kw)
+
+
+# ------------------------------------------------ the rank's noise band, sigma_min(R11)
+def _band(res, a, n, rule=oracle.STOP_PAPER, eps1=None, nref=None, upto=None):
+    amax = np.linalg.norm(a, axis=0).max()
+    nu = 4 * V.EPS * np.linalg.norm(a)
+    e1 = n * V.EPS if eps1 is None else eps1
+    p = min(a.shape)
+    return V.stop_band(res.qr, amax, e1, nu, p if upto is None else upto, maxnorm=(rule == oracle.STOP_MAXNORM),
+                       nref=nref)
+
+
+def test_stop_band_holds_the_rank_of_the_oracle_and_of_a_perturbed_run(geo):
+    """The oracle's rank lies in its own band, and so does the rank of a second
+    run on A perturbed at the rounding level (a stand-in for another correct
+    implementation); the band is a few columns wide on a geometric spectrum."""
+    a, res = geo
+    n = a.shape[1]
+    lo, hi = _band(res, a, n)
+    assert hi is not None and lo <= res.rank <= hi
+    assert hi - lo <= 60
+    pert = a * (1 + 2 * V.EPS * np.random.default_rng(7).standard_normal(a.shape))
+    r2 = oracle.qrdm(pert, tau=0.15, delta=0.9, kmax=32, stop_rule=oracle.STOP_NONE)
+    assert lo <= r2.rank <= hi, (lo, hi, r2.rank)
+
+
+def test_stop_band_rejects_a_rank_from_the_wrong_rule(geo):
+    """Planted mistake: the rank of the eps sqrt(n) variant (a rule the paper
+    calls less accurate) falls outside the band of eps n."""
+    a, res = geo
+    n = a.shape[1]
+    lo, hi = _band(res, a, n)
+    wrong = oracle.qrdm(a, tau=0.15, delta=0.9, kmax=32, stop_rule=oracle.STOP_NONE, eps1_scale=np.sqrt(n))
+    assert not (lo <= wrong.rank <= hi), (lo, hi, wrong.rank)
+
+
+def test_stop_band_of_stopped_runs():
+    """A run that stopped early keeps the trailing block in its columns >= rank:
+    the band reads it (nref).  On the gapped 256^2 spectrum (sigma 1e-3 -> 1e-15
+    at n_r = 64) the MAXNORM rule's band is the single column 64; the PAPER rule
+    compares sqrt(n - j) max ||c|| with eps n max ||a_j||, and past the gap both
+    sides are at the noise level, so its band starts after n_r (the rule never
+    fires before the numerical rank) and has no clear end before the stop."""
+    a = I.small_rank64(1)
+    n = a.shape[1]
+    res = oracle.qrdm(a, tau=0.9, delta=0.9, kmax=32, stop_rule=oracle.STOP_MAXNORM)
+    lo, hi = _band(res, a, n, rule=oracle.STOP_MAXNORM, nref=res.rank, upto=res.rank + 1)
+    assert res.rank == 64 and lo == 64 and hi == 64, (lo, hi, res.rank)
+    res = oracle.qrdm(a, tau=0.9, delta=0.9, kmax=32, stop_rule=oracle.STOP_PAPER)
+    lo, hi = _band(res, a, n, nref=res.rank, upto=res.rank + 1)
+    assert 64 < lo <= res.rank and hi is None, (lo, hi, res.rank)
+    # without nref the untriangularised block would be cut by triu: a smaller
+    # partial norm, and a band that starts earlier than the true one
+    res = oracle.qrdm(a, tau=0.9, delta=0.9, kmax=32, stop_rule=oracle.STOP_PAPER)
+    lo_bad, _ = _band(res, a, n, upto=res.rank + 1)
+    lo_ok, _ = _band(res, a, n, nref=res.rank, upto=res.rank + 1)
+    assert lo_bad <= lo_ok
+
+
+def test_sigma_min_r11_closed_forms():
+    """sigma_min of the leading block: a diagonal R (orthogonal columns, so the
+    singular values are the |r_ii|), and 1/||R11^{-1}||_2 by explicit inversion."""
+    r = np.zeros((9, 7))
+    d = np.array([5.0, -3.0, 2.0, 0.5, -0.25, 4.0, 1.0])
+    r[np.arange(7), np.arange(7)] = d
+    r[5:, 0] = 1.0  # reflector storage below the diagonal is ignored
+    assert M.sigma_min_r11(r, 5) == pytest.approx(0.25, rel=1e-15)
+    rng = np.random.default_rng(3)
+    t = np.triu(rng.standard_normal((40, 40))) + 5 * np.eye(40)
+    inv = np.linalg.inv(t[:30, :30])
+    assert M.sigma_min_r11(t, 30) == pytest.approx(1.0 / np.linalg.norm(inv, 2), rel=1e-12)
+    assert M.sigma_min_r11(t, 0) == 0.0
