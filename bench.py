@@ -265,6 +265,116 @@ def learned_leg(args, torch, Q, b, pristine, shapes, default_ms):
             "timing": "wall clock around features + MLP + factorization + check + fallback (eager)"}
 
 
+def _qt_sampled_residual(a, qr, tau, perm, nref, cols):
+    """Estimate of ||A P - Q R||_F / ||A||_F from the columns `cols` of A P
+    (LAPACK dormqr applies Q^T; host numpy/scipy, not the oracle)."""
+    from scipy.linalg import lapack
+    y = np.asfortranarray(a[:, perm[cols]])
+    if nref > 0:
+        y, _, info = lapack.dormqr("L", "T", np.asfortranarray(qr[:, :nref]), np.ascontiguousarray(tau[:nref]), y,
+                                   max(1, 64 * y.shape[1]))
+        assert info == 0
+    r = np.array(qr[:, cols], copy=True)
+    for c, j in enumerate(cols):
+        if j < nref:
+            r[j + 1:, c] = 0.0
+    return float(np.sqrt(a.shape[1] / len(cols) * np.sum((y - r) ** 2)) / np.linalg.norm(a))
+
+
+def _quality(a, qr, tau, perm, rank, sigma, full, eps_w=np.finfo(np.float64).eps):
+    """Rank against n_r = #{sigma_i > eps_w n sigma_1} (eps_w = 2^-52, or 2^-23 for
+    mixed precision, whose trailing data carry FP32 rounding), min/max d_i / sigma_i
+    over the first n_r (d_i = i-th largest |r_ii|, Section 5), sampled backward error."""
+    m, n = a.shape
+    nref = min(m, n) if full else rank
+    cols = np.random.default_rng(1).choice(n, min(n, 64), replace=False)
+    q = {"rank": int(rank), "residual": float(f"{_qt_sampled_residual(a, qr, tau, perm, nref, cols):.3e}")}
+    if sigma is not None:
+        sg = np.sort(sigma)[::-1]
+        nr = int(np.sum(sg > eps_w * n * sg[0]))
+        d = np.sort(np.abs(np.diag(qr)[:nr]))[::-1] / sg[:nr]
+        q.update({"n_r": nr, "d_over_sigma": [round(float(d.min()), 4), round(float(d.max()), 4)]})
+    return q
+
+
+def configs_leg(args, torch, Q):
+    """The workloads of every configuration besides the headline: one timed line
+    each (median of `reps` runs, the input restored from a device copy inside each
+    run, wall clock around a synchronized call), with the quality at the stated
+    rule.  Per matrix: QRDM with the paper's stopping rule (its rank is the
+    numerical rank the method reports), QRDM and GPU QRP at equal work (stop
+    off), and QRDM with the stop against full QRP (the comparison of the paper's
+    Fig. 7).  The 8192^2 spectra also run in mixed precision, with the gap of its
+    R diagonal to the FP64 run's."""
+    from paper_2106_03138_amd import inputs as I
+    out = []
+
+    def timed(A, a0, fn, reps):
+        ts = []
+        res = None
+        for _ in range(reps + 1):
+            A.copy_(a0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn(A)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        return float(np.median(ts[1:])), res
+
+    def one(name, a0, sigma, qp, reps, mixed):
+        m, n = a0.shape
+        A = torch.empty_like(a0.t().contiguous()).t()
+        th = torch.empty(min(m, n), dtype=torch.float64, device="cuda")
+        pm = torch.empty(n, dtype=torch.int32, device="cuda")
+        host = np.asfortranarray(a0.t().contiguous().cpu().numpy().T)
+        row = {"config": name, "m": m, "n": n, "tau": qp[0], "delta": qp[1], "k_DM": qp[2]}
+        kw = dict(tau=qp[0], delta=qp[1], kmax=qp[2], tau_house=th, perm=pm)
+        for label, stop, prec in [("qrdm_stop", Q.STOP_PAPER, Q.PREC_FP64), ("qrdm_full", Q.STOP_NONE, Q.PREC_FP64)] + \
+                ([("qrdm_full_mixed", Q.STOP_NONE, Q.PREC_MIXED), ("qrdm_stop_mixed", Q.STOP_PAPER, Q.PREC_MIXED)]
+                 if mixed else []):
+            ms, o = timed(A, a0, lambda X: Q.qrdm_factor(X, stop_rule=stop, precision=prec, **kw), reps)
+            full = stop == Q.STOP_NONE
+            r = o.rank
+            F = flops_full(m, n) if full else flops_cols(m, n, r)
+            qr = Q.host_matrix(A)
+            e = {"ms": round(ms, 3), "tflops": round(F / (ms * 1e-3) / 1e12, 3)}
+            e.update(_quality(host, qr, th.cpu().numpy(), pm.cpu().numpy(), r, sigma, full,
+                              2.0 ** -23 if prec == Q.PREC_MIXED else np.finfo(np.float64).eps))
+            if label == "qrdm_full":
+                d64 = np.sort(np.abs(np.diag(qr)))[::-1]
+            if label == "qrdm_full_mixed":
+                dmx = np.sort(np.abs(np.diag(qr)))[::-1]
+                e["max_diag_gap_to_fp64_over_norm"] = float(f"{np.max(np.abs(dmx - d64)) / abs(d64[0]):.3e}")
+            row[label] = e
+        for label, stop in [("qrp_full", Q.STOP_NONE), ("qrp_stop", Q.STOP_PAPER)]:
+            ms, o = timed(A, a0, lambda X: Q.qrp_factor(X, stop_rule=stop, tau_house=th, perm=pm), max(1, reps // 3))
+            row[label] = {"ms": round(ms, 3), "rank": int(o.rank)}
+        row["speedup_equal_work"] = round(row["qrp_full"]["ms"] / row["qrdm_full"]["ms"], 3)
+        row["speedup_fig7"] = round(row["qrp_full"]["ms"] / row["qrdm_stop"]["ms"], 3)
+        row["speedup_both_stopped"] = round(row["qrp_stop"]["ms"] / row["qrdm_stop"]["ms"], 3)
+        print(f"[bench configs] {name}: qrdm full {row['qrdm_full']['ms']} ms, qrp full {row['qrp_full']['ms']} ms",
+              file=sys.stderr, flush=True)
+        out.append(row)
+        del A
+
+    a0 = torch.from_numpy(np.ascontiguousarray(I.small_rank64(0).T)).cuda().t()
+    one("256x256 rank 64 (sigma 1 -> 1e-3, then 1e-15)", a0, I.geometric_rank(256, 64, 1.0, 1e-3, 1e-15),
+        (0.9, 0.9, 32), 10, False)
+    for spec, label in [("half_rank", "4096x4096 numerical rank 2048 (sigma 1 -> 1e-8, then 1e-16 noise)"),
+                        ("kahan", "Kahan 4096 (theta = 1.2)")]:
+        a0 = I.device_matrix(4096, spec, args.seed, torch)
+        one(label, a0, I.device_spectrum(4096, spec, args.seed) if spec != "kahan" else None,
+            (args.tau, args.delta, args.kmax), 3, False)
+        del a0
+    for spec in ["geometric", "stairs", "gaussian"]:
+        a0 = I.device_matrix(8192, spec, args.seed, torch)
+        one(f"8192x8192 {spec}", a0, I.device_spectrum(8192, spec) if spec != "gaussian" else None,
+            (args.tau, args.delta, args.kmax), 3, True)
+        del a0
+    torch.cuda.empty_cache()
+    return out
+
+
 def autotune_load():
     from paper_2106_03138_amd import autotune
     return autotune.load()
@@ -292,6 +402,8 @@ def main():
     ap.add_argument("--input-cache", default="",
                     help=".npy file holding the input: loaded if present, else written after generation")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--configs", type=int, default=1,
+                    help="1 = also time the other configurations (256^2, 4096^2, the 8192^2 spectra, mixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
@@ -384,6 +496,9 @@ def main():
                          f"({cf / 1e9:.1f} GFLOP in {ct:.1f} s)"}
 
     batched = batched_leg(args, torch, Q) if args.batched_count > 0 else None
+    del A
+    torch.cuda.empty_cache()
+    per_config = configs_leg(args, torch, Q) if args.configs else None
 
     line = {
         "metric": "QRDM TFLOP/s vs GPU QRP at 8192^2 (full factorization, FP64), at stated RR quality",
@@ -406,6 +521,7 @@ def main():
         "cpu_baseline": cpu,
         "qrp": qrp,
         "batched": batched,
+        "per_config": per_config,
     }
     print(json.dumps(line), flush=True)
 

@@ -245,20 +245,36 @@ def lstsq_factors(m: int, n: int, r: int, seed):
     return np.asfortranarray(qr), tau, perm
 
 
+def device_spectrum(n: int, spectrum: str, seed: int = 0) -> np.ndarray:
+    """Singular values (in U diag(s) V^T order) of the device workloads with a
+    prescribed spectrum: geometric 1 -> 1e-16; stairs, steps of 512 dropping 10x;
+    half_rank, geometric 1 -> 1e-8 over n/2 then 1e-16 |g_i| (the noise drawn
+    from its own stream, seed + 7919, as half_rank_noise)."""
+    if spectrum == "geometric":
+        return np.geomspace(1.0, 1e-16, n)
+    if spectrum == "stairs":
+        return 10.0 ** (-np.floor(np.arange(n) / 512))
+    if spectrum == "half_rank":
+        r = n // 2
+        s = np.empty(n)
+        s[:r] = np.geomspace(1.0, 1e-8, r)
+        s[r:] = 1e-16 * np.abs(np.random.default_rng(seed + 7919).standard_normal(n - r))
+        return s
+    raise ValueError(spectrum)
+
+
 def device_matrix(n: int, spectrum: str, seed: int, torch):
     """Seeded synthetic n x n matrix on the GPU (column-major float64), the benchmark workload.
-    geometric: sigma 1 -> 1e-16; stairs: steps of 512 dropping 10x; gaussian: N(0,1).
+    geometric: sigma 1 -> 1e-16; stairs: steps of 512 dropping 10x; half_rank: sigma
+    1 -> 1e-8 over n/2, then noise; gaussian: N(0,1); kahan: K_n(1.2).
     U, V are Haar: QR of seeded host Gaussians (signs fixed), formed on the GPU."""
     rng = np.random.default_rng(seed)
     if spectrum == "gaussian":
         a = torch.from_numpy(rng.standard_normal((n, n))).cuda()
         return a.t().contiguous().t()
-    if spectrum == "geometric":
-        s = np.geomspace(1.0, 1e-16, n)
-    elif spectrum == "stairs":
-        s = 10.0 ** (-np.floor(np.arange(n) / 512))
-    else:
-        raise ValueError(spectrum)
+    if spectrum == "kahan":
+        return torch.from_numpy(np.ascontiguousarray(kahan(n, 1.2).T)).cuda().t()
+    s = device_spectrum(n, spectrum, seed)
 
     def haar():
         g = torch.from_numpy(rng.standard_normal((n, n))).cuda()
