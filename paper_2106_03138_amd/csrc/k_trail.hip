@@ -124,7 +124,10 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
     const double *Abase = a.A + (c0 + jb) * a.lda + ns;
     // staged element u*512 + tid: row r = tid % G1_KC, column/reflector q = u*G1_CPP + tid/G1_KC
     const int rr = tid % G1_KC, qq = tid / G1_KC;
-    T vreg[G1_VU], areg[G1_AU];
+    // A is staged in registers as loaded (FP64) and rounded to T only when it is
+    // written to LDS, so the loads of a chunk stay in flight during the MFMAs
+    T vreg[G1_VU];
+    double areg[G1_AU];
     auto fetch = [&](int64_t rc) {
         const int64_t row = rc + rr;
         const bool rok = row < re;
@@ -136,7 +139,7 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
 #pragma unroll
         for (int u = 0; u < G1_AU; ++u) {
             const int q = u * G1_CPP + qq;
-            areg[u] = (rok && q < ncols) ? (T)Abase[(int64_t)q * a.lda + row] : (T)0;
+            areg[u] = (rok && q < ncols) ? Abase[(int64_t)q * a.lda + row] : 0.0;
         }
     };
     fetch(rb);
@@ -145,7 +148,7 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
 #pragma unroll
         for (int u = 0; u < G1_VU; ++u) Vs[(u * G1_CPP + qq) * G1_LD + rr] = vreg[u];
 #pragma unroll
-        for (int u = 0; u < G1_AU; ++u) As[(u * G1_CPP + qq) * G1_LD + rr] = areg[u];
+        for (int u = 0; u < G1_AU; ++u) As[(u * G1_CPP + qq) * G1_LD + rr] = (T)areg[u];
         __syncthreads();
         if (rc + G1_KC < re) fetch(rc + G1_KC);
         // wave wv owns columns [16 G1_CT wv, 16 G1_CT (wv + 1)): G1_CT column tiles x ltz row tiles
@@ -155,9 +158,12 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
 #pragma unroll
             for (int c = 0; c < G1_CT; ++c)
                 bcol[c] = As[(wv * 16 * G1_CT + c * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
+            // FP32: all four row tiles without a branch per tile (the V rows past
+            // l are staged as zeros; only the tiles below ltz are stored), which
+            // keeps the FP32 accumulators in place; FP64 skips the empty tiles
 #pragma unroll
             for (int ti = 0; ti < 4; ++ti) {
-                if (ti < ltz) {
+                if (sizeof(T) == 4 || ti < ltz) {
                     const T av = Vs[(ti * 16 + (lane & 15)) * G1_LD + k + (lane >> 4)];
 #pragma unroll
                     for (int c = 0; c < G1_CT; ++c)
