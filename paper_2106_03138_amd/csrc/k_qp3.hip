@@ -28,37 +28,20 @@
 #define QP_ROWS 256  // rows per workgroup of the pivot-column pass
 #define QP_NBMAX 64
 
-// Lane exchanges on the VALU (DPP row operations and the gfx950 lane swaps)
-// instead of LDS permutes, whose latency the reductions of these latency-bound
-// kernels would otherwise pay once per level: qp_x<K>(v) is v of lane ^ K for
-// K = 32, 16, 8, 2, 1, and qp_x<7> that of lane ^ 7 (the mirror within each
-// group of 8 lanes), which takes the place of lane ^ 4 in the trees below.
-// Every kernel of this file reduces through them, so all its paths sum in
-// the same order.
-template <int K>
-__device__ __forceinline__ uint32_t qp_xu(uint32_t v) {
-    if constexpr (K == 32) {
-        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-        return (threadIdx.x & 32) ? r[0] : r[1];
-    } else if constexpr (K == 16) {
-        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (threadIdx.x & 16) ? r[0] : r[1];
-    } else {
-        // row_ror:8, row_half_mirror, quad_perm(2,3,0,1), quad_perm(1,0,3,2)
-        constexpr int ctrl = K == 8 ? 0x128 : K == 7 ? 0x141 : K == 2 ? 0x4e : 0xb1;
-        static_assert(K == 8 || K == 7 || K == 2 || K == 1, "lane exchange");
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
-    }
-}
+// Lane exchanges on the VALU (lane_xu / lane_xd of qrdm_internal.h: DPP row
+// operations and the gfx950 lane swaps) instead of LDS permutes, whose latency
+// the reductions of these latency-bound kernels would otherwise pay once per
+// level: qp_x<K>(v) is v of lane ^ K for K = 32, 16, 8, 2, 1, and qp_x<7> that
+// of lane ^ 7 (the mirror within each group of 8 lanes), which takes the place
+// of lane ^ 4 in the trees below.  Every kernel of this file reduces through
+// them, so all its paths sum in the same order.
 template <int K>
 __device__ __forceinline__ double qp_x(double v) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint64_t lo = qp_xu<K>((uint32_t)b), hi = qp_xu<K>((uint32_t)(b >> 32));
-    return __longlong_as_double((long long)((hi << 32) | lo));
+    return lane_xd<K>(v);
 }
 template <int K>
 __device__ __forceinline__ int qp_xi(int v) {
-    return (int)qp_xu<K>((uint32_t)v);
+    return (int)lane_xu<K>((uint32_t)v);
 }
 // Sum over the 64 lanes, the same value in every lane.
 __device__ __forceinline__ double qp_wave_sum(double v) {
@@ -1283,4 +1266,464 @@ int qp3_block_grid(int64_t m) {
     const int g = ncu < QP_RUN_MAXWG ? ncu : QP_RUN_MAXWG;
     if (g < 1 || npart > (int64_t)g) return 0;
     return g;
+}
+
+// ====================================================== LDS-resident tail
+// Column pivoting (Algorithm 2) on a trailing block small enough for the LDS of
+// the grid: every remaining step in one persistent launch, in the unblocked
+// form (each reflector applied at once), with one grid barrier per step.
+//
+// Workgroup w holds the trailing columns c = w + G k (offsets from the first
+// column j0 of the launch) from row j0 down, with their partial norms and
+// current positions, for the whole launch.  Per step j:
+//   every workgroup reduces the G published (norm, position) partials to the
+//   pivot (largest partial norm, lowest position on ties), reads the pivot's
+//   column from its owner's published copy, and forms the reflector (LAPACK
+//   larfg convention) from it, all in the same order, so every workgroup
+//   holds the same bits; the owner writes the final column j (R above, beta,
+//   v below) and tau_j;
+//   the swap of positions j and the pivot's: each workgroup moves its slab of
+//   the rows above j0 (R12 entries of both columns), workgroup 0 the
+//   permutation, and the owner of the column at position j notes its new
+//   position;
+//   each workgroup applies H_j to its columns in LDS and downdates their
+//   partial norms by the cancellation-safe rule (recomputed from LDS when the
+//   downdate lost too much), then publishes its largest (norm, position) and,
+//   ahead of the barrier, a copy of that column below row j: whichever
+//   workgroup wins, its column is already out for the next step;
+//   grid barrier.
+// The stopping test is applied at every step as in the other QP3 kernels.  At
+// the end the columns not pivoted (a stop) are written back to their final
+// positions.  A launch that follows a QP3 block launch first finishes what the
+// block left: the last reflector's normalization and the flagged norms.
+#define QT_THREADS 256
+#define QT_LDS_MAX (150 * 1024)  // dynamic LDS of the tail kernel (at most)
+#define QT_ROWS_MAX 2048         // largest trailing block height it takes
+#define QT_META 4                // doubles per published partial: norm, position, column, unused
+
+extern __shared__ double qt_lds[];
+
+// Dynamic LDS of the tail kernel for cq columns of crows rows per workgroup:
+// the columns, the pivot column, and the columns' norms and positions.
+__host__ __device__ inline size_t qt_lds_bytes(int cq, int crows) {
+    return sizeof(double) * ((size_t)cq * crows + crows + 2 * (size_t)cq) + 2 * sizeof(int32_t) * (size_t)cq;
+}
+
+__global__ void __launch_bounds__(QT_THREADS)
+k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch) {
+    QrdmCtl *ctl = a.ctl;
+    if (ctl->done) {
+        if (a.snap && blockIdx.x == 0 && threadIdx.x == 0) qrdm_write_snapshot(ctl, a.snap);
+        return;
+    }
+    const int G = gridDim.x, wg = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t *gb = a.gbar + (launch & 1) * GBAR_GROUPS * GBAR_STRIDE;
+    if (wg == 0 && tid == 0) gbar_clear(a.gbar + ((launch + 1) & 1) * GBAR_GROUPS * GBAR_STRIDE);
+    const int64_t p = p_of(a);
+    __shared__ double s_v[QT_THREADS / 64];
+    __shared__ int s_j[QT_THREADS / 64];
+    __shared__ int s_k[QT_THREADS / 64];
+    __shared__ double s_red[QT_THREADS / 64];
+    // loop state (identical in every workgroup)
+    int64_t ns = ctl->ns, rank = ctl->rank, nblocks = ctl->nblocks, jm = ctl->jmax;
+    const int64_t k0 = ctl->qp_k0;
+    const int l = ctl->l, b = ctl->qp_b, qstop = ctl->qp_stop;
+    int pend = ctl->qp_pend, done = 0;
+    double amax = ctl->amax, umax = ctl->umax;
+    const double pbeta = ctl->qp_beta, pden = ctl->qp_den;
+    uint32_t bar = 0;
+    // ---- what a preceding QP3 block launch left (as k_qp_run's prologue): a
+    // block closed at its last step (l = 1) or by the stopping test (qstop)
+    if (l == 1 || qstop) {
+        const int kbp = qstop ? b : b + 1;
+        const int64_t last = k0 + kbp - 1;
+        const bool final_step = qstop || last + 1 >= p;
+        if (final_step && kbp > 0) {
+            const double rden = 1.0 / pden;
+            for (int64_t r = last + 1 + (int64_t)wg * QT_THREADS + tid; r < a.m; r += (int64_t)G * QT_THREADS)
+                a.A[last * a.lda + r] *= rden;
+            if (wg == 0 && tid == 0) a.A[last * a.lda + last] = pbeta;
+            pend = 0;
+        }
+        if (final_step && qstop) done = 1;
+    }
+    if (l == 1) {  // the advance past the block's last reflector
+        ns += 1;
+        pend = pend || !(ns >= p);
+    }
+    if (!done && pend && ns < p) {  // normalize the pending reflector ns - 1
+        const int64_t pc = ns - 1;
+        const double rden = 1.0 / pden;
+        for (int64_t r = ns + (int64_t)wg * QT_THREADS + tid; r < a.m; r += (int64_t)G * QT_THREADS)
+            a.A[pc * a.lda + r] *= rden;
+        if (wg == 0 && tid == 0) a.A[pc * a.lda + pc] = pbeta;
+    }
+    const int64_t j0 = ns;
+    const int64_t t0 = a.m > j0 ? a.m - j0 : 0, w0 = a.n > j0 ? a.n - j0 : 0;
+    const int q = wg < w0 ? (int)((w0 - wg + G - 1) / G) : 0;  // columns of this workgroup
+    if ((w0 + G - 1) / G > cq || t0 > crows) {  // the host sized the LDS from bounds (cannot fail)
+        if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
+        return;
+    }
+    double *cc = qt_lds;                          // [cq][crows], rows from j0
+    double *xs = cc + (size_t)cq * crows;         // [crows]: the pivot column, then v
+    double *n1 = xs + crows;                      // [cq]
+    double *n2 = n1 + cq;                         // [cq]
+    int32_t *pos = (int32_t *)(n2 + cq);          // [cq]: current position offset (from j0)
+    int32_t *act = pos + cq;                      // [cq]: not yet pivoted
+    double *meta = pub;                           // [2][G][QT_META]
+    double *pdat = pub + 2 * (size_t)G * QT_META; // [2][G][crows]
+    // ---- load this workgroup's columns, norms and flags
+    {
+        const int64_t tot = (int64_t)q * t0;
+        for (int64_t i0 = 0; i0 < tot; i0 += 8 * QT_THREADS) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + tid + QT_THREADS * u;
+                const int64_t k = t0 > 0 ? i / t0 : 0;
+                v[u] = i < tot ? a.A[(j0 + wg + (int64_t)G * k) * a.lda + j0 + i % t0] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + tid + QT_THREADS * u;
+                if (i < tot) cc[(i / t0) * crows + i % t0] = v[u];
+            }
+        }
+        for (int k = tid; k < q; k += QT_THREADS) {
+            const int64_t c = j0 + wg + (int64_t)G * k;
+            n1[k] = qr_ld(a.vn1 + c);
+            n2[k] = qr_ld(a.vn2 + c);
+            pos[k] = wg + G * k;
+            act[k] = 1;
+        }
+        __syncthreads();
+    }
+    int64_t nrec = 0;
+    // flagged partial norms (a preceding block launch): recomputed from LDS,
+    // one wavefront per column
+    for (int k = wv; k < q; k += QT_THREADS / 64) {
+        const int64_t c = j0 + wg + (int64_t)G * k;
+        if (!qr_ldi(flag + c)) continue;
+        double t = 0.0;
+        for (int64_t r = lane; r < t0; r += 64) t += cc[k * crows + r] * cc[k * crows + r];
+        t = qp_wave_sum(t);
+        if (lane == 0) {
+            const double v = sqrt(t);
+            n1[k] = v;
+            n2[k] = v;
+            qr_sti(flag + c, 0);
+            ++nrec;
+        }
+    }
+    __syncthreads();
+    // this workgroup's largest (norm, position) over its active columns: the
+    // wavefront k % 4 takes column k, as in the update below
+    auto local_best = [&](double &bv, int &bp, int &bk) {
+        bv = -1.0;
+        bp = 0x7fffffff;
+        bk = -1;
+        if (lane == 0) {
+            for (int k = wv; k < q; k += QT_THREADS / 64)
+                if (act[k] && qp_better(n1[k], pos[k], bv, bp)) { bv = n1[k]; bp = pos[k]; bk = k; }
+            s_v[wv] = bv;
+            s_j[wv] = bp;
+            s_k[wv] = bk;
+        }
+        __syncthreads();
+        bv = s_v[0];
+        bp = s_j[0];
+        bk = s_k[0];
+        for (int w = 1; w < QT_THREADS / 64; ++w)
+            if (qp_better(s_v[w], s_j[w], bv, bp)) { bv = s_v[w]; bp = s_j[w]; bk = s_k[w]; }
+        __syncthreads();
+    };
+    // publishes the partial (norm, position, column) and rows [jr, m) of the
+    // local best column for the step at jr, into parity slot par
+    auto publish = [&](int par, int64_t jr, double bv, int bp, int bk) {
+        double *me = meta + ((size_t)par * G + wg) * QT_META;
+        if (tid == 0) {
+            qr_st(me, bv);
+            qr_st(me + 1, (double)bp);
+            qr_st(me + 2, bk >= 0 ? (double)(wg + G * bk) : -1.0);
+        }
+        if (bk >= 0) {
+            double *dst = pdat + ((size_t)par * G + wg) * crows;
+            const double *src = cc + (size_t)bk * crows + (jr - j0);
+            const int64_t nr = a.m - jr;
+            for (int64_t i = tid; i < nr; i += QT_THREADS) qr_st(dst + i, src[i]);
+        }
+    };
+    {
+        double bv;
+        int bp, bk;
+        local_best(bv, bp, bk);
+        publish(0, j0, bv, bp, bk);
+    }
+    gbar_wait(gb, G, ++bar, &ctl->error);
+    // the slab of the rows above j0 whose R12 entries this workgroup swaps
+    const int64_t ur = (j0 + G - 1) / G;
+    const int64_t ur0 = (int64_t)wg * ur, ur1 = ur0 + ur < j0 ? ur0 + ur : j0;
+    int64_t j = j0;
+    for (int par = 0; !done; par ^= 1) {
+        if (j >= p) {
+            done = 1;
+            if (rank < 0) rank = j;
+            break;
+        }
+        // ---- the pivot: the G partials of this step
+        double uv = -1.0;
+        int up = 0x7fffffff, uc = -1;
+        {
+            double bv = -1.0;
+            int bp = 0x7fffffff, bc = -1;
+            for (int w = tid; w < G; w += QT_THREADS) {
+                const double *me = meta + ((size_t)par * G + w) * QT_META;
+                const double v = qr_ld(me), pd = qr_ld(me + 1), cd = qr_ld(me + 2);
+                if (qp_better(v, (int)pd, bv, bp)) { bv = v; bp = (int)pd; bc = (int)cd; }
+            }
+            // (norm, position) is a total order: the winner's column rides along
+            double vv = bv;
+            int pp = bp;
+            qp_argmax_lanes(vv, pp);
+            if (lane == 0) { s_v[wv] = vv; s_j[wv] = pp; s_k[wv] = -1; }
+            if (bp == pp && bv == vv && bc >= 0) s_k[wv] = bc;  // the one lane that holds it
+            __syncthreads();
+            uv = s_v[0];
+            up = s_j[0];
+            int wsel = 0;
+            for (int w = 1; w < QT_THREADS / 64; ++w)
+                if (qp_better(s_v[w], s_j[w], uv, up)) { uv = s_v[w]; up = s_j[w]; wsel = w; }
+            uc = s_k[wsel];
+            __syncthreads();
+        }
+        // ---- stopping test (as k_qp_select)
+        if (nblocks == 0 && j == 0) amax = uv;
+        if (amax == 0.0) {
+            rank = 0;
+            done = 1;
+            break;
+        }
+        if (rank < 0) {
+            const double lhs = (a.stop_rule == 1) ? uv : sqrt((double)(a.n - j)) * uv;
+            if (lhs <= a.eps1 * amax) {
+                rank = j;
+                if (a.stop_rule != 2) {
+                    done = 1;
+                    break;
+                }
+            }
+        }
+        if (uc < 0) {  // no column left (cannot happen before j = p)
+            if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
+            done = 1;
+            break;
+        }
+        jm = j0 + up;
+        umax = uv;
+        nblocks += 1;
+        const int owner = uc % G, kw = uc / G;
+        const int64_t t = a.m - j;  // rows of the reflector
+        // ---- the pivot column from its owner's copy, and the reflector
+        {
+            const double *src = pdat + ((size_t)par * G + owner) * crows;
+            double xv[8];
+            for (int64_t i0 = 0; i0 < t; i0 += 8 * QT_THREADS) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t i = i0 + tid + QT_THREADS * u;
+                    xv[u] = i < t ? qr_ld(src + i) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int64_t i = i0 + tid + QT_THREADS * u;
+                    if (i < t) xs[i] = xv[u];
+                }
+            }
+        }
+        __syncthreads();
+        double sp = 0.0;
+        for (int64_t i = 1 + tid; i < t; i += QT_THREADS) sp += xs[i] * xs[i];
+        sp = qp_wave_sum(sp);
+        if (lane == 0) s_red[wv] = sp;
+        __syncthreads();
+        sp = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        const double alpha = xs[0];
+        double beta, ti, den;
+        if (sp == 0.0) {
+            ti = 0.0;
+            beta = alpha;
+            den = 1.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + sp);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            ti = (beta - alpha) / beta;
+            den = alpha - beta;
+        }
+        const double rden = 1.0 / den;
+        __syncthreads();  // every thread has read xs[0]
+        for (int64_t i = tid; i < t; i += QT_THREADS) xs[i] = (i == 0) ? 1.0 : xs[i] * rden;
+        __syncthreads();
+        // ---- the owner: the final column j and tau_j
+        if (wg == owner) {
+            double *colj = a.A + j * a.lda;
+            const double *mine = cc + (size_t)kw * crows;
+            for (int64_t r = tid; r < t0; r += QT_THREADS) {
+                const int64_t row = j0 + r;
+                const double v = row < j ? mine[r] : (row == j ? beta : xs[row - j]);
+                colj[row] = v;
+            }
+            if (tid == 0) {
+                a.tau_house[j] = ti;
+                act[kw] = 0;
+                pos[kw] = (int32_t)(j - j0);
+            }
+        }
+        // ---- the swap of positions j and jm: this workgroup's slab of rows
+        // above j0, the permutation (workgroup 0), the displaced column's position
+        if (jm != j) {
+            for (int64_t r = ur0 + tid; r < ur1; r += QT_THREADS) {
+                const double x1 = a.A[j * a.lda + r], x2 = a.A[jm * a.lda + r];
+                a.A[j * a.lda + r] = x2;
+                a.A[jm * a.lda + r] = x1;
+            }
+            if (wg == 0 && tid == 0) {
+                const int32_t p1 = a.perm[j], p2 = a.perm[jm];
+                a.perm[j] = p2;
+                a.perm[jm] = p1;
+            }
+            for (int k = tid; k < q; k += QT_THREADS)
+                if (act[k] && pos[k] == (int32_t)(j - j0) && !(wg == owner && k == kw)) pos[k] = (int32_t)up;
+        }
+        __syncthreads();
+        // ---- H_j applied to this workgroup's active columns (wavefront k % 4
+        // takes column k), then the partial norm downdate
+        const int64_t rj = j - j0;
+        for (int k = wv; k < q; k += QT_THREADS / 64) {
+            if (!act[k]) continue;
+            double *col = cc + (size_t)k * crows + rj;
+            double e[4] = {0.0, 0.0, 0.0, 0.0};
+            int64_t i = lane;
+            for (; i + 192 < t; i += 256) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) e[u] += xs[i + 64 * u] * col[i + 64 * u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (i + 64 * u < t) e[u] += xs[i + 64 * u] * col[i + 64 * u];
+            const double dot = qp_wave_sum((e[0] + e[1]) + (e[2] + e[3]));
+            const double wcol = ti * dot;
+            for (int64_t r = lane; r < t; r += 64) col[r] -= wcol * xs[r];
+            const double rjc = __shfl(col[0], 0, 64);  // row j of the column after H_j (lane 0's store)
+            double v1 = n1[k];
+            if (v1 != 0.0) {
+                double qq = 1.0 - (rjc * rjc) / (v1 * v1);
+                if (qq < 0.0) qq = 0.0;
+                const double r12 = v1 / n2[k];
+                const double q2 = qq * (r12 * r12);
+                if (q2 <= a.tol3z) {  // recompute from the rows below j (one sum order in every path)
+                    double s2 = 0.0;
+                    for (int64_t r = 1 + lane; r < t; r += 64) s2 += col[r] * col[r];
+                    s2 = qp_wave_sum(s2);
+                    v1 = sqrt(s2);
+                    if (lane == 0) {
+                        n2[k] = v1;
+                        ++nrec;
+                    }
+                } else {
+                    v1 = v1 * sqrt(qq);
+                }
+                if (lane == 0) n1[k] = v1;
+            }
+        }
+        __syncthreads();
+        // ---- publish for the step at j + 1, then the barrier
+        {
+            double bv;
+            int bp, bk;
+            local_best(bv, bp, bk);
+            publish(par ^ 1, j + 1, bv, bp, bk);
+        }
+        gbar_wait(gb, G, ++bar, &ctl->error);
+        j += 1;
+    }
+    // ---- the columns not pivoted (a stop): back to their final positions
+    for (int k = 0; k < q; ++k) {
+        if (!act[k]) continue;
+        double *dst = a.A + (j0 + pos[k]) * a.lda + j0;
+        for (int64_t r = tid; r < t0; r += QT_THREADS) dst[r] = cc[(size_t)k * crows + r];
+    }
+    if (nrec && lane == 0) atomicAdd((unsigned long long *)&ctl->nrecompute, (unsigned long long)nrec);
+    // every workgroup has read the loop state (the barrier after the first
+    // publish) before workgroup 0 writes it back
+    if (wg == 0 && tid == 0) {
+        ctl->ns = j;
+        ctl->rank = rank;
+        ctl->qp_k0 = j;
+        ctl->nblocks = nblocks;
+        ctl->jmax = jm;
+        ctl->l = 0;
+        ctl->qp_b = 0;
+        ctl->qp_pend = 0;
+        ctl->qp_stop = 0;
+        ctl->qp_flag = 0;
+        ctl->amax = amax;
+        ctl->umax = umax;
+        ctl->done = 1;
+        __builtin_amdgcn_s_waitcnt(0);
+        if (a.snap) qrdm_write_snapshot(ctl, a.snap);
+    }
+}
+
+// LDS shape of the tail kernel from bounds on its trailing block (t_bound rows,
+// w_bound columns) and its grid; false when it does not fit.
+bool qp3_tail_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, int *crows, size_t *bytes) {
+    if (grid < 1) return false;
+    const int64_t rows = t_bound > 1 ? t_bound : 1;
+    const int64_t q = w_bound > 0 ? (w_bound + grid - 1) / grid : 1;
+    if (rows > QT_ROWS_MAX || q > (int64_t)(QT_LDS_MAX / 8)) return false;
+    const size_t need = qt_lds_bytes((int)q, (int)rows);
+    if (need > QT_LDS_MAX) return false;
+    *cq = (int)q;
+    *crows = (int)rows;
+    *bytes = need;
+    return true;
+}
+
+// Doubles of the published partials and column copies of the tail kernel for m rows.
+size_t qp3_tail_pub_doubles(int64_t m) {
+    const int64_t rows = m < QT_ROWS_MAX ? (m > 1 ? m : 1) : QT_ROWS_MAX;
+    return 2 * (size_t)QP_RUN_MAXWG * QT_META + 2 * (size_t)QP_RUN_MAXWG * (size_t)rows;
+}
+
+// One workgroup per compute unit (at most QP_RUN_MAXWG), all co-resident; 0
+// when the device cannot hold that grid with the kernel's LDS.
+int qp3_tail_grid() {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipFuncSetAttribute((const void *)k_qp_tail, hipFuncAttributeMaxDynamicSharedMemorySize, QT_LDS_MAX) !=
+        hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_tail, QT_THREADS, QT_LDS_MAX) !=
+            hipSuccess ||
+        per_cu < 1)
+        return 0;
+    return ncu < QP_RUN_MAXWG ? ncu : QP_RUN_MAXWG;
+}
+
+hipError_t launch_qp3_tail(QrdmArgs a, double *pub, int32_t *flag, int64_t t_bound, int64_t w_bound, int grid,
+                           int launch, hipStream_t s, hipEvent_t *ev) {
+    int cq = 0, crows = 0;
+    size_t lds = 0;
+    if (grid < 1 || grid > QP_RUN_MAXWG || !qp3_tail_shape(t_bound, w_bound, grid, &cq, &crows, &lds))
+        return hipErrorInvalidValue;
+    void *args[] = {&a, &pub, &flag, &cq, &crows, &launch};
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    e = launch_resident((const void *)k_qp_tail, dim3(grid), dim3(QT_THREADS), args, (unsigned)lds, s);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    return hipSuccess;
 }

@@ -185,7 +185,10 @@ Layout make_layout(int64_t m, int64_t n, int kmax) {
     L.vw = take(sizeof(double) * kp * (size_t)mm);
     L.vw32 = take(sizeof(float) * kp * (size_t)mm);
     L.z = take(sizeof(double) * kp * (size_t)nn);
-    L.yp = take(sizeof(double) * (size_t)trail_splits_max() * (size_t)trail_ysplit((int)kp, nn));
+    // split-K partials of V^T A; the column-pivoting tail kernel, which runs after
+    // the DM loop, publishes its partials and column copies in the same region
+    L.yp = take(sizeof(double) * std::max((size_t)trail_splits_max() * (size_t)trail_ysplit((int)kp, nn),
+                                          qp3_tail_pub_doubles(mm)));
     L.pb2 = take(sizeof(double) * (size_t)((mm + 255) / 256) * (2 + 2 * 64));
     L.fz = take(sizeof(double) * kQp3NbMax * (size_t)nn);
     L.flag = take(sizeof(int32_t) * (size_t)nn);
@@ -307,8 +310,16 @@ const double kEps32 = 1.1920928955078125e-07;
 struct ProfRun {
     bool on = false;
     int64_t dm_iters = 0;     // DM steps with 8 events each
-    int64_t qp_launches = 0;  // QP3 block-kernel launches with 2 events each
+    int64_t qp_launches = 0;  // QP3 block- and tail-kernel launches with 2 events each
+    int64_t tail_launches = 0;  // of which tail-kernel launches (0 or 1)
 };
+
+// The failure a snapshot reports (NaN/Inf in A, a timed-out grid wait), or 0.
+int snapshot_code(const Snapshot &sn) {
+    if (sn.nonfinite) return QRDM_ERR_NONFINITE;
+    if (sn.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
+    return 0;
+}
 const int kEv = 8;  // per DM step: select, panel, panel end, GEMM1/GEMM2 start/end, downdate end
 
 double qp3_bytes(int64_t m, int64_t n, int64_t j0, int64_t j1) {
@@ -326,14 +337,20 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
     bf.Fz = (double *)(ws + L.fz);
     bf.flag = (int32_t *)(ws + L.flag);
     bf.amx = (double *)(ws + L.qrb);
+    bf.pub = (double *)(ws + L.yp);
     HIP_TRY(launch_qp3_init(a, nb, s));
     const int ring = pc.ring;
     const int64_t pmin = std::min(a.m, a.n);
     const char *mode = getenv("QRDM_QP3_STEPS");  // "1": the per-step kernels (comparison runs)
     const int grid = (mode && strcmp(mode, "1") == 0) ? 0 : qp3_block_grid(a.m);
+    // "0": no LDS-resident tail (comparison runs of the block kernel)
+    const char *tmode = getenv("QRDM_QP3_TAIL");
+    const int tgrid = (grid > 0 && !(tmode && strcmp(tmode, "0") == 0)) ? qp3_tail_grid() : 0;
     if (grid > 0) {
         // one block of up to nb steps per launch; a snapshot after each, the
-        // host waiting on the one `lag` launches back
+        // host waiting on the one `lag` launches back; once the trailing block
+        // fits in LDS (by the host's bound), one tail launch takes every
+        // remaining step
         for (int64_t iter = 0;; ++iter) {
             const int64_t tb = a.m - ns_known, wb = a.n - ns_known;
             hipEvent_t *ev = nullptr;
@@ -343,7 +360,22 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
                 prof.qp_launches = iter + 1;
             }
             QrdmArgs al = a;
-            al.snap = pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block kernel
+            al.snap = pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS;  // written by the block or tail kernel
+            int cq = 0, crows = 0;
+            size_t lds = 0;
+            if (tgrid > 0 && qp3_tail_shape(tb, wb, tgrid, &cq, &crows, &lds)) {
+                HIP_TRY(launch_qp3_tail(al, bf.pub, bf.flag, tb, wb, tgrid, (int)iter, s, ev));
+                if (prof.on) prof.tail_launches += 1;
+                int rc = poll_mark(pc, iter, s);
+                if (rc) return rc;
+                // the launches before it are older: this snapshot is the last one
+                Snapshot sn;
+                rc = poll_read(pc, iter, pc.dev_snap + (iter % ring) * QRDM_SNAP_WORDS, s, &sn);
+                if (rc) return rc;
+                if (!sn.done) return (sn.error || sn.nonfinite) ? snapshot_code(sn) : QRDM_ERR_INTERNAL;
+                *last = sn;
+                return 0;
+            }
             HIP_TRY(launch_qp3_block(al, bf, nb, tb, wb, grid, (int)iter, s, ev));
             int rc = poll_mark(pc, iter, s);
             if (rc) return rc;
@@ -593,12 +625,6 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
     if (env.rank_dev) HIP_TRY(launch_rank_out(a.ctl, env.rank_dev, s));
     if (env.nlog) *env.nlog = nrec;
     *final = last;
-    return 0;
-}
-
-int snapshot_code(const Snapshot &sn) {
-    if (sn.nonfinite) return QRDM_ERR_NONFINITE;
-    if (sn.error) return QRDM_ERR_HIP + (int)hipErrorLaunchTimeOut;
     return 0;
 }
 

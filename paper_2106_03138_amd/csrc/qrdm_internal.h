@@ -203,6 +203,7 @@ struct Qp3Bufs {
     double *Fz;       // [nb][n]: F^T of the deferred update, absolute column index
     int32_t *flag;    // [n]: partial norm needs recomputation
     double *amx;      // [QP_RUN_MAXWG][4]: per-workgroup arg-max partials of the block kernel
+    double *pub;      // [qp3_tail_pub_doubles(m)]: the tail kernel's published partials and columns
 };
 hipError_t launch_qp3_init(QrdmArgs a, int nb, hipStream_t s);
 hipError_t launch_gemm2_qp3(QrdmArgs a, const double *Vw, int64_t ldv, const double *Fz, int64_t t_bound,
@@ -212,6 +213,13 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64
 int qp3_block_grid(int64_t m);
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, int grid,
                             int launch, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
+// LDS-resident tail of the column-pivoting loop: every remaining step in one
+// launch once the trailing block fits in the LDS of the grid (qp3_tail_shape).
+int qp3_tail_grid();
+bool qp3_tail_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, int *crows, size_t *bytes);
+size_t qp3_tail_pub_doubles(int64_t m);
+hipError_t launch_qp3_tail(QrdmArgs a, double *pub, int32_t *flag, int64_t t_bound, int64_t w_bound, int grid,
+                           int launch, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_tail
 int panel_max_wgs(int rows_per_wg);
 int panel_rows_per_wg(int kmax);
 int panel_rows_for(int64_t m, int kmax);

@@ -1,11 +1,19 @@
 """The QP3 column loop (Algorithm 2 blocked like xgeqp3) runs one block of up
-to nb pivots per cooperative launch; the per-step kernels remain selectable
+to nb pivots per launch; the per-step kernels remain selectable
 (QRDM_QP3_STEPS=1).  Both carry out the same arithmetic in the same order, so
 pivots and rank must agree exactly and R / tau to rounding of the contraction
-(1e-13 relative).  The block kernel holds its columns in LDS when they fit
+(1e-13 relative); these comparisons switch the LDS-resident tail off
+(QRDM_QP3_TAIL=0).  The block kernel holds its columns in LDS when they fit
 (2048 rows at most) and reads them from memory otherwise: tall_2200x400
 starts in the second mode and ends in the first.  The block path is also
-checked against the oracle."""
+checked against the oracle.
+
+Once the trailing block fits in the LDS of the grid, the loop hands every
+remaining step to one launch of the tail kernel (unblocked, one grid barrier
+per step): from the start on matrices of at most 2048 rows, after some block
+launches on taller ones (the hand-over finishes the block's last reflector
+and its flagged norms, or a stop inside the block).  It is checked against the
+oracle on the same cases."""
 import numpy as np
 import pytest
 
@@ -42,11 +50,15 @@ CASES = {
 }
 
 
-def _run(Q, a, steps, monkeypatch, **kw):
+def _run(Q, a, steps, monkeypatch, tail=False, **kw):
     if steps:
         monkeypatch.setenv("QRDM_QP3_STEPS", "1")
     else:
         monkeypatch.delenv("QRDM_QP3_STEPS", raising=False)
+    if tail:
+        monkeypatch.delenv("QRDM_QP3_TAIL", raising=False)
+    else:
+        monkeypatch.setenv("QRDM_QP3_TAIL", "0")
     A = Q.device_matrix(a)
     out = Q.qrp_factor(A, **kw)
     return Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.stats
@@ -88,6 +100,7 @@ def test_qrdm_continuation_block_vs_steps(monkeypatch):
     n = 768
     a = I.from_spectrum(n, n, np.geomspace(1, 1e-16, n), 2)
     res = []
+    monkeypatch.setenv("QRDM_QP3_TAIL", "0")
     for steps in (True, False):
         if steps:
             monkeypatch.setenv("QRDM_QP3_STEPS", "1")
@@ -98,3 +111,60 @@ def test_qrdm_continuation_block_vs_steps(monkeypatch):
         res.append((Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.stats))
     assert res[0][4]["nfallback"] > 0
     _same(res[0], res[1], 1.0)
+
+
+TAIL_CASES = dict(CASES)
+TAIL_CASES["graded_2200x300"] = lambda: _graded(2200, 300, 19)  # blocks with flagged norms, then the tail
+
+
+@pytest.mark.parametrize("name", sorted(TAIL_CASES))
+@pytest.mark.parametrize("rule", [oracle.STOP_PAPER, oracle.STOP_NONE, oracle.STOP_MAXNORM])
+def test_tail_kernel_matches_oracle(name, rule, monkeypatch):
+    """QRP with the LDS-resident tail (the default path) against the oracle."""
+    Q = _gpu()
+    a = TAIL_CASES[name]()
+    print(f"case {name} rule {rule}", flush=True)
+    R, tau, perm, rank, st = _run(Q, a, False, monkeypatch, tail=True, stop_rule=rule)
+    ref = oracle.qrp(a, stop_rule=rule)
+    m, n = a.shape
+    if min(m, n) == 0 or not np.any(a):
+        assert rank == 0 and np.array_equal(perm, np.arange(n))
+        return
+    compare(a, ref, R, tau, perm, rank, [], check_blocks=False, full=(rule == oracle.STOP_NONE), stop_rule=rule,
+            kmax=1)
+
+
+def test_tail_after_a_stop_inside_a_block(monkeypatch):
+    """A stop inside a block launch (column 60 of the block 32..63), and the tail
+    launch right after it (no poll lag: the host sees 2040 rows left): the tail
+    finishes the stopped block and ends the loop."""
+    Q = _gpu()
+    n = 300
+    s = np.concatenate([np.geomspace(1.0, 1e-3, 60), np.full(n - 60, 1e-15)])
+    a = I.from_spectrum(2100, n, s, 23)
+    ref = oracle.qrp(a, stop_rule=oracle.STOP_MAXNORM)
+    R, tau, perm, rank, _ = _run(Q, a, False, monkeypatch, tail=True, stop_rule=oracle.STOP_MAXNORM, poll_lag=0)
+    assert rank == ref.rank == 60
+    compare(a, ref, R, tau, perm, rank, [], check_blocks=False, stop_rule=oracle.STOP_MAXNORM, kmax=1)
+
+
+def test_qrdm_continuation_with_the_tail(monkeypatch):
+    """QRDM's scalar-pivoting continuation on the tail kernel agrees with the
+    block kernel's to rounding on the decisions taken above the noise level,
+    and both with the oracle."""
+    Q = _gpu()
+    n = 1300
+    a = I.from_spectrum(1500, n, np.geomspace(1, 1e-16, n), 9)
+    ref = oracle.qrdm(a, stop_rule=oracle.STOP_NONE)
+    outs = []
+    for tail in (True, False):
+        if tail:
+            monkeypatch.delenv("QRDM_QP3_TAIL", raising=False)
+        else:
+            monkeypatch.setenv("QRDM_QP3_TAIL", "0")
+        A = Q.device_matrix(a)
+        out = Q.qrdm_factor(A, stop_rule=oracle.STOP_NONE, log=True)
+        outs.append(out)
+        compare(a, ref, Q.host_matrix(A), out.tau_house.cpu().numpy(), out.perm.cpu().numpy(), out.rank, out.blocks,
+                full=True, stop_rule=oracle.STOP_NONE, kmax=64)
+    assert outs[0].stats["qp3_start"] == outs[1].stats["qp3_start"] > 0
