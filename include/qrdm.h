@@ -129,6 +129,9 @@ typedef struct {
     int64_t qp3_start;   /* first column of the column-pivoting loop: the column where the
                             switch of eq. (column_norm_bound_DM) held (QRDM), 0 for QRP,
                             -1 when the factorization never switched (always filled)       */
+    int64_t ngram;       /* panels formed from the Gram matrix of the block (CholeskyQR2 and
+                            Householder reconstruction) rather than column by column
+                            (always filled)                                                  */
 } qrdm_stats;
 
 /* One record per outer step of the DM loop, for tests and tracing.  When the

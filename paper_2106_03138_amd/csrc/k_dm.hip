@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             // greedy acceptance in candidate order (Algorithm 1): candidate i joins
             // when it conflicts with no accepted candidate and its norm is nonzero;
             // lane L holds the masks of candidates L and L + 64
-            const unsigned long long r00 = lane < nL ? sbad[lane][0] : 0ull, r01 = lane < nL ? sbad[lane][1] : 0ull;
+            const unsigned long long r00 = lane < nL ? sbad[lane][0] : 0ull;
             const unsigned long long r10 = lane + 64 < nL ? sbad[lane + 64][0] : 0ull;
             const unsigned long long r11 = lane + 64 < nL ? sbad[lane + 64][1] : 0ull;
             const bool pos0 = lane < nL && sd[lane] > 0.0, pos1 = lane + 64 < nL && sd[lane + 64] > 0.0;
@@ -684,7 +684,10 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             ctl->nswap = nmv;
             ctl->ks = ks;
         }
-        for (int i = lane; i < ks; i += 64) ctl->J[i] = sJ[i];
+        for (int i = lane; i < ks; i += 64) {
+            ctl->J[i] = sJ[i];
+            ctl->Ai[i] = sAi[i];
+        }
     }
 }
 

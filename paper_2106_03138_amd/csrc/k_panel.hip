@@ -130,7 +130,7 @@ __device__ __forceinline__ void pn_update(double *S, int ksp, int r0, int nrows,
 __global__ void __launch_bounds__(PN_THREADS)
 k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv, int rows) {
     QrdmCtl *ctl = a.ctl;
-    if (qrdm_dm_idle(ctl)) return;
+    if (qrdm_dm_idle(ctl) || ctl->cpath) return;  // the Gram-matrix panel took the block
     const int64_t ns = ctl->ns;
     const int ks = ctl->ks;
     const double eps_s = ctl->eps_s;
@@ -301,8 +301,12 @@ k_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv
             q2 = (sR[i] - sTop2[i] * sTop2[i]) * (rden * rden);
             p1 = (sR[i + 1] - sTop2[i] * sTop2[i + 1]) * rden;
             const double alpha2 = sTop2[i + 1] - vc1 * wn;
-            const double sp2 = sG2[i + 1] - 2.0 * wn * p1 + wn * wn * q2;
-            const double mag = sG2[i + 1] + 2.0 * fabs(wn * p1) + wn * wn * q2;
+            // a column i+1 whose top is the last row has nothing below it: larfg
+            // leaves it alone (tau = 0, beta = alpha), so its sum of squares is
+            // zero exactly, not the rounding residue of the closed form
+            const bool last = c + 2 >= a.m;
+            const double sp2 = last ? 0.0 : sG2[i + 1] - 2.0 * wn * p1 + wn * wn * q2;
+            const double mag = last ? 0.0 : sG2[i + 1] + 2.0 * fabs(wn * p1) + wn * wn * q2;
             if (sp2 >= 0.05 * mag) {
                 const double nrm2 = sqrt(alpha2 * alpha2 + sp2);
                 if (nrm2 < eps_s) {

@@ -92,9 +92,9 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
     QrdmCtl *ctl = a.ctl;
     if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
-    const int ks = ctl->ks, l = ctl->l;
+    const int l = ctl->l;
     const int64_t t = a.m - ns;
-    const int64_t c0 = ns + ks;
+    const int64_t c0 = ns + ctl->c0off;  // k_s, or l after the Gram-matrix panel
     const int64_t w2 = a.n - c0;
     const int64_t jb = (int64_t)blockIdx.x * G1_NT;
     if (l <= 0 || jb >= w2 || t <= 0) return;
@@ -308,14 +308,15 @@ __device__ __forceinline__ void zs_apply(const double *Ys, const double *Tm, int
 // Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) per column (Z_a = 0 when tau_a = 0).
 template <typename T, int CW>
 __global__ void __launch_bounds__(G1_TH)
-k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp, T *__restrict__ Z, int64_t ldz,
-       int64_t ysplit) {
+k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ cpT, const double *__restrict__ Yp,
+       T *__restrict__ Z, int64_t ldz, int64_t ysplit) {
     QrdmCtl *ctl = a.ctl;
     if (qrdm_dm_idle(ctl)) return;
     const int64_t ns = ctl->ns;
-    const int ks = ctl->ks, l = ctl->l;
+    const int l = ctl->l;
+    const bool tgiven = ctl->cpath != 0;  // T formed by the Gram-matrix panel
     const int64_t t = a.m - ns;
-    const int64_t w2 = a.n - (ns + ks);
+    const int64_t w2 = a.n - (ns + ctl->c0off);
     const int64_t cb = (int64_t)blockIdx.x * CW;
     if (l <= 0 || cb >= w2 || t <= 0) return;
     const int krows = g1_krows(t, w2);
@@ -336,7 +337,13 @@ k_zsum(QrdmArgs a, const double *__restrict__ VV, const double *__restrict__ Yp,
     double *VVf = Ys + 64 * ZT_LD;                 // explicit T: [64][ZT_LD] v_b^T v_a (b < a)
     double *Tm = VVf + 64 * ZT_LD;                 // [64][ZT_LD]
     double *taux = Tm + 64 * ZT_LD;                // [64]
-    if (xt) {
+    if (xt && tgiven) {
+        for (int e = tid; e < 64 * ZT_LD; e += G1_TH) {
+            const int b = e / ZT_LD, aa = e - b * ZT_LD;
+            Tm[e] = (b <= aa && aa < l) ? cpT[b * 64 + aa] : 0.0;
+        }
+        __syncthreads();
+    } else if (xt) {
         for (int e = tid; e < 64 * ZT_LD; e += G1_TH) {
             const int b = e / ZT_LD, aa = e - b * ZT_LD;
             VVf[e] = (b < aa && aa < l) ? VV[b * QK_KM + aa] : 0.0;
@@ -427,7 +434,7 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
     int64_t vk0 = 0;     // mode 1: first column of V in A
     if constexpr (MODE == 0) {
         r0 = ctl->ns;
-        c0 = ctl->ns + ctl->ks;
+        c0 = ctl->ns + ctl->c0off;  // k_s, or l after the Gram-matrix panel
         l = ctl->l;
     } else {
         // QP3 block end: same predicate as the column-pivoting kernels
@@ -547,7 +554,7 @@ int64_t trail_ysplit(int kmax, int64_t n) {
 }
 int trail_splits_max() { return QK_SPLIT_MAX; }
 
-hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
+hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *cpT, const double *Vw, const float *Vw32,
                         int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, int64_t w_lo,
                         hipStream_t s, hipEvent_t *ev) {
     if (t_bound <= 0 || w_bound <= 0) return hipSuccess;
@@ -593,12 +600,12 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0) {
         hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz, ysplit);
-        if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz, ysplit);
-        else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (double *)Z, ldz, ysplit);
+        if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (double *)Z, ldz, ysplit);
+        else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (double *)Z, ldz, ysplit);
     } else {
         hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz, ysplit);
-        if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz, ysplit);
-        else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, (const double *)Yp, (float *)Z, ldz, ysplit);
+        if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (float *)Z, ldz, ysplit);
+        else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (float *)Z, ldz, ysplit);
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);

@@ -157,7 +157,7 @@ int grow_events(std::vector<hipEvent_t> &v, size_t count) {
 
 // ------------------------------------------------------------ workspace
 struct Layout {
-    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, gbar, perm_dbg, total;
+    size_t ctl, vn1, vn2, gp, g, theta, pb, tm, vw, vw32, z, yp, pb2, fz, flag, qrb, gbar, perm_dbg, cp, total;
 };
 
 const int kMinRowsPerWg = 16;  // smallest panel slab (bounds the partial buffer)
@@ -196,6 +196,7 @@ Layout make_layout(int64_t m, int64_t n, int kmax) {
     L.qrb = take(sizeof(double) * 4 * QP_RUN_MAXWG);
     L.gbar = take(2 * sizeof(uint32_t) * GBAR_GROUPS * GBAR_STRIDE);  // grid-barrier counters: panel, QP3 block kernel (2 sets)
     L.perm_dbg = take(sizeof(int32_t) * nn);
+    L.cp = take(sizeof(double) * CP_DOUBLES);  // the Gram-matrix panel's small matrices
     L.total = off;
     return L;
 }
@@ -471,6 +472,7 @@ void stats_fill(const QrdmCtl &cf, qrdm_stats *st) {
     st->nrecompute = cf.nrecompute;
     st->ncols_factored = cf.ns;
     st->npanel = cf.npanel;
+    st->ngram = cf.ngram;
     st->qp3_start = cf.fallback ? cf.qp3_start : -1;
     st->nfallback = cf.fallback ? cf.ns - cf.qp3_start : 0;
 }
@@ -515,6 +517,8 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
     double *Gp = (double *)(ws + L.gp), *G = (double *)(ws + L.g), *PB = (double *)(ws + L.pb);
     double *VVb = (double *)(ws + L.tm), *Vw = (double *)(ws + L.vw);
     float *Vw32 = (float *)(ws + L.vw32);
+    double *cp = (double *)(ws + L.cp);
+    const int kpg = (std::min(std::max(p.kmax, 1), QK_KM) + 15) & ~15;  // leading dimension of the Gram partials
     void *Z = ws + L.z;
     const int64_t ldv = m;
     const int64_t pmin = std::min(m, n);
@@ -530,6 +534,9 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
         HIP_TRY(hipEventRecord(pc.prof_ev[0], s));
     }
     const int rows_per_wg = panel_rows_for(m, std::min<int>(p.kmax, QK_KM));
+    // "0": every block on the column-by-column panel (comparison runs)
+    const char *gmode = getenv("QRDM_GRAM_PANEL");
+    const int gram = !(gmode && strcmp(gmode, "0") == 0);
     bool switch_qp3 = false, finished = false;
     int64_t ns_known = 0, nrec = 0, iter = 0;
     const int ring = pc.ring;
@@ -548,15 +555,25 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
         HIP_TRY(launch_gram(a, Gp, tb, s));
         HIP_TRY(launch_gram_reduce(a, Gp, G, tb, s));
         HIP_TRY(launch_dm_finish(a, G, nullptr, s));
+        HIP_TRY(launch_cpchol(a, G, cp, gram, s));
         HIP_TRY(launch_swap(a, s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(launch_panel(a, PB, VVb, Vw, p.precision == 1 ? Vw32 : nullptr, ldv, tb, rows_per_wg, s));
+        // the panel: from the Gram matrix when the block allows it, else (and
+        // then only) column by column
+        float *v32 = p.precision == 1 ? Vw32 : nullptr;
+        if (gram) {
+            HIP_TRY(launch_cpanel1(a, cp, Vw, ldv, Gp, kpg, tb, s));
+            HIP_TRY(launch_cpreduce(a, Gp, kpg, cp, s));
+            HIP_TRY(launch_cpanel2(a, cp, Vw, ldv, Vw, v32, s));
+            HIP_TRY(launch_cpanel3(a, cp, Vw, ldv, v32, tb, s));
+        }
+        HIP_TRY(launch_panel(a, PB, VVb, Vw, v32, ldv, tb, rows_per_wg, s));
         if (ev) HIP_TRY(hipEventRecord(ev[2], s));
         // the device is at most lag + 1 blocks of at most kmax columns ahead of
         // ns_known, and the block's own k_s <= kmax columns leave the trailing
         // part (one block more of slack; k_gemm1 flags a grid that is too small)
         const int64_t wlo = wb - (int64_t)(lag + 3) * p.kmax;
-        HIP_TRY(launch_trail(a, p.precision, VVb, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, wlo, s,
+        HIP_TRY(launch_trail(a, p.precision, VVb, cp + CP_OFF_T, Vw, Vw32, ldv, Z, (double *)(ws + L.yp), tb, wb, wlo, s,
                              ev ? ev + 3 : nullptr));
         {
             QrdmArgs al = a;

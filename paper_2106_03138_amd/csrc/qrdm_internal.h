@@ -55,7 +55,21 @@ struct QrdmCtl {
     int32_t qp_pad;
     double qp_beta, qp_den;  // scalars of the pending reflector
     int64_t qp3_start;       // first column of the column-pivoting loop
+    // the panel of the current DM step
+    int32_t cpath;           // 1 = formed from the Gram matrix (k_cpanel.hip), 0 = column by column
+    int32_t c0off;           // first column of the trailing update, from n_s: k_s, or l when cpath
+    int32_t Ai[QK_KM];       // candidate index (row of the Gram matrix) of each accepted column
+    int64_t ngram;           // panels formed from the Gram matrix
 };
+
+// Region of the workspace for the Gram-matrix panel (doubles, 64 x 64 each):
+// R1, W1 = R1^{-1}, Q1^T Q1, T, P.
+#define CP_OFF_R1 0
+#define CP_OFF_W1 4096
+#define CP_OFF_G2 8192
+#define CP_OFF_T 12288
+#define CP_OFF_P 16384
+#define CP_DOUBLES 20480
 
 struct QrdmArgs {
     double *A;
@@ -183,6 +197,18 @@ hipError_t launch_gram(QrdmArgs a, double *Gp, int64_t t_bound, hipStream_t s);
 hipError_t launch_gram_reduce(QrdmArgs a, const double *Gp, double *G, int64_t t_bound, hipStream_t s);
 hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipStream_t s);
 hipError_t launch_swap(QrdmArgs a, hipStream_t s);
+// The Gram-matrix panel (k_cpanel.hip): cp is the CP_DOUBLES region; Gp the Gram
+// partials of the DM step (free once k_dm_finish has run); kp their leading
+// dimension.
+hipError_t launch_cpchol(QrdmArgs a, const double *G, double *cp, int enable, hipStream_t s);
+hipError_t launch_cpanel1(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, double *Gp, int kp, int64_t t_bound,
+                          hipStream_t s);
+hipError_t launch_cpreduce(QrdmArgs a, const double *Gp, int kp, double *cp, hipStream_t s);
+hipError_t launch_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo, float *Vo32,
+                          hipStream_t s);
+hipError_t launch_cpanel3(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, float *Vw32, int64_t t_bound,
+                          hipStream_t s);
+int cpanel_partials(int64_t m);
 hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *Vw32, int64_t ldv,
                         int64_t t_bound, int rows_per_wg, hipStream_t s);
 // VV: v_a^T v_i (a < i) at VV[a * QK_KM + i], from the panel.
@@ -190,9 +216,10 @@ hipError_t launch_panel(QrdmArgs a, double *PB, double *VV, double *Vw, float *V
 // Yp: QK_SPLIT_MAX x QK_KM x n partials of V^T A (k_gemm1), summed by k_zsum
 // t_bound, w_bound: upper bounds on the trailing rows and columns; w_lo: a lower
 // bound on the trailing columns (sizes GEMM1's split grid)
-hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *Vw, const float *Vw32,
-                        int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound, int64_t w_lo,
-                        hipStream_t s, hipEvent_t *ev);
+// cpT: T of the Gram-matrix panel (used when ctl->cpath; k_zsum forms T from VV otherwise)
+hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const double *cpT, const double *Vw,
+                        const float *Vw32, int64_t ldv, void *Z, double *Yp, int64_t t_bound, int64_t w_bound,
+                        int64_t w_lo, hipStream_t s, hipEvent_t *ev);
 hipError_t launch_downdate(QrdmArgs a, int64_t w_bound, hipStream_t s);
 
 // QP3 (LAPACK xgeqp3-style) column loop: either one block of up to nb steps

@@ -5,7 +5,8 @@ break, the stopping test) must agree exactly up to the first block where the
 oracle records a decision margin below ETA (relative); beyond it two correct
 FP64 implementations may differ.  Floating-point results are compared
 normwise: two Householder QRs with different summation orders differ by
-O(eps ||A||).
+O(eps ||A||); the R diagonal also entrywise (relative 1e-12 where it is at
+least 1e-3 ||A||_2, above a floor of DIAG_FLOOR eps ||A||_2).
 
 The rank (the practical stopping criterion of Section 4) is compared exactly
 when the oracle took no low-margin decision.  Otherwise the GPU's rank must lie
@@ -24,6 +25,12 @@ from oracle import metrics as M
 EPS = np.finfo(np.float64).eps
 ETA = 1e-10
 NU_SCALE = 4.0  # noise of partial norms: NU_SCALE * eps * ||A||_F (the oracle's margin floor)
+# Two FP64 Householder QRs of one matrix with one column order differ on the R
+# diagonal by a few eps ||A||_2 (LAPACK's dgeqrf against a blocked Householder
+# QR, on the 8192^2 Gaussian matrix: 5 eps ||A||_2, 4.4e-13 relative on its
+# smallest entries), so the relative check of large diagonal entries has this
+# floor, in units of eps ||A||_2; the normwise bound is 10 n eps ||A||_2.
+DIAG_FLOOR = 32.0
 STOP_PAPER, STOP_MAXNORM, STOP_NONE = 0, 1, 2
 
 
@@ -97,11 +104,17 @@ def compare(a, ref, qr, tau, perm, rank, blocks, tol_scale=10.0, check_blocks=Tr
         ro = np.triu(ref.qr[:pc, :])[:, np.argsort(ref.perm)]
         dr = np.abs(rg - ro)
         assert np.max(dr) <= tol_scale * n * EPS * na, np.max(dr)
-        # R diagonal: relative where large, absolute where small
+        # R diagonal: relative 1e-12 where large, with a floor of DIAG_FLOOR eps ||A||_2
         d_g, d_o = np.abs(np.diag(qr)[:pc]), np.abs(np.diag(ref.qr)[:pc])
         big = d_o >= 1e-3 * na
         if np.any(big):
-            assert np.max(np.abs(d_g[big] - d_o[big]) / d_o[big]) <= 1e-12
+            dev = np.abs(d_g[big] - d_o[big])
+            tol = np.maximum(1e-12 * d_o[big], DIAG_FLOOR * EPS * na)
+            out["diag_rel"] = float(np.max(dev / d_o[big]))
+            out["diag_eps"] = float(np.max(dev) / (EPS * na))  # in units of eps ||A||_2
+            q = int(np.argmax(dev / tol))
+            w = int(np.flatnonzero(big)[q])
+            assert dev[q] <= tol[q], f"R diagonal {w}: {d_g[w]!r} vs {d_o[w]!r} ({dev[q] / (EPS * na):.1f} eps ||A||)"
         assert np.max(np.abs(d_g - d_o)) <= tol_scale * n * EPS * na
     # ---- sigma_min(R11) / sigma_r(A) at the numerical rank
     if sigma is not None:

@@ -174,6 +174,8 @@ def test_oracle_parity_at_full_size(run, which):
                   residual_cols=cols, check_blocks=which == "logged", norm2=_norm2(run["a"], spec),
                   stop_rule=oracle.STOP_NONE, kmax=KMAX, sigma=sig)
     cut = out["ns_cut"]
+    _say(spec, f"R diagonal against the oracle's (entries >= 1e-3 ||A||): relative {out.get('diag_rel')}, "
+               f"{out.get('diag_eps')} eps ||A||_2")
     _say(spec, f"exact prefix ns_cut = {cut} (ended by {out.get('cut_by')}); rank gpu {g['rank']} oracle "
                f"{ref.rank} band {out['rank_band']}; sigma_min(R11)/sigma_r {out.get('smin_ratio')} at n_r = "
                f"{out.get('n_r')}")
