@@ -60,116 +60,240 @@ __device__ __forceinline__ double cp_rcp(double x) {
     return fma(y, fma(-x, y, 1.0), y);
 }
 
-// ------------------------------------------------------------------ k_cpchol
-// The sequential factorizations of this file run on all four wavefronts with
-// one barrier per step: thread (wavefront w, lane c) keeps the entries (r, c)
-// for the rows r = w + 4u (u < 16) of a 64 x 64 matrix in registers, and the
-// row (or column) that a step eliminates with reaches every thread through LDS.
-#define CP_U 16
+// 1 / sqrt(x) from the hardware estimate and two Newton steps
+__device__ __forceinline__ double cp_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
 
+// ------------------------------------------------------------------ blocked helpers
+// The sequential factorizations of this file are blocked by 16 columns: the
+// dependent steps inside a 16-column panel run on one wavefront without
+// barriers (values move between lanes by readlane), the solves and updates
+// around them on FP64 MFMA over the four wavefronts, one barrier between
+// phases.
+#define CP_LD16 17  // row stride of the 16 x 16 staging blocks
+
+// acc + A B for one 16 x 16 block on one wavefront (K = 16), fa(i, k) and
+// fb(k, j) giving the operands; register v of a lane then holds row
+// 4v + lane / 16, column lane % 16.
+template <typename FA, typename FB>
+__device__ __forceinline__ dbl4 cp_mm16(FA fa, FB fb, dbl4 acc) {
+    const int lane = threadIdx.x & 63, i16 = lane & 15, k4 = lane >> 4;
+    double av[4], bv[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        av[kb] = fa(i16, 4 * kb + k4);
+        bv[kb] = fb(4 * kb + k4, i16);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = cp_mfma(av[kb], bv[kb], acc);
+    return acc;
+}
+
+// X = R^{-1} for an upper triangular R of order 64: r(i, k) gives R_ik for
+// i < k and rinv(i) = 1 / R_ii (the caller makes R the identity outside its
+// leading block).  Wavefront w inverts diagonal block w by back substitution
+// (lane c < 16 forms column c), then the blocks above the diagonal follow by
+// block diagonals on MFMA, X_ij = -X_ii sum_{i < k <= j} R_ik X_kj, one
+// barrier per diagonal.  xr(i, j) reads X (on and above the diagonal blocks
+// only), xw(i, j, v) writes it; Tmp holds four 16 x CP_LD16 blocks.  Every
+// thread of the workgroup calls it.
+template <typename RA, typename RI, typename XR, typename XW>
+__device__ __forceinline__ void cp_trinv(RA r, RI rinv, XR xr, XW xw, double *Tmp) {
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i16 = lane & 15, k4 = lane >> 4;
+    {
+        // column i16 of the block's inverse, right-looking from the bottom: x_k is
+        // final once scaled, then swept out of the rows above it
+        const int b0 = 16 * wv;
+        double x[16], rin[16];
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+            x[ii] = ii == i16 ? 1.0 : 0.0;
+            rin[ii] = rinv(b0 + ii);
+        }
+#pragma unroll
+        for (int kk = 15; kk >= 0; --kk) {
+            double rv[16];
+#pragma unroll
+            for (int ii = 0; ii < kk; ++ii) rv[ii] = r(b0 + ii, b0 + kk);
+            x[kk] *= rin[kk];
+#pragma unroll
+            for (int ii = 0; ii < kk; ++ii) x[ii] -= rv[ii] * x[kk];
+        }
+        if (lane < 16) {
+#pragma unroll
+            for (int ii = 0; ii < 16; ++ii) xw(b0 + ii, b0 + i16, x[ii]);
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int d = 1; d < 4; ++d) {
+        const int bi = wv, bj = wv + d;
+        if (bj < 4) {
+            double *M = Tmp + wv * 16 * CP_LD16;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int kb = bi + 1; kb <= bj; ++kb)
+                acc = cp_mm16([&](int i, int k) { return r(16 * bi + i, 16 * kb + k); },
+                              [&](int k, int j) { return xr(16 * kb + k, 16 * bj + j); }, acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) M[(4 * v + k4) * CP_LD16 + i16] = acc[v];
+            __builtin_amdgcn_wave_barrier();  // M is this wavefront's own: LDS keeps its order
+            acc = cp_mm16([&](int i, int k) { return xr(16 * bi + i, 16 * bi + k); },
+                          [&](int k, int j) { return M[k * CP_LD16 + j]; }, dbl4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xw(16 * bi + 4 * v + k4, 16 * bj + i16, -acc[v]);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ k_cpchol
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_cpchol(QrdmArgs a, const double *G, double *cp, int enable) {
     QrdmCtl *ctl = a.ctl;
     if (qrdm_dm_idle(ctl)) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i16 = lane & 15, k4 = lane >> 4;
     const int ks = ctl->ks, nL = ctl->nL;
     if (tid == 0) {  // the column-by-column panel unless this kernel takes the block
         ctl->cpath = 0;
         ctl->c0off = ks;
     }
     if (!enable || ks < 2 || ks > CP_K || nL > CP_K || a.kmax > CP_K) return;
-    __shared__ double Rl[CP_K * CP_LD];  // row j of S when step j takes it, then R1
-    __shared__ double Xl[CP_K * CP_LD];  // the rows of R1^{-1}
-    __shared__ double d0[CP_K], mri[CP_K], rdg[CP_K];
-    __shared__ int sAi[CP_K];
-    for (int i = tid; i < ks; i += 256) sAi[i] = ctl->Ai[i];
-    __syncthreads();
-    double s[CP_U];  // G_JJ, rows wv + 4u
-#pragma unroll
-    for (int u = 0; u < CP_U; ++u) {
-        const int r = wv + 4 * u;
-        s[u] = (r < ks && lane < ks) ? G[sAi[r] * QK_KM + sAi[lane]] : 0.0;
-        if (r == lane && r < ks) d0[r] = s[u];
+    __shared__ double S[CP_K * CP_LD];   // G_JJ, then R1 on and above the diagonal
+    __shared__ double Xl[CP_K * CP_LD];  // R1^{-1}
+    __shared__ double Tmp[4 * 16 * CP_LD16];
+    __shared__ double d0[CP_K], mri[CP_K];
+    __shared__ int sAi[CP_K], mfl[2];
+    for (int i = tid; i < CP_K; i += 256) {
+        if (i < ks) sAi[i] = ctl->Ai[i];
+        mri[i] = 0.0;
     }
-    const double eps2 = ctl->eps_s * ctl->eps_s;
-    // right-looking Cholesky G_JJ = R1^T R1 on the rows of S as they are
-    // eliminated: step j takes d = S_jj and S_rc -= S_jr S_jc / d for r > j, and
-    // R1_j. = S_j. / sqrt(d) is formed afterwards.  The break of eq.
-    // (lenght_check): sqrt(d) < eps_s for j >= 1 (the norm of column j after j
-    // reflectors); sqrt(d) below CP_SAFE of the column's norm leaves the block to
-    // the column-by-column panel.  Every thread takes the same decisions from
-    // the same d.
-    int l = ks, flag = 0;
     __syncthreads();
+    {  // G_JJ, zero outside k_s x k_s; every load of a thread before its stores
+        double v[16];
 #pragma unroll
-    for (int j = 0; j < CP_K; ++j) {
-        if (j < l) {  // uniform: l drops to j at a break
-            if (wv == (j & 3)) Rl[j * CP_LD + lane] = s[j >> 2];
-            __syncthreads();
-            const double d = Rl[j * CP_LD + j], sjc = Rl[j * CP_LD + lane];
-            double sjr[CP_U];
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, i = e >> 6, c = e & 63;
+            v[u] = (i < ks && c < ks) ? G[sAi[i] * QK_KM + sAi[c]] : 0.0;
+        }
 #pragma unroll
-            for (int u = 0; u < CP_U; ++u) sjr[u] = Rl[j * CP_LD + wv + 4 * u];
-            if (j >= 1 && !(d >= eps2)) flag = 1;
-            else if (!(d > 0.0) || !(d >= CP_SAFE * CP_SAFE * d0[j])) flag = 2;
-            if (flag) {
-                l = j;
-            } else {
-                // rows r <= j are finished (row j is in Rl): updating them too
-                // keeps the step free of branches
-                const double t = sjc * cp_rcp(d);
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, i = e >> 6, c = e & 63;
+            S[i * CP_LD + c] = v[u];
+            if (i == c) d0[i] = v[u];
+        }
+    }
+    __syncthreads();
+    const double eps2 = ctl->eps_s * ctl->eps_s;
+    // Cholesky G_JJ = R1^T R1, right-looking by 16-column panels.  Step j takes
+    // d = S_jj, R1_j. = S_j. / sqrt(d) and S_ic -= R1_ji R1_jc (i, c > j).  The
+    // break of eq. (lenght_check): sqrt(d) < eps_s for j >= 1 (the norm of
+    // column j after j reflectors), l = j; sqrt(d) below CP_SAFE of the
+    // column's norm leaves the block to the column-by-column panel.
+    int l = ks, flag = 0;
+#pragma unroll 1
+    for (int kb = 0; kb < 4; ++kb) {
+        const int j0 = 16 * kb;
+        if (j0 >= l) break;
+        // (a) the diagonal block on wavefront 0, lane i16 holding row j0 + i16.
+        // Row j keeps S_j. as it stood when it was eliminated, and is scaled to
+        // R1_j. once the block is done; the rows below take S_ic -= (S_ij / d) S_jc.
+        if (wv == 0) {
+            double g[16], d0b[16];
 #pragma unroll
-                for (int uu = 0; uu < CP_U; ++uu) {
-                    const int u = (uu + ((j + 1) >> 2)) & (CP_U - 1);  // the next pivot row first
-                    s[u] -= sjr[u] * t;
+            for (int c = 0; c < 16; ++c) g[c] = S[(j0 + i16) * CP_LD + j0 + c];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) d0b[jj] = d0[j0 + jj];
+            int f = 0, lb = l;
+            double myd = 1.0;  // the pivot d of this lane's row
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int j = j0 + jj;
+                if (j < ks) {
+                    const double d = cp_readlane(g[jj], jj);
+                    const int fj = (j >= 1 && !(d >= eps2)) ? 1
+                                 : ((!(d > 0.0) || !(d >= CP_SAFE * CP_SAFE * d0b[jj])) ? 2 : 0);
+                    const bool first = f == 0 && fj != 0;  // the first failing column decides
+                    lb = first ? j : lb;
+                    f = first ? fj : f;
+                    const double al = i16 > jj ? g[jj] * cp_rcp(d) : 0.0;
+#pragma unroll
+                    for (int c = jj + 1; c < 16; ++c) g[c] -= al * cp_readlane(g[c], jj);
+                    myd = i16 == jj ? d : myd;
                 }
             }
-        }
-    }
-    if (flag == 2) return;
-    if (tid < l) {
-        const double r = sqrt(Rl[tid * CP_LD + tid]);
-        mri[tid] = 1.0 / r;
-        rdg[tid] = r;
-    }
-    __syncthreads();
+            const double ri = cp_rsqrt(myd);
+            if (lane < 16) {
 #pragma unroll
-    for (int u = 0; u < CP_U; ++u) {
-        const int i = wv + 4 * u;
-        if (i < l) {
-            const double v = Rl[i * CP_LD + lane];
-            Rl[i * CP_LD + lane] = lane == i ? rdg[i] : ((lane > i && lane < ks) ? v * mri[i] : 0.0);
-        }
-    }
-    // W1 = R1^{-1} by rows from the bottom: row i = (e_i - sum_{k > i} R1_ik W1_k.) / r_ii,
-    // each finished row swept out of the rows above it
-    double x[CP_U];
-#pragma unroll
-    for (int u = 0; u < CP_U; ++u) x[u] = (wv + 4 * u == lane && lane < l) ? 1.0 : 0.0;
-#pragma unroll
-    for (int i = CP_K - 1; i >= 0; --i) {
-        if (i < l) {
-            if (wv == (i & 3)) Xl[i * CP_LD + lane] = lane < l ? x[i >> 2] * mri[i] : 0.0;
-            __syncthreads();
-            const double xic = Xl[i * CP_LD + lane];
-            double rri[CP_U];
-#pragma unroll
-            for (int u = 0; u < CP_U; ++u) rri[u] = Rl[(wv + 4 * u) * CP_LD + i];
-#pragma unroll
-            for (int uu = 0; uu < CP_U; ++uu) {  // rows >= i are finished; row i - 1 first
-                const int u = (uu + ((i + 63) >> 2)) & (CP_U - 1);
-                x[u] -= rri[u] * xic;
+                for (int c = 0; c < 16; ++c)
+                    S[(j0 + i16) * CP_LD + j0 + c] = c > i16 ? g[c] * ri : (c == i16 ? myd * ri : 0.0);
+                mri[j0 + i16] = ri;
+            }
+            if (lane == 0) {
+                mfl[0] = f;
+                mfl[1] = lb;
             }
         }
+        __syncthreads();
+        flag = mfl[0];
+        l = mfl[1];
+        if (flag) break;
+        // (b) rows j0 .. j0+15 of R1 right of the block: R1_12 = R1_11^{-T} S_12,
+        // lane c - j0 - 16 of wavefront 0 forming column c
+        if (wv == 0) {
+            const int c = j0 + 16 + lane;
+            if (c < ks) {
+                double x[16];
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) x[ii] = S[(j0 + ii) * CP_LD + c];
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) {
+                    double rv[16];
+#pragma unroll
+                    for (int jj = 0; jj < ii; ++jj) rv[jj] = S[(j0 + jj) * CP_LD + j0 + ii];
+                    double sum = x[ii];
+#pragma unroll
+                    for (int jj = 0; jj < ii; ++jj) sum -= rv[jj] * x[jj];
+                    x[ii] = sum * mri[j0 + ii];
+                }
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) S[(j0 + ii) * CP_LD + c] = x[ii];
+            }
+        }
+        __syncthreads();
+        // (c) the trailing Gram block: S_22 -= R1_12^T R1_12 on MFMA
+        {
+            const int nt = 3 - kb;
+            for (int tile = wv; tile < nt * nt; tile += 4) {
+                const int rt = kb + 1 + tile / nt, ct = kb + 1 + tile % nt;
+                const dbl4 acc = cp_mm16([&](int i, int k) { return S[(j0 + k) * CP_LD + 16 * rt + i]; },
+                                         [&](int k, int j) { return S[(j0 + k) * CP_LD + 16 * ct + j]; },
+                                         dbl4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S[(16 * rt + 4 * v + k4) * CP_LD + 16 * ct + i16] -= acc[v];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    if (flag == 2) return;
+    // W1 = R1^{-1} (l x l; the identity past l)
+    // (the accessors load first and select after: their addresses are always in range)
+    cp_trinv([&](int i, int k) { const double v = S[i * CP_LD + k]; return k < l ? v : 0.0; },
+             [&](int i) { const double v = mri[i]; return i < l ? v : 1.0; },
+             [&](int i, int j) { return Xl[i * CP_LD + j]; },
+             [&](int i, int j, double v) { Xl[i * CP_LD + j] = v; }, Tmp);
     {
         double *R1 = cp + CP_OFF_R1, *W1 = cp + CP_OFF_W1;
 #pragma unroll
-        for (int u = 0; u < CP_U; ++u) {
+        for (int u = 0; u < 16; ++u) {
             const int e = tid + 256 * u, i = e >> 6, c = e & 63;
             const bool in = i <= c && c < l;
-            R1[e] = in ? Rl[i * CP_LD + c] : 0.0;
+            R1[e] = in ? S[i * CP_LD + c] : 0.0;
             W1[e] = in ? Xl[i * CP_LD + c] : 0.0;
         }
     }
@@ -305,26 +429,36 @@ hipError_t launch_cpreduce(QrdmArgs a, const double *Gp, int kp, double *cp, hip
 }
 
 // ------------------------------------------------------------------ k_cpanel2
-// C = A B for 64 x 64 operands on FP64 MFMA by the four wavefronts (sixteen
-// 16 x 16 output tiles, four per wavefront): fa(i, k) and fb(k, j) give the
-// operands (zero outside the block), out(i, j, v) takes each result.  A tile's
-// operands are all loaded before its MFMAs.
-template <typename FA, typename FB, typename OUT>
+// C = A B for 64 x 64 operands on FP64 MFMA by the four wavefronts, fa(i, k)
+// and fb(k, j) giving the operands, out(i, j, v) taking each result.  Only the
+// products the triangular shapes leave are formed: MODE 1 (B upper
+// triangular): every 16 x 16 tile, tile (rt, ct) summing the k-tiles up to ct,
+// row tile rt on wavefront rt; MODE 2 (A and B upper triangular): the ten
+// tiles on and above the diagonal, k-tiles rt .. ct, five k-tiles per
+// wavefront.  A tile's operands for one k-tile are loaded before its MFMAs.
+template <int MODE, typename FA, typename FB, typename OUT>
 __device__ __forceinline__ void cp_mm(FA fa, FB fb, OUT out) {
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, k4 = lane >> 4;
+    // MODE 2: the tiles (4 rt + ct, plus one; 0 = none) of each wavefront, five bits each
+    const uint32_t pk = wv == 0 ? (4u | 1u << 5) : wv == 1 ? (3u | 2u << 5) : wv == 2 ? (8u | 7u << 5)
+                                                                                : (12u | 6u << 5 | 11u << 10 | 16u << 15);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int tile = wv + 4 * u, rt = tile >> 2, ct = tile & 3;
-        double av[16], bv[16];
-#pragma unroll
-        for (int kb = 0; kb < 16; ++kb) {
-            av[kb] = fa(rt * 16 + i16, 4 * kb + k4);
-            bv[kb] = fb(4 * kb + k4, ct * 16 + i16);
-        }
+        const int t = MODE == 1 ? 4 * wv + u : (int)((pk >> (5 * u)) & 31u) - 1;
+        if (t < 0) break;
+        const int rt = t >> 2, ct = t & 3, k0 = MODE == 2 ? rt : 0;
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int kt = k0; kt <= ct; ++kt) {
+            double av[4], bv[4];
 #pragma unroll
-        for (int kb = 0; kb < 16; ++kb) acc = cp_mfma(av[kb], bv[kb], acc);
+            for (int kb = 0; kb < 4; ++kb) {
+                av[kb] = fa(rt * 16 + i16, kt * 16 + 4 * kb + k4);
+                bv[kb] = fb(kt * 16 + 4 * kb + k4, ct * 16 + i16);
+            }
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc = cp_mfma(av[kb], bv[kb], acc);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) out(rt * 16 + 4 * v + k4, ct * 16 + i16, acc[v]);
     }
@@ -343,9 +477,10 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
     // dq on it, Y above)
     extern __shared__ double cp_lds[];
     double *A1 = cp_lds, *A2 = A1 + CP_K * CP_LD, *A3 = A2 + CP_K * CP_LD, *A4 = A3 + CP_K * CP_LD;
+    double *Tmp = A4 + CP_K * CP_LD;  // four 16 x CP_LD16 blocks for the triangular inverses
+    const int i16 = lane & 15, k4 = lane >> 4;
     __shared__ double sS[CP_K], sUd[CP_K], sUi[CP_K], s_red[4];
     double *Tg = cp + CP_OFF_T, *Pg = cp + CP_OFF_P;
-    for (int e = tid; e < 4 * CP_K * CP_LD; e += 256) cp_lds[e] = 0.0;
     for (int e = tid; e < CP_K * CP_K; e += 256) {
         Tg[e] = 0.0;
         Pg[e] = 0.0;
@@ -362,16 +497,15 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
             r1[u] = (i <= c && c < l) ? cp[CP_OFF_R1 + e] : 0.0;
             q[u] = (c < l && i < l) ? Vw[(int64_t)i * ldv + c] : 0.0;  // row c, column i of Q1
         }
+        // every entry of A1, A2 and A3 is written (zero outside the block)
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int e = tid + 256 * u, i = e >> 6, c = e & 63;
-            if (i < l && c < l) {
-                const double v = g[u] - (i == c ? 1.0 : 0.0);
-                emax = fmax(emax, fabs(v));
-                if (i <= c) A2[i * CP_LD + c] = (i == c) ? 0.5 * v : v;
-                A3[c * CP_LD + i] = q[u];
-            }
-            if (i <= c && c < l) A1[i * CP_LD + c] = r1[u];
+            const double v = (i < l && c < l) ? g[u] - (i == c ? 1.0 : 0.0) : 0.0;
+            emax = fmax(emax, fabs(v));
+            A2[i * CP_LD + c] = i < c ? v : (i == c ? 0.5 * v : 0.0);
+            A3[c * CP_LD + i] = q[u];
+            A1[i * CP_LD + c] = r1[u];
         }
     }
     for (int o = 32; o > 0; o >>= 1) emax = fmax(emax, __shfl_xor(emax, o, 64));
@@ -386,49 +520,83 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
         return;
     }
     // ---- Q_top = Q1_top (I - N) (R2^{-1} to first order) into A4; R = (I + N) R1 into A3
-    cp_mm([&](int i, int k) { return A3[i * CP_LD + k]; }, [&](int k, int j) { return A2[k * CP_LD + j]; },
+    cp_mm<1>([&](int i, int k) { return A3[i * CP_LD + k]; }, [&](int k, int j) { return A2[k * CP_LD + j]; },
           [&](int i, int j, double v) { A4[i * CP_LD + j] = A3[i * CP_LD + j] - v; });
     __syncthreads();
-    cp_mm([&](int i, int k) { return A2[i * CP_LD + k]; }, [&](int k, int j) { return A1[k * CP_LD + j]; },
-          [&](int i, int j, double v) { A3[i * CP_LD + j] = (i <= j) ? A1[i * CP_LD + j] + v : 0.0; });
+    cp_mm<2>([&](int i, int k) { return A2[i * CP_LD + k]; }, [&](int k, int j) { return A1[k * CP_LD + j]; },
+          [&](int i, int j, double v) {
+              const double r1 = A1[i * CP_LD + j];
+              A3[i * CP_LD + j] = (i <= j) ? r1 + v : 0.0;
+          });
     __syncthreads();
-    // ---- LU of I - Q_top S, signs chosen on the way: pivot j is 1 + |dq_j| with
-    // dq_j = W_jj after j steps, L_rj = -S_j W_rj / U_jj, and W_rc -= L_rj W_jc for
-    // r, c > j.  Thread (wavefront w, lane c) holds W_rc for the rows r = w + 4u;
-    // row j, final at step j, goes to A4 (which ends as L below the diagonal, dq
-    // on it, Y above) and the entries W_rj of a wavefront's rows come from its
-    // lane j.
-    {
-        double w[CP_U];
-#pragma unroll
-        for (int u = 0; u < CP_U; ++u) w[u] = A4[(wv + 4 * u) * CP_LD + lane];
-        __syncthreads();  // Q_top read everywhere before its rows are replaced
-        // a loop at run time (the register holding row j is picked by a select)
+    // ---- LU of I - Q_top S, the signs chosen on the way, in W = Q_top: pivot j
+    // is U_jj = 1 + |dq_j| with dq_j = W_jj after j steps and S_j = -sign(dq_j),
+    // L_rj = -S_j W_rj / U_jj, W_rc -= L_rj W_jc (r, c > j).  Blocked by 16:
+    // (a) the panel on wavefront 0, lane r holding W_r,panel; (b) the panel's
+    // rows right of it, by forward substitution with the unit L_11; (c) the
+    // trailing block, W_22 -= L_21 W_12, on MFMA.  A4 ends as L below the
+    // diagonal, dq on it and W (the Y of U_rc = -S_c Y_rc) above.
 #pragma unroll 1
-        for (int j = 0; j < l; ++j) {
-            if (wv == (j & 3)) {
-                const int uj = j >> 2;
-                double wr = w[0];
+    for (int kb = 0; kb < 4; ++kb) {
+        const int j0 = 16 * kb;
+        if (j0 >= l) break;
+        if (wv == 0) {
+            double p[16];
 #pragma unroll
-                for (int u = 1; u < CP_U; ++u) wr = u == uj ? w[u] : wr;
-                A4[j * CP_LD + lane] = wr;
+            for (int c = 0; c < 16; ++c) p[c] = A4[lane * CP_LD + j0 + c];
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const int j = j0 + jj;
+                if (j < l) {
+                    const double dq = cp_readlane(p[jj], j);
+                    const double sj = dq >= 0.0 ? -1.0 : 1.0;
+                    const double f = -sj * cp_rcp(1.0 - sj * dq);
+                    const double m = lane > j ? f * p[jj] : 0.0;  // zero on the finished rows
+#pragma unroll
+                    for (int c = jj + 1; c < 16; ++c) p[c] -= m * cp_readlane(p[c], j);
+                    p[jj] = lane > j ? m : p[jj];
+                }
             }
-            __syncthreads();
-            const double dq = A4[j * CP_LD + j];
-            const double sj = dq >= 0.0 ? -1.0 : 1.0;
-            const double ujj = 1.0 - sj * dq;
-            const double f = -sj * cp_rcp(ujj);
-            const double wjc = lane > j ? A4[j * CP_LD + lane] : 0.0;
-            // rows r <= j are finished (row j is in A4): updating them too keeps
-            // the sixteen updates free of branches, so that they overlap
+            if (lane >= j0) {
 #pragma unroll
-            for (int u = 0; u < CP_U; ++u) {
-                const double m = f * cp_readlane(w[u], j);
-                w[u] = lane == j ? m : w[u] - m * wjc;
+                for (int c = 0; c < 16; ++c) A4[lane * CP_LD + j0 + c] = p[c];
             }
         }
+        __syncthreads();
+        if (wv == 0) {
+            const int c = j0 + 16 + lane;
+            if (c < CP_K) {
+                double x[16];
+#pragma unroll
+                for (int ii = 0; ii < 16; ++ii) x[ii] = A4[(j0 + ii) * CP_LD + c];
+#pragma unroll
+                for (int ii = 1; ii < 16; ++ii) {
+                    double lv[16];
+#pragma unroll
+                    for (int jj = 0; jj < ii; ++jj) lv[jj] = A4[(j0 + ii) * CP_LD + j0 + jj];
+                    double sum = x[ii];
+#pragma unroll
+                    for (int jj = 0; jj < ii; ++jj) sum -= lv[jj] * x[jj];
+                    x[ii] = sum;
+                }
+#pragma unroll
+                for (int ii = 1; ii < 16; ++ii) A4[(j0 + ii) * CP_LD + c] = x[ii];
+            }
+        }
+        __syncthreads();
+        {
+            const int nt = 3 - kb;
+            for (int tile = wv; tile < nt * nt; tile += 4) {
+                const int rt = kb + 1 + tile / nt, ct = kb + 1 + tile % nt;
+                const dbl4 acc = cp_mm16([&](int i, int k) { return A4[(16 * rt + i) * CP_LD + j0 + k]; },
+                                         [&](int k, int j) { return A4[(j0 + k) * CP_LD + 16 * ct + j]; },
+                                         dbl4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A4[(16 * rt + 4 * v + k4) * CP_LD + 16 * ct + i16] -= acc[v];
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (tid < l) {  // the signs and pivots, from dq on the diagonal of the LU
         const double dq = A4[tid * CP_LD + tid];
         const double sj = dq >= 0.0 ? -1.0 : 1.0;
@@ -438,54 +606,21 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
         sUi[tid] = 1.0 / ujj;
     }
     __syncthreads();
-    // ---- Linv = L^{-1} into A2 below the diagonal and Uinv = U^{-1} into A1 (upper;
-    // U_ik = -S_k Y_ik, U_ii = 1 + |dq_i|), in one sweep: step s finishes row
-    // k = s of Linv (forward) and row i = l - 1 - s of Uinv (backward) and
-    // sweeps each out of the rows that remain.
-    {
-        double xl[CP_U], xu[CP_U];
-#pragma unroll
-        for (int u = 0; u < CP_U; ++u) {
-            const int r = wv + 4 * u;
-            xl[u] = (r == lane && r < l) ? 1.0 : 0.0;
-            xu[u] = xl[u];
-        }
-#pragma unroll 1
-        for (int st = 0; st < l; ++st) {
-            const int k = st, i = l - 1 - st;  // the rows finished at this step
-            if (wv == (k & 3)) {
-                double xk = 0.0;
-#pragma unroll
-                for (int u = 0; u < CP_U; ++u) xk = wv + 4 * u == k ? xl[u] : xk;
-                if (lane < k) A2[k * CP_LD + lane] = xk;
-            }
-            if (wv == (i & 3)) {
-                double xi = 0.0;
-#pragma unroll
-                for (int u = 0; u < CP_U; ++u) xi = wv + 4 * u == i ? xu[u] : xi;
-                A1[i * CP_LD + lane] = lane >= i && lane < l ? xi * sUi[i] : 0.0;
-            }
-            __syncthreads();
-            const double xkc = lane < k ? A2[k * CP_LD + lane] : (lane == k ? 1.0 : 0.0);
-            const double xic = A1[i * CP_LD + lane];
-            const double nsi = -sS[i];
-            const double *a4k = A4 + wv * CP_LD + k, *a4i = A4 + wv * CP_LD + i;
-            double lk[CP_U], ui[CP_U];  // every load of the step before its updates
-#pragma unroll
-            for (int u = 0; u < CP_U; ++u) {
-                lk[u] = a4k[4 * u * CP_LD];
-                ui[u] = a4i[4 * u * CP_LD];
-            }
-            // rows <= k of Linv, >= i of Uinv, and >= l are finished or unused:
-            // updating them too keeps the step free of branches
-#pragma unroll
-            for (int u = 0; u < CP_U; ++u) {
-                xl[u] -= lk[u] * xkc;
-                xu[u] -= (nsi * ui[u]) * xic;
-            }
-        }
-    }
-    __syncthreads();
+    // ---- Uinv = U^{-1} into A1 (U_ik = -S_k Y_ik, U_ii = 1 + |dq_i|; A1's R1 is no
+    // longer needed) and Linv = L^{-1} into A2 below the diagonal, as the
+    // inverse of the unit upper L^T (A2 keeps N above)
+    // (the accessors load first and select after: their addresses are always in range)
+    cp_trinv([&](int i, int k) { const double y = A4[i * CP_LD + k], sk = sS[k]; return k < l ? -sk * y : 0.0; },
+             [&](int i) { const double v = sUi[i]; return i < l ? v : 1.0; },
+             [&](int i, int j) { return A1[i * CP_LD + j]; },
+             [&](int i, int j, double v) { A1[i * CP_LD + j] = v; }, Tmp);
+    cp_trinv([&](int i, int k) { const double v = A4[k * CP_LD + i]; return k < l ? v : 0.0; },
+             [&](int) { return 1.0; },
+             [&](int i, int j) { const double v = A2[j * CP_LD + i]; return i < j ? v : (i == j ? 1.0 : 0.0); },
+             [&](int i, int j, double v) {
+                 if (i < j) A2[j * CP_LD + i] = v;
+             },
+             Tmp);
     // ---- T = U Linv^T and P = -(I - N) S Uinv.  A block that reaches the last
     // row (t = l) ends with a column of one row: larfg leaves it alone (tau = 0,
     // beta = alpha), where the reconstruction reflects it (tau = 2, v = e); its
@@ -495,7 +630,7 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
         const double y = A4[i * CP_LD + k], sk = sS[k], ud = sUd[i];  // loads first, then selects
         return (i >= l || k >= l || k < i) ? 0.0 : (k == i ? ud : -sk * y);
     };
-    cp_mm(uval,
+    cp_mm<2>(uval,
           [&](int k, int j) {
               const double v = A2[j * CP_LD + k];
               return (j >= l || k >= l) ? 0.0 : (j == k ? 1.0 : (j > k ? v : 0.0));
@@ -503,7 +638,7 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
           [&](int i, int j, double v) {
               if (i < l && j < l && !(lastrow && j == l - 1)) Tg[i * CP_K + j] = v;
           });
-    cp_mm(
+    cp_mm<2>(
           [&](int i, int k) {
               const double n = A2[i * CP_LD + k], sk = sS[k];
               return (i >= l || k >= l || k < i) ? 0.0 : (k == i ? -(1.0 - n) * sk : n * sk);
@@ -513,13 +648,17 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
               if (i < l && j < l) Pg[i * CP_K + j] = v;
           });
     // ---- the top block of A (R_H = S R above, L below), V_top, tau
-    for (int e = tid; e < l * l; e += 256) {
-        const int i = e / l, c = e - i * l;
-        const double flip = (lastrow && i == l - 1) ? -1.0 : 1.0;
-        a.A[(ns + c) * a.lda + ns + i] = (i <= c) ? flip * sS[i] * A3[i * CP_LD + c] : A4[i * CP_LD + c];
-        const double v = (i > c) ? A4[i * CP_LD + c] : (i == c ? 1.0 : 0.0);
-        Vo[(int64_t)c * ldv + i] = v;
-        if (Vo32) Vo32[(int64_t)c * ldv + i] = (float)v;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {  // row i of column c, i fastest: each column's rows are contiguous
+        const int e = tid + 256 * u, c = e >> 6, i = e & 63;
+        const double r = A3[i * CP_LD + c], lw = A4[i * CP_LD + c], si = sS[i];
+        if (i < l && c < l) {
+            const double flip = (lastrow && i == l - 1) ? -1.0 : 1.0;
+            a.A[(ns + c) * a.lda + ns + i] = (i <= c) ? flip * si * r : lw;
+            const double v = (i > c) ? lw : (i == c ? 1.0 : 0.0);
+            Vo[(int64_t)c * ldv + i] = v;
+            if (Vo32) Vo32[(int64_t)c * ldv + i] = (float)v;
+        }
     }
     if (tid < l) a.tau_house[ns + tid] = (lastrow && tid == l - 1) ? 0.0 : sUd[tid];  // T_ii = U_ii
     if (tid == 0) {
@@ -537,7 +676,7 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
 
 hipError_t launch_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo, float *Vo32,
                           hipStream_t s) {
-    const unsigned lds = 4 * CP_K * CP_LD * sizeof(double);
+    const unsigned lds = (4 * CP_K * CP_LD + 4 * 16 * CP_LD16) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_cpanel2, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
