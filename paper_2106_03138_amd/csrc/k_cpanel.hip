@@ -35,7 +35,7 @@
 
 #define CP_K 64          // largest block of the Gram route
 #define CP_LD 65         // LDS row stride (doubles)
-#define CP_ROWS 128      // rows per workgroup of the slab kernels
+#define CP_SR 64         // rows per workgroup of the slab kernels
 #define CP_SAFE 1e-4     // r_ii / ||c_i|| below this: the column-by-column panel
 #define CP_EMAX 1e-9     // max |Q1^T Q1 - I| above this: the column-by-column panel
 
@@ -308,86 +308,107 @@ hipError_t launch_cpchol(QrdmArgs a, const double *G, double *cp, int enable, hi
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ slab kernels
+// A slab of CP_SR rows (row stride CP_LD in LDS) times an upper triangular
+// 64 x 64 matrix on MFMA: row tile w of the slab on wavefront w, output tile
+// ct summing the k-tiles up to ct (the rest of the product is zero); the four
+// tiles' accumulations are independent.  acc[ct] returns tile (w, ct).
+__device__ __forceinline__ void cp_slab_upper(const double *Xs, const double *Us, dbl4 acc[4]) {
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i16 = lane & 15, k4 = lane >> 4;
+    double av[16], bv[4][16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) av[kk] = Xs[(16 * wv + i16) * CP_LD + 4 * kk + k4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+        for (int kk = 0; kk < 4 * (ct + 1); ++kk) bv[ct][kk] = Us[(4 * kk + k4) * CP_LD + 16 * ct + i16];
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+            if (kk < 4 * (ct + 1)) acc[ct] = cp_mfma(av[kk], bv[ct][kk], acc[ct]);
+    }
+}
+
 // ------------------------------------------------------------------ k_cpanel1
-// Slab s: rows [128 s, 128 s + 128) of the block (from row n_s); Q1 = C W1
-// (32 output tiles of 16 x 16, eight per wavefront) and the slab's Q1^T Q1
-// (16 tiles, four per wavefront) to Gp[s] (leading dimension kp).
-__global__ void __launch_bounds__(256) k_cpanel1(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, double *Gp,
-                                                 int kp) {
+// Slab s: rows [64 s, 64 s + 64) of the block (from row n_s): Q1 = C W1 into
+// the V staging buffer, and the slab's Q1^T Q1 to Gp[s] (leading dimension
+// kp): its ten tiles on and above the diagonal, each off-diagonal one also
+// stored transposed, so the partial is the full symmetric matrix.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_cpanel1(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, double *Gp, int kp) {
     const QrdmCtl *ctl = a.ctl;
     if (qrdm_dm_idle(ctl) || !ctl->cpath) return;
     const int64_t ns = ctl->ns, t = a.m - ns;
     const int l = ctl->l;
-    const int64_t r0 = (int64_t)blockIdx.x * CP_ROWS;
+    const int64_t r0 = (int64_t)blockIdx.x * CP_SR;
     if (r0 >= t) return;
-    const int nr = (int)(t - r0 < CP_ROWS ? t - r0 : CP_ROWS);
-    __shared__ double Cs[CP_ROWS * CP_LD];
+    const int nr = (int)(t - r0 < CP_SR ? t - r0 : CP_SR);
+    __shared__ double Cs[CP_SR * CP_LD];
     __shared__ double Ws[CP_K * CP_LD];
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lt = (l + 15) >> 4, lp = 16 * lt;
-    {  // the slab (column-major walk: coalesced rows) and W1, all loads before the stores
-        double v[32], w[16];
+    const int i16 = lane & 15, k4 = lane >> 4;
+    {  // the slab (column by column: coalesced rows) and W1, all loads before the stores
+        double v[16], w[16];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, c = e >> 6, r = e & 63;
             v[u] = (c < l && r < nr) ? a.A[(ns + c) * a.lda + ns + r0 + r] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) w[u] = cp[CP_OFF_W1 + tid + 256 * u];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
-            Cs[r * CP_LD + c] = v[u];
+            w[u] = cp[CP_OFF_W1 + e];
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            Ws[(e >> 6) * CP_LD + (e & 63)] = w[u];
+            const int e = tid + 256 * u, c = e >> 6, r = e & 63;
+            Cs[r * CP_LD + c] = v[u];
+            Ws[c * CP_LD + r] = w[u];  // W1 row c, column r (W1 is stored by rows)
         }
     }
     __syncthreads();
-    const int i16 = lane & 15, k4 = lane >> 4;
-    dbl4 acc[8];
-    const int ntile = 8 * lt;  // 8 row tiles x lt column tiles
+    dbl4 acc[4];
+    cp_slab_upper(Cs, Ws, acc);
+    __syncthreads();  // every MFMA has read Cs: it now takes Q1
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int tile = wv + 4 * u;
-        acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-        if (tile < ntile) {
-            const int rt = tile / lt, ct = tile - rt * lt;
-            for (int kb = 0; kb < lp; kb += 4)
-                acc[u] = cp_mfma(Cs[(rt * 16 + i16) * CP_LD + kb + k4], Ws[(kb + k4) * CP_LD + ct * 16 + i16], acc[u]);
-        }
-    }
-    __syncthreads();  // every MFMA has read Cs: it now holds Q1
+    for (int ct = 0; ct < 4; ++ct) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int tile = wv + 4 * u;
-        if (tile < ntile) {
-            const int rt = tile / lt, ct = tile - rt * lt;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Cs[(rt * 16 + 4 * v + k4) * CP_LD + ct * 16 + i16] = acc[u][v];
-        }
+        for (int v = 0; v < 4; ++v) Cs[(16 * wv + 4 * v + k4) * CP_LD + 16 * ct + i16] = acc[ct][v];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int u = 0; u < 32; ++u) {
-        const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
-        if (c < l && r < nr) Vw[(int64_t)c * ldv + r0 + r] = Cs[r * CP_LD + c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, c = e >> 6, r = e & 63;
+        const double q = Cs[r * CP_LD + c];
+        if (c < l && r < nr) Vw[(int64_t)c * ldv + r0 + r] = q;
     }
-    // the slab's Q1^T Q1 (rows past nr are zero)
+    // the slab's Q1^T Q1 (rows past nr are zero): tile d-th diagonal order,
+    // wavefront w taking tiles w, w + 4, w + 8 of (0,0) (1,1) (2,2) (3,3) (0,1)
+    // (1,2) (2,3) (0,2) (1,3) (0,3)
     double *out = Gp + (int64_t)blockIdx.x * kp * kp;
-    const int gt = lt * lt;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int tile = wv + 4 * u;
-        if (tile < gt) {
-            const int ti = tile / lt, tj = tile - ti * lt;
+    for (int u = 0; u < 3; ++u) {
+        const int idx = wv + 4 * u;
+        if (idx < 10) {
+            const int d = idx < 4 ? 0 : (idx < 7 ? 1 : (idx < 9 ? 2 : 3));
+            const int ti = idx - (d == 0 ? 0 : (d == 1 ? 4 : (d == 2 ? 7 : 9))), tj = ti + d;
+            double av[16], bv[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                av[kk] = Cs[(4 * kk + k4) * CP_LD + 16 * ti + i16];
+                bv[kk] = Cs[(4 * kk + k4) * CP_LD + 16 * tj + i16];
+            }
             dbl4 g = {0.0, 0.0, 0.0, 0.0};
-            for (int kb = 0; kb < CP_ROWS; kb += 4)
-                g = cp_mfma(Cs[(kb + k4) * CP_LD + ti * 16 + i16], Cs[(kb + k4) * CP_LD + tj * 16 + i16], g);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) out[(ti * 16 + 4 * v + k4) * kp + tj * 16 + i16] = g[v];
+            for (int kk = 0; kk < 16; ++kk) g = cp_mfma(av[kk], bv[kk], g);
+            if (16 * tj < kp) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    out[(16 * ti + 4 * v + k4) * kp + 16 * tj + i16] = g[v];
+                    if (d) out[(16 * tj + i16) * kp + 16 * ti + 4 * v + k4] = g[v];
+                }
+            }
         }
     }
 }
@@ -395,12 +416,12 @@ __global__ void __launch_bounds__(256) k_cpanel1(QrdmArgs a, const double *cp, d
 hipError_t launch_cpanel1(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, double *Gp, int kp, int64_t t_bound,
                           hipStream_t s) {
     if (t_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cpanel1, dim3((unsigned)((t_bound + CP_ROWS - 1) / CP_ROWS)), dim3(256), 0, s, a, cp, Vw,
-                       ldv, Gp, kp);
+    hipLaunchKernelGGL(k_cpanel1, dim3((unsigned)((t_bound + CP_SR - 1) / CP_SR)), dim3(256), 0, s, a, cp, Vw, ldv,
+                       Gp, kp);
     return hipGetLastError();
 }
 
-int cpanel_partials(int64_t m) { return (int)((m + CP_ROWS - 1) / CP_ROWS); }
+int cpanel_partials(int64_t m) { return (int)((m + CP_SR - 1) / CP_SR); }
 
 // ------------------------------------------------------------------ k_cpreduce
 __global__ void __launch_bounds__(256) k_cpreduce(QrdmArgs a, const double *Gp, int kp, double *cp) {
@@ -408,7 +429,7 @@ __global__ void __launch_bounds__(256) k_cpreduce(QrdmArgs a, const double *Gp, 
     if (qrdm_dm_idle(ctl) || !ctl->cpath) return;
     const int l = ctl->l;
     const int64_t t = a.m - ctl->ns;
-    const int np = (int)((t + CP_ROWS - 1) / CP_ROWS);
+    const int np = (int)((t + CP_SR - 1) / CP_SR);
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= l * l) return;
     const int i = e / l, j = e - i * l;
@@ -688,73 +709,54 @@ hipError_t launch_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv,
 }
 
 // ------------------------------------------------------------------ k_cpanel3
-// Slab s: rows [128 s, 128 s + 128) of the block past its top l rows:
-// V = Q1 P, written to A (below the top block) and, in place of Q1, to the V
-// staging buffer (and its FP32 copy in mixed precision).
-__global__ void __launch_bounds__(256) k_cpanel3(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, float *Vw32) {
+// Slab s: rows [64 s, 64 s + 64) of the block past its top l rows: V = Q1 P,
+// written to A (below the top block) and, in place of Q1, to the V staging
+// buffer (and its FP32 copy in mixed precision).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+k_cpanel3(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, float *Vw32) {
     const QrdmCtl *ctl = a.ctl;
     if (qrdm_dm_idle(ctl) || !ctl->cpath) return;
     const int64_t ns = ctl->ns, t = a.m - ns;
     const int l = ctl->l;
-    const int64_t r0 = (int64_t)blockIdx.x * CP_ROWS;
+    const int64_t r0 = (int64_t)blockIdx.x * CP_SR;
     if (r0 >= t) return;
-    const int nr = (int)(t - r0 < CP_ROWS ? t - r0 : CP_ROWS);
+    const int nr = (int)(t - r0 < CP_SR ? t - r0 : CP_SR);
     const int rlo = r0 < l ? (int)(l - r0) : 0;  // rows of the top block (written by k_cpanel2)
     if (rlo >= nr) return;
-    __shared__ double Qs[CP_ROWS * CP_LD];
+    __shared__ double Qs[CP_SR * CP_LD];
     __shared__ double Ps[CP_K * CP_LD];
     const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lt = (l + 15) >> 4, lp = 16 * lt;
+    const int i16 = lane & 15, k4 = lane >> 4;
     {
-        double v[32], w[16];
+        double v[16], w[16];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
+        for (int u = 0; u < 16; ++u) {
+            const int e = tid + 256 * u, c = e >> 6, r = e & 63;
             v[u] = (c < l && r >= rlo && r < nr) ? Vw[(int64_t)c * ldv + r0 + r] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) w[u] = cp[CP_OFF_P + tid + 256 * u];
-#pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
-            Qs[r * CP_LD + c] = v[u];
+            w[u] = cp[CP_OFF_P + e];
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int e = tid + 256 * u;
-            Ps[(e >> 6) * CP_LD + (e & 63)] = w[u];
+            const int e = tid + 256 * u, c = e >> 6, r = e & 63;
+            Qs[r * CP_LD + c] = v[u];
+            Ps[c * CP_LD + r] = w[u];  // P row c, column r (P is stored by rows)
         }
     }
     __syncthreads();
-    const int i16 = lane & 15, k4 = lane >> 4;
-    dbl4 acc[8];
-    const int ntile = 8 * lt;
+    dbl4 acc[4];
+    cp_slab_upper(Qs, Ps, acc);
+    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int tile = wv + 4 * u;
-        acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-        if (tile < ntile) {
-            const int rt = tile / lt, ct = tile - rt * lt;
-            for (int kb = 0; kb < lp; kb += 4)
-                acc[u] = cp_mfma(Qs[(rt * 16 + i16) * CP_LD + kb + k4], Ps[(kb + k4) * CP_LD + ct * 16 + i16], acc[u]);
-        }
+    for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Qs[(16 * wv + 4 * v + k4) * CP_LD + 16 * ct + i16] = acc[ct][v];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int tile = wv + 4 * u;
-        if (tile < ntile) {
-            const int rt = tile / lt, ct = tile - rt * lt;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Qs[(rt * 16 + 4 * v + k4) * CP_LD + ct * 16 + i16] = acc[u][v];
-        }
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int u = 0; u < 32; ++u) {
-        const int e = tid + 256 * u, c = e >> 7, r = e & (CP_ROWS - 1);
+    for (int u = 0; u < 16; ++u) {
+        const int e = tid + 256 * u, c = e >> 6, r = e & 63;
+        const double v = Qs[r * CP_LD + c];
         if (c < l && r >= rlo && r < nr) {
-            const double v = Qs[r * CP_LD + c];
             a.A[(ns + c) * a.lda + ns + r0 + r] = v;
             Vw[(int64_t)c * ldv + r0 + r] = v;
             if (Vw32) Vw32[(int64_t)c * ldv + r0 + r] = (float)v;
@@ -765,7 +767,7 @@ __global__ void __launch_bounds__(256) k_cpanel3(QrdmArgs a, const double *cp, d
 hipError_t launch_cpanel3(QrdmArgs a, const double *cp, double *Vw, int64_t ldv, float *Vw32, int64_t t_bound,
                           hipStream_t s) {
     if (t_bound <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cpanel3, dim3((unsigned)((t_bound + CP_ROWS - 1) / CP_ROWS)), dim3(256), 0, s, a, cp, Vw,
+    hipLaunchKernelGGL(k_cpanel3, dim3((unsigned)((t_bound + CP_SR - 1) / CP_SR)), dim3(256), 0, s, a, cp, Vw,
                        ldv, Vw32);
     return hipGetLastError();
 }

@@ -175,7 +175,7 @@ Layout make_layout(int64_t m, int64_t n, int kmax) {
     L.ctl = take(sizeof(QrdmCtl));
     L.vn1 = take(sizeof(double) * nn);
     L.vn2 = take(sizeof(double) * nn);
-    L.gp = take(sizeof(double) * (size_t)gram_partials(mm) * kp * kp);
+    L.gp = take(sizeof(double) * (size_t)std::max(gram_partials(mm), cpanel_partials(mm)) * kp * kp);
     L.g = take(sizeof(double) * QK_KM * QK_KM);
     L.theta = take(sizeof(double) * QK_KM * QK_KM);
     const int64_t pmax = (mm + kMinRowsPerWg - 1) / kMinRowsPerWg;
