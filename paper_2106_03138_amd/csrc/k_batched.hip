@@ -109,9 +109,11 @@ __device__ __forceinline__ void qb_gram(const F &col, int nc, int t, double *G) 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * bi + 4 * v + kk, cc = 16 * bj + i;
-            if (row < nc && cc < nc) {
+            // a diagonal tile holds both (row, cc) and (cc, row): each entry is
+            // stored once, by the lane with row <= cc
+            if (row < nc && cc < nc && row <= cc) {
                 G[row * QB_LD + cc] = acc[v];
-                G[cc * QB_LD + row] = acc[v];
+                if (row < cc) G[cc * QB_LD + row] = acc[v];
             }
         }
     }
