@@ -45,11 +45,12 @@ template <> struct Mfma<float> {
 #define G1_NT 256   // trailing columns per workgroup (V reused across them): 128 or 256
 #endif
 #ifndef G1_TARGET_WGS
-#define G1_TARGET_WGS 256  // split count aims at this many workgroups
+#define G1_TARGET_WGS 512  // split count aims at this many workgroups (two per compute unit)
 #endif
 #ifndef G1_KC
-#define G1_KC 32    // rows staged per step: 16 or 32
+#define G1_KC 16    // rows staged per step: 16 or 32 (16: 120 VGPRs and 44 KB of LDS, two workgroups per CU)
 #endif
+#define G1_MINROWS 128  // rows of a split at least
 #define G1_TH 512   // threads: 8 wavefronts, G1_NT / 8 columns each
 #define G1_CT (G1_NT / 128)  // 16-column tiles per wavefront
 #define G1_CPP (G1_TH / G1_KC)          // columns staged per pass (one thread per row of a column)
@@ -71,13 +72,13 @@ __device__ __forceinline__ double ld_coh(const double *p) {
 // columns) alone, so that the bits of the result do not depend on the launch
 // bounds the host passes: at most G1_TARGET_WGS workgroups (one wave over the
 // compute units: one more split past it would start a second wave), at most
-// QK_SPLIT_MAX splits of at least 256 rows, krows a multiple of G1_KC.  Both
+// QK_SPLIT_MAX splits of at least G1_MINROWS rows, krows a multiple of G1_KC.  Both
 // GEMM1 and the partial sum in k_zsum take it from here.
 __device__ __forceinline__ int g1_krows(int64_t t, int64_t w) {
     const int ntile = (int)((w + G1_NT - 1) / G1_NT);
     int ns = G1_TARGET_WGS / ntile;
     if (ns > QK_SPLIT_MAX) ns = QK_SPLIT_MAX;
-    const int64_t maxs = (t + 255) / 256;
+    const int64_t maxs = (t + G1_MINROWS - 1) / G1_MINROWS;
     if (ns > maxs) ns = (int)maxs;
     if (ns < 1) ns = 1;
     return (int)(((t + ns - 1) / ns + G1_KC - 1) / G1_KC * G1_KC);
@@ -562,9 +563,9 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const int64_t ysplit = trail_ysplit(a.kmax, a.n);
     const int ntile = (int)((w_bound + G1_NT - 1) / G1_NT);
     // enough splits for any trailing size within the bounds: g1_krows picks the
-    // split on the device (at most 16, at most t/256, at most G1_TARGET_WGS over
+    // split on the device (at most 16, at most t/G1_MINROWS, at most G1_TARGET_WGS over
     // the column tiles of the narrowest possible w); workgroups past it return
-    int64_t nsplit = (t_bound + 255) / 256;
+    int64_t nsplit = (t_bound + G1_MINROWS - 1) / G1_MINROWS;
     if (nsplit > QK_SPLIT_MAX) nsplit = QK_SPLIT_MAX;
     {
         const int64_t wl = w_lo > 1 ? w_lo : 1;
