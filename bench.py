@@ -43,8 +43,8 @@ def flops_cols(m, n, r):
     return float(np.sum(4.0 * (m - s) * (n - s)))
 
 
-KERNEL_SOURCES = {"k_panel": "k_panel.hip", "k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip",
-                  "k_qp_run": "k_qp3.hip"}
+KERNEL_SOURCES = {"k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip", "k_qp_run": "k_qp3.hip",
+                  "k_qp_tail": "k_qp3.hip"}
 
 
 def source_sha(kernel):
@@ -74,23 +74,23 @@ def measured_traffic(kernel, workload_tag):
 
 
 def roofline(prof, prec, Q, workload_tag=None):
-    """Roofline of the kernel with the largest summed time.  The panel is
-    HBM-bound (arithmetic intensity k_s/8 flop/B is below the FP64 ridge of
-    78.6/8 = 9.8 flop/B); the two trailing GEMMs are MFMA-bound; the QP3 block
-    kernel (column pivoting, a matrix-vector product over the trailing matrix
-    per pivot, 2 flop per 8 B) is HBM-bound."""
-    times = {"k_panel": prof["panel_ms"], "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"],
-             "k_qp_run": prof.get("qp3_run_ms", 0.0)}
+    """Roofline of the kernel with the largest summed time among the column-
+    pivoting kernel and the two trailing GEMMs (the panel and the DM selection
+    are chains of short single-workgroup and grid launches, reported in
+    phase_ms).  The column-pivoting kernel (one matrix-vector product over the
+    trailing matrix per pivot: 2 flop per 8 B) is HBM-bound; at 8192^2 the whole
+    tail is one launch of the LDS-resident k_qp_tail, otherwise block launches
+    of k_qp_run.  The trailing GEMMs are MFMA-bound; GEMM1's time includes the
+    partial sum and Z = T^T Y (k_zsum) between the same events."""
+    qp_name = "k_qp_tail" if int(prof.get("nqp3_tail", 0)) > 0 and int(prof.get("nqp3_launch", 0)) == 1 \
+        else "k_qp_run"
+    times = {qp_name: prof.get("qp3_run_ms", 0.0), "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"]}
     dom = max(times, key=times.get)
-    nlaunch = max(int(prof["npanel"]), 1)  # one panel and one launch of each GEMM per block
-    if dom == "k_qp_run":
+    nlaunch = max(int(prof["npanel"]), 1)  # one launch of each GEMM per block
+    if dom in ("k_qp_run", "k_qp_tail"):
         nlaunch = max(int(prof["nqp3_launch"]), 1)
         bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
         work = prof["qp3_bytes"]
-        achieved = work / (times[dom] * 1e-3) / 1e9
-    elif dom == "k_panel":
-        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
-        work = prof["panel_bytes"]
         achieved = work / (times[dom] * 1e-3) / 1e9
     else:
         bound, unit = "mfma", "TFLOP/s"
@@ -105,8 +105,12 @@ def roofline(prof, prec, Q, workload_tag=None):
             "phase_ms": {"dm_select": round(prof["dm_ms"], 3), "panel": round(prof["panel_ms"], 3),
                          "gemm1": round(prof["gemm1_ms"], 3), "gemm2": round(prof["gemm2_ms"], 3),
                          "downdate": round(prof["downdate_ms"], 3), "qp3_tail": round(prof["qp3_ms"], 3),
-                         "qp3_block_kernel": round(prof.get("qp3_run_ms", 0.0), 3),
-                         "loop_total": round(prof["total_ms"], 3)}}
+                         "qp3_kernel": round(prof.get("qp3_run_ms", 0.0), 3),
+                         "loop_total": round(prof["total_ms"], 3)},
+            "gemm_tflops": {"gemm1_with_zsum": round(prof["gemm_flop"] / (prof["gemm1_ms"] * 1e-3) / 1e12, 3)
+                            if prof["gemm1_ms"] > 0 else None,
+                            "gemm2": round(prof["gemm_flop"] / (prof["gemm2_ms"] * 1e-3) / 1e12, 3)
+                            if prof["gemm2_ms"] > 0 else None}}
 
 
 def batched_leg(args, torch, Q):

@@ -30,7 +30,8 @@ class Stats(ctypes.Structure):
                 ("downdate_ms", ctypes.c_double), ("qp3_ms", ctypes.c_double), ("panel_flop", ctypes.c_double),
                 ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64),
                 ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64),
-                ("qp3_start", ctypes.c_int64), ("ngram", ctypes.c_int64)]
+                ("qp3_start", ctypes.c_int64), ("ngram", ctypes.c_int64),
+                ("nqp3_tail", ctypes.c_int64)]
 
 
 class Block(ctypes.Structure):

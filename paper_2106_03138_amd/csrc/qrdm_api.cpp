@@ -457,6 +457,7 @@ void prof_fill(const ProfRun &prof, PollCtx &pc, const QrdmCtl &cf, int64_t m, i
     if (hipEventElapsedTime(&ms, pc.prof_ev[1], pc.prof_ev[2]) == hipSuccess) st->qp3_ms = ms;
     if (hipEventElapsedTime(&ms, pc.prof_ev[0], pc.prof_ev[2]) == hipSuccess) st->total_ms = ms;
     st->nqp3_launch = prof.qp_launches;
+    st->nqp3_tail = prof.tail_launches;
     double q = 0.0;
     for (int64_t i = 0; i < prof.qp_launches; ++i) {
         float x = 0.f;
@@ -1081,6 +1082,7 @@ int qrp_factor_ex(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_param
             if (hipEventElapsedTime(&ms, pg.pc->prof_ev[0], pg.pc->prof_ev[1]) == hipSuccess)
                 stats->qp3_ms = stats->total_ms = ms;
             stats->nqp3_launch = prof.qp_launches;
+            stats->nqp3_tail = prof.tail_launches;
             double q = 0.0;
             for (int64_t i = 0; i < prof.qp_launches; ++i) {
                 float x = 0.f;
