@@ -2,18 +2,23 @@
 // compact WY form of Section 3.2).  With the l kept reflectors written as
 // H_0...H_{l-1} = I - V T V^T (forward accumulation),
 //     A_tr <- (I - V T V^T)^T A_tr = A_tr - V Z,   Z = T^T (V^T A_tr),
-// A_tr = A[n_s:m, n_s+k_s:n].  T is not formed: since T^{-1} = diag(1/tau) +
-// strict_upper(V^T V), Z solves the lower recurrence
-//     Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b),   Y = V^T A_tr,
-// (Z_a = 0 when tau_a = 0, the identity reflector), with v_b^T v_a recorded by
-// the panel.  Two kernels on gfx950 MFMA:
+// A_tr = A[n_s:m, n_s+c0:n], c0 = k_s (or l when the panel came from the Gram
+// matrix: the rejected columns of the block take the update too).  Three
+// kernels on gfx950 MFMA:
 //   k_gemm1  Y = V^T A_tr, split over rows, partial products published;
-//   k_zsum   per 32 (explicit T) or 64 (recurrence) trailing columns: Y = sum
-//            of the partials in split order, then Z = T^T Y or the recurrence;
+//   k_zsum   per 32 or 64 trailing columns: Y = the sum of the partials in split
+//            order, then Z = T^T Y.  For l <= 64, T is formed explicitly (the
+//            Gram-matrix panel provides it; otherwise from the v_b^T v_a the
+//            column panel records: 16 x 16 diagonal blocks by the larft column
+//            recurrence, T_12 = -T_11 (V_1^T V_2) T_22 for the halves) and Z is
+//            a product on FP64 MFMA.  For larger blocks, with
+//            T^{-1} = diag(1/tau) + strict_upper(V^T V), Z solves the lower
+//            recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) (Z_a = 0
+//            when tau_a = 0, the identity reflector);
 //   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once.
 // Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode runs both products
-// on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and the
-// recurrence runs in FP64.
+// on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and Z is
+// formed in FP64.
 #include "qrdm_internal.h"
 
 #define QK_SPLIT_MAX 16  // row splits of the V^T A product
