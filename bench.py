@@ -79,7 +79,7 @@ def roofline(prof, prec, Q, workload_tag=None):
     are chains of short single-workgroup and grid launches, reported in
     phase_ms).  The column-pivoting kernel (one matrix-vector product over the
     trailing matrix per pivot: 2 flop per 8 B) is HBM-bound; at 8192^2 the whole
-    tail is one launch of the LDS-resident k_qp_tail, otherwise block launches
+    tail is one launch of the register-resident k_qp_tail, otherwise block launches
     of k_qp_run.  The trailing GEMMs are MFMA-bound; GEMM1's time includes the
     partial sum and Z = T^T Y (k_zsum) between the same events."""
     qp_name = "k_qp_tail" if int(prof.get("nqp3_tail", 0)) > 0 and int(prof.get("nqp3_launch", 0)) == 1 \

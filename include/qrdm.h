@@ -132,9 +132,10 @@ typedef struct {
     int64_t ngram;       /* panels formed from the Gram matrix of the block (CholeskyQR2 and
                             Householder reconstruction) rather than column by column
                             (always filled)                                                  */
-    int64_t nqp3_tail;   /* of the nqp3_launch launches, those of the LDS-resident tail kernel,
-                            which takes every step left once the trailing block has at most
-                            2048 rows (0 or 1; profile = 1)                                  */
+    int64_t nqp3_tail;   /* of the nqp3_launch launches, those of the register-resident tail
+                            kernel, which takes every step left once the trailing block has
+                            at most 2048 rows and 8 columns per compute unit (0 or 1;
+                            profile = 1)                                                     */
 } qrdm_stats;
 
 /* One record per outer step of the DM loop, for tests and tracing.  When the

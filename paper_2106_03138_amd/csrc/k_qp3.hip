@@ -1268,14 +1268,18 @@ int qp3_block_grid(int64_t m) {
     return g;
 }
 
-// ====================================================== LDS-resident tail
-// Column pivoting (Algorithm 2) on a trailing block small enough for the LDS of
-// the grid: every remaining step in one persistent launch, in the unblocked
-// form (each reflector applied at once), with one grid barrier per step.
+// ================================================= register-resident tail
+// Column pivoting (Algorithm 2) on a trailing block small enough for the
+// registers of the grid: every remaining step in one persistent launch, in the
+// unblocked form (each reflector applied at once), with one grid barrier per
+// step.
 //
-// Workgroup w holds the trailing columns c = w + G k (offsets from the first
-// column j0 of the launch) from row j0 down, with their partial norms and
-// current positions, for the whole launch.  Per step j:
+// Workgroup w holds the trailing columns c = w + G k (k < QT_QMAX, offsets from
+// the first column j0 of the launch) from row j0 down, in registers: thread i
+// holds rows j0 + i + QT_THREADS u (u < QT_RPT) of each.  Lane k of every
+// wavefront holds column k's two partial norms, its current position and
+// whether it is still active (the eight wavefronts keep identical copies).
+// Per step j:
 //   every workgroup reduces the G published (norm, position) partials to the
 //   pivot (largest partial norm, lowest position on ties), reads the pivot's
 //   column from its owner's published copy, and forms the reflector (LAPACK
@@ -1286,31 +1290,93 @@ int qp3_block_grid(int64_t m) {
 //   the rows above j0 (R12 entries of both columns), workgroup 0 the
 //   permutation, and the owner of the column at position j notes its new
 //   position;
-//   each workgroup applies H_j to its columns in LDS and downdates their
-//   partial norms by the cancellation-safe rule (recomputed from LDS when the
-//   downdate lost too much), then publishes its largest (norm, position) and,
-//   ahead of the barrier, a copy of that column below row j: whichever
-//   workgroup wins, its column is already out for the next step;
+//   each workgroup applies H_j to its active columns: the dot products of a
+//   thread's rows with v are summed over the wavefront for all columns at
+//   once and over the eight wavefronts through LDS; lane k downdates column
+//   k's partial norm by the cancellation-safe rule (recomputed from the rows
+//   below j when the downdate lost too much); the workgroup publishes its
+//   largest (norm, position) and, ahead of the barrier, a copy of that column
+//   below row j: whichever workgroup wins, its column is already out for the
+//   next step;
 //   grid barrier.
 // The stopping test is applied at every step as in the other QP3 kernels.  At
 // the end the columns not pivoted (a stop) are written back to their final
 // positions.  A launch that follows a QP3 block launch first finishes what the
 // block left: the last reflector's normalization and the flagged norms.
-#define QT_THREADS 256
-#define QT_LDS_MAX (150 * 1024)  // dynamic LDS of the tail kernel (at most)
-#define QT_ROWS_MAX 2048         // largest trailing block height it takes
-#define QT_META 4                // doubles per published partial: norm, position, column, unused
+#define QT_THREADS 512
+#define QT_WAVES (QT_THREADS / 64)
+#define QT_ROWS_MAX 2048                   // largest trailing block height it takes
+#define QT_RPT (QT_ROWS_MAX / QT_THREADS)  // rows of each column per thread
+#define QT_QMAX 8                          // columns per workgroup (at most)
+#define QT_META 4                          // doubles per published partial: norm, position, column, unused
+static_assert(QT_WAVES == 8 && QT_QMAX == 8, "the sums below take eight values over eight wavefronts");
 
-extern __shared__ double qt_lds[];
-
-// Dynamic LDS of the tail kernel for cq columns of crows rows per workgroup:
-// the columns, the pivot column, and the columns' norms and positions.
-__host__ __device__ inline size_t qt_lds_bytes(int cq, int crows) {
-    return sizeof(double) * ((size_t)cq * crows + crows + 2 * (size_t)cq) + 2 * sizeof(int32_t) * (size_t)cq;
+// v of lane l (the same l in every lane).
+__device__ __forceinline__ double qt_lane(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__global__ void __launch_bounds__(QT_THREADS)
-k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch) {
+// The eight per-wavefront partial sums p[0..7] in a fixed order.
+__device__ __forceinline__ double qt_waves(const double *p) {
+    return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+}
+
+// Column k of the register array c (k the same in every lane), row register u:
+// a tree of selects on the bits of k (an equality chain would be folded into an
+// indexed access, which puts c in scratch memory).
+__device__ __forceinline__ double qt_pick(const double (&c)[QT_QMAX][QT_RPT], int k, int u) {
+    const bool b0 = k & 1, b1 = k & 2, b2 = k & 4;
+    const double y01 = b0 ? c[1][u] : c[0][u], y23 = b0 ? c[3][u] : c[2][u];
+    const double y45 = b0 ? c[5][u] : c[4][u], y67 = b0 ? c[7][u] : c[6][u];
+    return b2 ? (b1 ? y67 : y45) : (b1 ? y23 : y01);
+}
+
+// x + y, where lanes with bit K of the lane index clear take x and the partner
+// lane's x (lane ^ K), the others y and the partner's y (K = 32 or 16): the
+// gfx950 lane swaps exchange the two halves of x and y in one step.
+template <int K>
+__device__ __forceinline__ double qt_swapsum(double x, double y) {
+    const uint64_t xb = (uint64_t)__double_as_longlong(x), yb = (uint64_t)__double_as_longlong(y);
+    const uint32_t xl = (uint32_t)xb, xh = (uint32_t)(xb >> 32), yl = (uint32_t)yb, yh = (uint32_t)(yb >> 32);
+    uint32_t a0, a1, b0, b1;
+    if constexpr (K == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+        a0 = lo[0]; b0 = lo[1]; a1 = hi[0]; b1 = hi[1];
+    } else {
+        static_assert(K == 16, "lane swap");
+        const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+        a0 = lo[0]; b0 = lo[1]; a1 = hi[0]; b1 = hi[1];
+    }
+    return __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0)) +
+           __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+}
+
+// Sums over the 64 lanes of e[0..7] at once: the exchanges with lane ^ 32,
+// ^ 16 and ^ 8 each halve the values a lane carries (the lane with the bit
+// clear keeps the lower half of its set), the rest sum within groups of eight
+// lanes.  Lanes 8g .. 8g + 7 return the total of e[g].
+__device__ __forceinline__ double qt_sum8(const double (&e)[QT_QMAX]) {
+    const int lane = threadIdx.x & 63;
+    const bool h8 = lane & 8;
+    double f[4], g[2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) f[c] = qt_swapsum<32>(e[c], e[c + 4]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) g[c] = qt_swapsum<16>(f[c], f[c + 2]);
+    double h = (h8 ? g[1] : g[0]) + qp_x<8>(h8 ? g[0] : g[1]);
+    h += qp_x<7>(h);
+    h += qp_x<2>(h);
+    h += qp_x<1>(h);
+    return h;
+}
+
+__global__ void __launch_bounds__(QT_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
     QrdmCtl *ctl = a.ctl;
     if (ctl->done) {
         if (a.snap && blockIdx.x == 0 && threadIdx.x == 0) qrdm_write_snapshot(ctl, a.snap);
@@ -1321,10 +1387,14 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
     uint32_t *gb = a.gbar + (launch & 1) * GBAR_GROUPS * GBAR_STRIDE;
     if (wg == 0 && tid == 0) gbar_clear(a.gbar + ((launch + 1) & 1) * GBAR_GROUPS * GBAR_STRIDE);
     const int64_t p = p_of(a);
-    __shared__ double s_v[QT_THREADS / 64];
-    __shared__ int s_j[QT_THREADS / 64];
-    __shared__ int s_k[QT_THREADS / 64];
-    __shared__ double s_red[QT_THREADS / 64];
+    __shared__ double s_v[QT_WAVES];
+    __shared__ int s_j[QT_WAVES];
+    __shared__ int s_k[QT_WAVES];
+    __shared__ double s_red[QT_WAVES];
+    __shared__ double s_alpha;
+    __shared__ double s_dp[QT_QMAX * QT_WAVES];  // per-wavefront sums of v^T c_k
+    __shared__ double s_rp[QT_QMAX * QT_WAVES];  // per-wavefront sums of squares (recomputed norms)
+    __shared__ double s_c0[QT_QMAX];      // row j of each column before H_j
     // loop state (identical in every workgroup)
     int64_t ns = ctl->ns, rank = ctl->rank, nblocks = ctl->nblocks, jm = ctl->jmax;
     const int64_t k0 = ctl->qp_k0;
@@ -1362,86 +1432,88 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
     const int64_t j0 = ns;
     const int64_t t0 = a.m > j0 ? a.m - j0 : 0, w0 = a.n > j0 ? a.n - j0 : 0;
     const int q = wg < w0 ? (int)((w0 - wg + G - 1) / G) : 0;  // columns of this workgroup
-    if ((w0 + G - 1) / G > cq || t0 > crows) {  // the host sized the LDS from bounds (cannot fail)
+    if ((w0 + G - 1) / G > QT_QMAX || t0 > crows || crows > QT_ROWS_MAX) {  // the host's bounds (cannot fail)
         if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
         return;
     }
-    double *cc = qt_lds;                          // [cq][crows], rows from j0
-    double *xs = cc + (size_t)cq * crows;         // [crows]: the pivot column, then v
-    double *n1 = xs + crows;                      // [cq]
-    double *n2 = n1 + cq;                         // [cq]
-    int32_t *pos = (int32_t *)(n2 + cq);          // [cq]: current position offset (from j0)
-    int32_t *act = pos + cq;                      // [cq]: not yet pivoted
     double *meta = pub;                           // [2][G][QT_META]
     double *pdat = pub + 2 * (size_t)G * QT_META; // [2][G][crows]
-    // ---- load this workgroup's columns, norms and flags
-    {
-        const int64_t tot = (int64_t)q * t0;
-        for (int64_t i0 = 0; i0 < tot; i0 += 8 * QT_THREADS) {
-            double v[8];
+    // ---- this workgroup's columns, and lane k's column state
+    // (every load issued before any is used: clamped addresses, then the selects)
+    double c[QT_QMAX][QT_RPT];
+    if (t0 > 0 && w0 > 0) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t i = i0 + tid + QT_THREADS * u;
-                const int64_t k = t0 > 0 ? i / t0 : 0;
-                v[u] = i < tot ? a.A[(j0 + wg + (int64_t)G * k) * a.lda + j0 + i % t0] : 0.0;
+        for (int k = 0; k < QT_QMAX; ++k)
+#pragma unroll
+            for (int u = 0; u < QT_RPT; ++u) {
+                const int64_t r = tid + QT_THREADS * u;
+                const int64_t col = k < q ? j0 + wg + (int64_t)G * k : j0;
+                c[k][u] = a.A[col * a.lda + j0 + (r < t0 ? r : 0)];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t i = i0 + tid + QT_THREADS * u;
-                if (i < tot) cc[(i / t0) * crows + i % t0] = v[u];
-            }
-        }
-        for (int k = tid; k < q; k += QT_THREADS) {
-            const int64_t c = j0 + wg + (int64_t)G * k;
-            n1[k] = qr_ld(a.vn1 + c);
-            n2[k] = qr_ld(a.vn2 + c);
-            pos[k] = wg + G * k;
-            act[k] = 1;
-        }
-        __syncthreads();
+        for (int k = 0; k < QT_QMAX; ++k)
+#pragma unroll
+            for (int u = 0; u < QT_RPT; ++u)
+                if (!(k < q && tid + QT_THREADS * u < t0)) c[k][u] = 0.0;
+    } else {
+#pragma unroll
+        for (int k = 0; k < QT_QMAX; ++k)
+#pragma unroll
+            for (int u = 0; u < QT_RPT; ++u) c[k][u] = 0.0;
     }
+    const int kl = lane < QT_QMAX ? lane : 0;
+    const int64_t cl = j0 + wg + (int64_t)G * kl;  // lane k's column
+    bool actv = lane < q;
+    double n1v = actv ? qr_ld(a.vn1 + cl) : 0.0, n2v = actv ? qr_ld(a.vn2 + cl) : 1.0;
+    int posv = wg + G * kl;  // current position offset (from j0)
     int64_t nrec = 0;
-    // flagged partial norms (a preceding block launch): recomputed from LDS,
-    // one wavefront per column
-    for (int k = wv; k < q; k += QT_THREADS / 64) {
-        const int64_t c = j0 + wg + (int64_t)G * k;
-        if (!qr_ldi(flag + c)) continue;
-        double t = 0.0;
-        for (int64_t r = lane; r < t0; r += 64) t += cc[k * crows + r] * cc[k * crows + r];
-        t = qp_wave_sum(t);
-        if (lane == 0) {
-            const double v = sqrt(t);
-            n1[k] = v;
-            n2[k] = v;
-            qr_sti(flag + c, 0);
-            ++nrec;
+    // partial norms recomputed from the rows rs .. t0 - 1 (offsets from j0) of
+    // the columns in the mask nm, the same in every thread; lane k takes column k's
+    auto recompute = [&](uint32_t nm, int64_t rs) {
+        double e[QT_QMAX];
+#pragma unroll
+        for (int k = 0; k < QT_QMAX; ++k) {
+            e[k] = 0.0;
+            if (nm >> k & 1) {
+#pragma unroll
+                for (int u = 0; u < QT_RPT; ++u) {
+                    const int64_t r = tid + QT_THREADS * u;
+                    const double y = r >= rs ? c[k][u] : 0.0;
+                    e[k] += y * y;
+                }
+            }
+        }
+        const double h = qt_sum8(e);
+        if ((lane & 7) == 0) s_rp[(lane >> 3) * QT_WAVES + wv] = h;
+        __syncthreads();
+        if (lane < QT_QMAX && (nm >> kl & 1)) {
+            const double v = sqrt(qt_waves(s_rp + QT_WAVES * kl));
+            n1v = v;
+            n2v = v;
+            if (wv == 0) ++nrec;
+        }
+    };
+    // flagged partial norms (a preceding block launch)
+    {
+        const bool f = actv && qr_ldi(flag + cl) != 0;
+        const uint32_t nm = (uint32_t)__ballot(f);
+        if (nm) {
+            recompute(nm, 0);
+            if (f && wv == 0) qr_sti(flag + cl, 0);
         }
     }
-    __syncthreads();
-    // this workgroup's largest (norm, position) over its active columns: the
-    // wavefront k % 4 takes column k, as in the update below
+    // this workgroup's largest (norm, position) over its active columns, the
+    // same in every thread
     auto local_best = [&](double &bv, int &bp, int &bk) {
-        bv = -1.0;
-        bp = 0x7fffffff;
-        bk = -1;
-        if (lane == 0) {
-            for (int k = wv; k < q; k += QT_THREADS / 64)
-                if (act[k] && qp_better(n1[k], pos[k], bv, bp)) { bv = n1[k]; bp = pos[k]; bk = k; }
-            s_v[wv] = bv;
-            s_j[wv] = bp;
-            s_k[wv] = bk;
-        }
-        __syncthreads();
-        bv = s_v[0];
-        bp = s_j[0];
-        bk = s_k[0];
-        for (int w = 1; w < QT_THREADS / 64; ++w)
-            if (qp_better(s_v[w], s_j[w], bv, bp)) { bv = s_v[w]; bp = s_j[w]; bk = s_k[w]; }
-        __syncthreads();
+        bv = actv ? n1v : -1.0;
+        bp = actv ? posv : 0x7fffffff;
+        qp_argmax_lanes(bv, bp);  // a total order: one lane holds the winner
+        const unsigned long long hold = __ballot(actv && n1v == bv && posv == bp);
+        bk = hold ? __ffsll((long long)hold) - 1 : -1;
     };
-    // publishes the partial (norm, position, column) and rows [jr, m) of the
-    // local best column for the step at jr, into parity slot par
-    auto publish = [&](int par, int64_t jr, double bv, int bp, int bk) {
+    // publishes the partial (norm, position, column) and rows rs .. t0 - 1
+    // (offsets from j0) of the local best column, into parity slot par
+    auto publish = [&](int par, int64_t rs, double bv, int bp, int bk) {
         double *me = meta + ((size_t)par * G + wg) * QT_META;
         if (tid == 0) {
             qr_st(me, bv);
@@ -1450,16 +1522,19 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
         }
         if (bk >= 0) {
             double *dst = pdat + ((size_t)par * G + wg) * crows;
-            const double *src = cc + (size_t)bk * crows + (jr - j0);
-            const int64_t nr = a.m - jr;
-            for (int64_t i = tid; i < nr; i += QT_THREADS) qr_st(dst + i, src[i]);
+#pragma unroll
+            for (int u = 0; u < QT_RPT; ++u) {
+                const int64_t r = tid + QT_THREADS * u;
+                const double y = qt_pick(c, bk, u);
+                if (r >= rs && r < t0) qr_st(dst + (r - rs), y);
+            }
         }
     };
     {
         double bv;
         int bp, bk;
         local_best(bv, bp, bk);
-        publish(0, j0, bv, bp, bk);
+        publish(0, 0, bv, bp, bk);
     }
     gbar_wait(gb, G, ++bar, &ctl->error);
     // the slab of the rows above j0 whose R12 entries this workgroup swaps
@@ -1472,7 +1547,8 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
             if (rank < 0) rank = j;
             break;
         }
-        // ---- the pivot: the G partials of this step
+        // ---- the pivot: the G partials of this step (s_v, s_j and s_k are
+        // written again only a step later, after the barriers below)
         double uv = -1.0;
         int up = 0x7fffffff, uc = -1;
         {
@@ -1493,10 +1569,9 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
             uv = s_v[0];
             up = s_j[0];
             int wsel = 0;
-            for (int w = 1; w < QT_THREADS / 64; ++w)
+            for (int w = 1; w < QT_WAVES; ++w)
                 if (qp_better(s_v[w], s_j[w], uv, up)) { uv = s_v[w]; up = s_j[w]; wsel = w; }
             uc = s_k[wsel];
-            __syncthreads();
         }
         // ---- stopping test (as k_qp_select)
         if (nblocks == 0 && j == 0) amax = uv;
@@ -1524,32 +1599,60 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
         umax = uv;
         nblocks += 1;
         const int owner = uc % G, kw = uc / G;
-        const int64_t t = a.m - j;  // rows of the reflector
-        // ---- the pivot column from its owner's copy, and the reflector
+        const int rj = (int)(j - j0);  // row j: thread rj % QT_THREADS, register ru
+        const int ru = rj / QT_THREADS, tr = (int)t0;
+        // ---- the pivot column from its owner's copy (rows j .. m - 1), in the
+        // row layout of the columns, zero above row j
+        // (all loads issued before any is used)
+        double x[QT_RPT];
         {
             const double *src = pdat + ((size_t)par * G + owner) * crows;
-            double xv[8];
-            for (int64_t i0 = 0; i0 < t; i0 += 8 * QT_THREADS) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int64_t i = i0 + tid + QT_THREADS * u;
-                    xv[u] = i < t ? qr_ld(src + i) : 0.0;
-                }
+            for (int u = 0; u < QT_RPT; ++u) {
+                const int r = tid + QT_THREADS * u;
+                x[u] = qr_ld(src + (r >= rj && r < tr ? r - rj : 0));
+            }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int64_t i = i0 + tid + QT_THREADS * u;
-                    if (i < t) xs[i] = xv[u];
-                }
+            for (int u = 0; u < QT_RPT; ++u) {
+                const int r = tid + QT_THREADS * u;
+                if (!(r >= rj && r < tr)) x[u] = 0.0;
             }
         }
-        __syncthreads();
-        double sp = 0.0;
-        for (int64_t i = 1 + tid; i < t; i += QT_THREADS) sp += xs[i] * xs[i];
+        // ---- lane k: the pivot leaves the active set at position j; the
+        // column at position j (when another) takes the pivot's old position
+        if (wg == owner && lane == kw) {
+            actv = false;
+            posv = rj;
+        } else if (jm != j && actv && posv == rj) {
+            posv = up;
+        }
+        // ---- the swap of positions j and jm in this workgroup's slab of the
+        // rows above j0, and in the permutation (workgroup 0)
+        if (jm != j) {
+            for (int64_t r = ur0 + tid; r < ur1; r += QT_THREADS) {
+                const double x1 = a.A[j * a.lda + r], x2 = a.A[jm * a.lda + r];
+                a.A[j * a.lda + r] = x2;
+                a.A[jm * a.lda + r] = x1;
+            }
+            if (wg == 0 && tid == 0) {
+                const int32_t p1 = a.perm[j], p2 = a.perm[jm];
+                a.perm[j] = p2;
+                a.perm[jm] = p1;
+            }
+        }
+        // ---- the reflector (larfg): alpha is row j, sp the sum of squares below it
+        double sp = 0.0, xa = 0.0;
+#pragma unroll
+        for (int u = 0; u < QT_RPT; ++u) {
+            if (tid + QT_THREADS * u == rj) xa = x[u];
+            else sp += x[u] * x[u];
+        }
         sp = qp_wave_sum(sp);
         if (lane == 0) s_red[wv] = sp;
+        if (tid == (int)(rj % QT_THREADS)) s_alpha = xa;
         __syncthreads();
-        sp = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-        const double alpha = xs[0];
+        sp = qt_waves(s_red);
+        const double alpha = s_alpha;
         double beta, ti, den;
         if (sp == 0.0) {
             ti = 0.0;
@@ -1562,99 +1665,98 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
             den = alpha - beta;
         }
         const double rden = 1.0 / den;
-        __syncthreads();  // every thread has read xs[0]
-        for (int64_t i = tid; i < t; i += QT_THREADS) xs[i] = (i == 0) ? 1.0 : xs[i] * rden;
-        __syncthreads();
-        // ---- the owner: the final column j and tau_j
+#pragma unroll
+        for (int u = 0; u < QT_RPT; ++u) x[u] = (tid + QT_THREADS * u == rj) ? 1.0 : x[u] * rden;
+        // ---- the owner: the final column j (rows j0 .. m - 1) and tau_j
         if (wg == owner) {
-            double *colj = a.A + j * a.lda;
-            const double *mine = cc + (size_t)kw * crows;
-            for (int64_t r = tid; r < t0; r += QT_THREADS) {
-                const int64_t row = j0 + r;
-                const double v = row < j ? mine[r] : (row == j ? beta : xs[row - j]);
-                colj[row] = v;
-            }
-            if (tid == 0) {
-                a.tau_house[j] = ti;
-                act[kw] = 0;
-                pos[kw] = (int32_t)(j - j0);
-            }
-        }
-        // ---- the swap of positions j and jm: this workgroup's slab of rows
-        // above j0, the permutation (workgroup 0), the displaced column's position
-        if (jm != j) {
-            for (int64_t r = ur0 + tid; r < ur1; r += QT_THREADS) {
-                const double x1 = a.A[j * a.lda + r], x2 = a.A[jm * a.lda + r];
-                a.A[j * a.lda + r] = x2;
-                a.A[jm * a.lda + r] = x1;
-            }
-            if (wg == 0 && tid == 0) {
-                const int32_t p1 = a.perm[j], p2 = a.perm[jm];
-                a.perm[j] = p2;
-                a.perm[jm] = p1;
-            }
-            for (int k = tid; k < q; k += QT_THREADS)
-                if (act[k] && pos[k] == (int32_t)(j - j0) && !(wg == owner && k == kw)) pos[k] = (int32_t)up;
-        }
-        __syncthreads();
-        // ---- H_j applied to this workgroup's active columns (wavefront k % 4
-        // takes column k), then the partial norm downdate
-        const int64_t rj = j - j0;
-        for (int k = wv; k < q; k += QT_THREADS / 64) {
-            if (!act[k]) continue;
-            double *col = cc + (size_t)k * crows + rj;
-            double e[4] = {0.0, 0.0, 0.0, 0.0};
-            int64_t i = lane;
-            for (; i + 192 < t; i += 256) {
+            double *colj = a.A + j * a.lda + j0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) e[u] += xs[i + 64 * u] * col[i + 64 * u];
-            }
+            for (int k = 0; k < QT_QMAX; ++k)
+                if (k == kw) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (i + 64 * u < t) e[u] += xs[i + 64 * u] * col[i + 64 * u];
-            const double dot = qp_wave_sum((e[0] + e[1]) + (e[2] + e[3]));
-            const double wcol = ti * dot;
-            for (int64_t r = lane; r < t; r += 64) col[r] -= wcol * xs[r];
-            const double rjc = __shfl(col[0], 0, 64);  // row j of the column after H_j (lane 0's store)
-            double v1 = n1[k];
-            if (v1 != 0.0) {
-                double qq = 1.0 - (rjc * rjc) / (v1 * v1);
-                if (qq < 0.0) qq = 0.0;
-                const double r12 = v1 / n2[k];
-                const double q2 = qq * (r12 * r12);
-                if (q2 <= a.tol3z) {  // recompute from the rows below j (one sum order in every path)
-                    double s2 = 0.0;
-                    for (int64_t r = 1 + lane; r < t; r += 64) s2 += col[r] * col[r];
-                    s2 = qp_wave_sum(s2);
-                    v1 = sqrt(s2);
-                    if (lane == 0) {
-                        n2[k] = v1;
-                        ++nrec;
+                    for (int u = 0; u < QT_RPT; ++u) {
+                        const int r = tid + QT_THREADS * u;
+                        if (r < tr) colj[r] = r < rj ? c[k][u] : (r == rj ? beta : x[u]);
                     }
-                } else {
-                    v1 = v1 * sqrt(qq);
                 }
-                if (lane == 0) n1[k] = v1;
+            if (tid == 0) a.tau_house[j] = ti;
+        }
+        // ---- H_j: v^T c_k over this thread's rows (v is zero above row j, so
+        // every register takes part; the sums of columns no longer active are
+        // not used), then over the wavefront (all columns at once) and the
+        // workgroup
+        {
+            double e[QT_QMAX];
+#pragma unroll
+            for (int k = 0; k < QT_QMAX; ++k) {
+                e[k] = x[0] * c[k][0];
+#pragma unroll
+                for (int u = 1; u < QT_RPT; ++u) e[k] += x[u] * c[k][u];
+            }
+            const double h = qt_sum8(e);
+            if ((lane & 7) == 0) s_dp[(lane >> 3) * QT_WAVES + wv] = h;
+            if (tid == (int)(rj % QT_THREADS)) {
+                static_assert(QT_RPT == 4, "row register ru from its two bits");
+                const bool b0 = ru & 1, b1 = ru & 2;
+#pragma unroll
+                for (int k = 0; k < QT_QMAX; ++k)
+                    s_c0[k] = b1 ? (b0 ? c[k][3] : c[k][2]) : (b0 ? c[k][1] : c[k][0]);
             }
         }
         __syncthreads();
+        // lane k: w_k = tau_j v^T c_k, and the partial norm downdate by the
+        // cancellation-safe rule; row j after H_j is c0 - w_k (v_j = 1)
+        double wl = 0.0;
+        bool nd = false;
+        if (actv) {
+            wl = ti * qt_waves(s_dp + QT_WAVES * kl);
+            const double rjc = s_c0[kl] - wl;
+            if (n1v != 0.0) {
+                double qq = 1.0 - (rjc * rjc) / (n1v * n1v);
+                if (qq < 0.0) qq = 0.0;
+                const double r12 = n1v / n2v;
+                const double q2 = qq * (r12 * r12);
+                if (q2 <= a.tol3z) nd = true;
+                else n1v = n1v * sqrt(qq);
+            }
+        }
+        // the update of this thread's rows (w_k = 0 for the columns no longer
+        // active; rows above j, where v is zero, keep their value up to the
+        // sign of a zero)
+#pragma unroll
+        for (int k = 0; k < QT_QMAX; ++k) {
+            const double w = qt_lane(wl, k);
+#pragma unroll
+            for (int u = 0; u < QT_RPT; ++u) c[k][u] -= w * x[u];
+        }
+        const uint32_t nm = (uint32_t)__ballot(nd);
+        if (nm) recompute(nm, rj + 1);  // from the rows below j
         // ---- publish for the step at j + 1, then the barrier
         {
             double bv;
             int bp, bk;
             local_best(bv, bp, bk);
-            publish(par ^ 1, j + 1, bv, bp, bk);
+            publish(par ^ 1, rj + 1, bv, bp, bk);
         }
         gbar_wait(gb, G, ++bar, &ctl->error);
         j += 1;
     }
     // ---- the columns not pivoted (a stop): back to their final positions
-    for (int k = 0; k < q; ++k) {
-        if (!act[k]) continue;
-        double *dst = a.A + (j0 + pos[k]) * a.lda + j0;
-        for (int64_t r = tid; r < t0; r += QT_THREADS) dst[r] = cc[(size_t)k * crows + r];
+    {
+        const uint32_t am = (uint32_t)__ballot(actv);
+#pragma unroll
+        for (int k = 0; k < QT_QMAX; ++k)
+            if (am >> k & 1) {
+                const int pk = __builtin_amdgcn_readlane(posv, k);
+                double *dst = a.A + (j0 + pk) * a.lda + j0;
+#pragma unroll
+                for (int u = 0; u < QT_RPT; ++u) {
+                    const int64_t r = tid + QT_THREADS * u;
+                    if (r < t0) dst[r] = c[k][u];
+                }
+            }
     }
-    if (nrec && lane == 0) atomicAdd((unsigned long long *)&ctl->nrecompute, (unsigned long long)nrec);
+    if (nrec) atomicAdd((unsigned long long *)&ctl->nrecompute, (unsigned long long)nrec);
     // every workgroup has read the loop state (the barrier after the first
     // publish) before workgroup 0 writes it back
     if (wg == 0 && tid == 0) {
@@ -1676,18 +1778,18 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int cq, int crows, int launch)
     }
 }
 
-// LDS shape of the tail kernel from bounds on its trailing block (t_bound rows,
-// w_bound columns) and its grid; false when it does not fit.
+// Shape of the tail kernel from bounds on its trailing block (t_bound rows,
+// w_bound columns) and its grid: columns per workgroup and rows of a published
+// column; false when the block does not fit the registers of the grid.  The
+// kernel takes no dynamic LDS (bytes = 0).
 bool qp3_tail_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, int *crows, size_t *bytes) {
     if (grid < 1) return false;
     const int64_t rows = t_bound > 1 ? t_bound : 1;
     const int64_t q = w_bound > 0 ? (w_bound + grid - 1) / grid : 1;
-    if (rows > QT_ROWS_MAX || q > (int64_t)(QT_LDS_MAX / 8)) return false;
-    const size_t need = qt_lds_bytes((int)q, (int)rows);
-    if (need > QT_LDS_MAX) return false;
+    if (rows > QT_ROWS_MAX || q > QT_QMAX) return false;
     *cq = (int)q;
     *crows = (int)rows;
-    *bytes = need;
+    *bytes = 0;
     return true;
 }
 
@@ -1698,15 +1800,12 @@ size_t qp3_tail_pub_doubles(int64_t m) {
 }
 
 // One workgroup per compute unit (at most QP_RUN_MAXWG), all co-resident; 0
-// when the device cannot hold that grid with the kernel's LDS.
+// when the device cannot hold that grid.
 int qp3_tail_grid() {
     int dev = 0, ncu = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipFuncSetAttribute((const void *)k_qp_tail, hipFuncAttributeMaxDynamicSharedMemorySize, QT_LDS_MAX) !=
-        hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_tail, QT_THREADS, QT_LDS_MAX) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_qp_tail, QT_THREADS, 0) !=
             hipSuccess ||
         per_cu < 1)
         return 0;
@@ -1719,10 +1818,10 @@ hipError_t launch_qp3_tail(QrdmArgs a, double *pub, int32_t *flag, int64_t t_bou
     size_t lds = 0;
     if (grid < 1 || grid > QP_RUN_MAXWG || !qp3_tail_shape(t_bound, w_bound, grid, &cq, &crows, &lds))
         return hipErrorInvalidValue;
-    void *args[] = {&a, &pub, &flag, &cq, &crows, &launch};
+    void *args[] = {&a, &pub, &flag, &crows, &launch};
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    e = launch_resident((const void *)k_qp_tail, dim3(grid), dim3(QT_THREADS), args, (unsigned)lds, s);
+    e = launch_resident((const void *)k_qp_tail, dim3(grid), dim3(QT_THREADS), args, 0, s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     return hipSuccess;

@@ -344,7 +344,7 @@ int run_qp3(const QrdmArgs &a, char *ws, const Layout &L, int nb, int lag, int64
     const int64_t pmin = std::min(a.m, a.n);
     const char *mode = getenv("QRDM_QP3_STEPS");  // "1": the per-step kernels (comparison runs)
     const int grid = (mode && strcmp(mode, "1") == 0) ? 0 : qp3_block_grid(a.m);
-    // "0": no LDS-resident tail (comparison runs of the block kernel)
+    // "0": no register-resident tail (comparison runs of the block kernel)
     const char *tmode = getenv("QRDM_QP3_TAIL");
     const int tgrid = (grid > 0 && !(tmode && strcmp(tmode, "0") == 0)) ? qp3_tail_grid() : 0;
     if (grid > 0) {

@@ -240,8 +240,9 @@ hipError_t launch_qp3_step(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64
 int qp3_block_grid(int64_t m);
 hipError_t launch_qp3_block(QrdmArgs a, Qp3Bufs b, int nb, int64_t t_bound, int64_t w_bound, int grid,
                             int launch, hipStream_t s, hipEvent_t *ev = nullptr);  // ev[0], ev[1] around k_qp_run
-// LDS-resident tail of the column-pivoting loop: every remaining step in one
-// launch once the trailing block fits in the LDS of the grid (qp3_tail_shape).
+// Register-resident tail of the column-pivoting loop: every remaining step in
+// one launch once the trailing block fits in the registers of the grid (at most
+// 2048 rows and 8 columns per workgroup: qp3_tail_shape).
 int qp3_tail_grid();
 bool qp3_tail_shape(int64_t t_bound, int64_t w_bound, int grid, int *cq, int *crows, size_t *bytes);
 size_t qp3_tail_pub_doubles(int64_t m);

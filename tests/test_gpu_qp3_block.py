@@ -2,18 +2,20 @@
 to nb pivots per launch; the per-step kernels remain selectable
 (QRDM_QP3_STEPS=1).  Both carry out the same arithmetic in the same order, so
 pivots and rank must agree exactly and R / tau to rounding of the contraction
-(1e-13 relative); these comparisons switch the LDS-resident tail off
+(1e-13 relative); these comparisons switch the register-resident tail off
 (QRDM_QP3_TAIL=0).  The block kernel holds its columns in LDS when they fit
 (2048 rows at most) and reads them from memory otherwise: tall_2200x400
 starts in the second mode and ends in the first.  The block path is also
 checked against the oracle.
 
-Once the trailing block fits in the LDS of the grid, the loop hands every
-remaining step to one launch of the tail kernel (unblocked, one grid barrier
-per step): from the start on matrices of at most 2048 rows, after some block
-launches on taller ones (the hand-over finishes the block's last reflector
-and its flagged norms, or a stop inside the block).  It is checked against the
-oracle on the same cases."""
+Once the trailing block fits in the registers of the grid (at most 2048 rows
+and 8 columns per workgroup), the loop hands every remaining step to one
+launch of the tail kernel (unblocked, one grid barrier per step): from the
+start on matrices of at most 2048 rows and columns, after some block launches
+on taller ones (the hand-over finishes the block's last reflector and its
+flagged norms, or a stop inside the block); wide_150x3000 never fits and runs
+on block launches throughout.  It is checked against the oracle on the same
+cases."""
 import numpy as np
 import pytest
 
@@ -120,7 +122,7 @@ TAIL_CASES["graded_2200x300"] = lambda: _graded(2200, 300, 19)  # blocks with fl
 @pytest.mark.parametrize("name", sorted(TAIL_CASES))
 @pytest.mark.parametrize("rule", [oracle.STOP_PAPER, oracle.STOP_NONE, oracle.STOP_MAXNORM])
 def test_tail_kernel_matches_oracle(name, rule, monkeypatch):
-    """QRP with the LDS-resident tail (the default path) against the oracle."""
+    """QRP with the register-resident tail (the default path) against the oracle."""
     Q = _gpu()
     a = TAIL_CASES[name]()
     print(f"case {name} rule {rule}", flush=True)
