@@ -1334,6 +1334,19 @@ __device__ __forceinline__ double qt_pick(const double (&c)[QT_QMAX][QT_RPT], in
     return b2 ? (b1 ? y67 : y45) : (b1 ? y23 : y01);
 }
 
+// A published partial of the tail kernel is two 64-bit words, each with the
+// step's tag in its top 16 bits, so that a reader tells this step's words from
+// older ones without a barrier: word 0 = tag | position | high half of the
+// norm, word 1 = tag | column | low half of the norm (position and column
+// 0xffff: none).  Tags start at 1; the launch clears its slots first.
+__device__ __forceinline__ void qt_meta_put(uint64_t *me, uint32_t tag, double v, int pos, int col) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v), t = (uint64_t)(tag & 0xffff) << 48;
+    __hip_atomic_store(me, t | ((uint64_t)(pos & 0xffff) << 32) | (b >> 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(me + 1, t | ((uint64_t)(col & 0xffff) << 32) | (b & 0xffffffffull), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // x + y, where lanes with bit K of the lane index clear take x and the partner
 // lane's x (lane ^ K), the others y and the partner's y (K = 32 or 16): the
 // gfx950 lane swaps exchange the two halves of x and y in one step.
@@ -1395,6 +1408,7 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
     __shared__ double s_dp[QT_QMAX * QT_WAVES];  // per-wavefront sums of v^T c_k
     __shared__ double s_rp[QT_QMAX * QT_WAVES];  // per-wavefront sums of squares (recomputed norms)
     __shared__ double s_c0[QT_QMAX];      // row j of each column before H_j
+    __shared__ int s_fail;                // a partial did not arrive within the spin limit
     // loop state (identical in every workgroup)
     int64_t ns = ctl->ns, rank = ctl->rank, nblocks = ctl->nblocks, jm = ctl->jmax;
     const int64_t k0 = ctl->qp_k0;
@@ -1436,8 +1450,14 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
         if (wg == 0 && tid == 0) atomicOr(&ctl->error, 4);
         return;
     }
-    double *meta = pub;                           // [2][G][QT_META]
+    uint64_t *meta = (uint64_t *)pub;             // [2][G][QT_META]: tagged partials
     double *pdat = pub + 2 * (size_t)G * QT_META; // [2][G][crows]
+    if (tid < 2 * QT_META) {  // this workgroup's partial slots, both parities: no tag
+        const int par = tid / QT_META;
+        __hip_atomic_store(meta + ((size_t)par * G + wg) * QT_META + tid % QT_META, (uint64_t)0, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (tid == 0) s_fail = 0;
     // ---- this workgroup's columns, and lane k's column state
     // (every load issued before any is used: clamped addresses, then the selects)
     double c[QT_QMAX][QT_RPT];
@@ -1511,15 +1531,10 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
         const unsigned long long hold = __ballot(actv && n1v == bv && posv == bp);
         bk = hold ? __ffsll((long long)hold) - 1 : -1;
     };
-    // publishes the partial (norm, position, column) and rows rs .. t0 - 1
-    // (offsets from j0) of the local best column, into parity slot par
-    auto publish = [&](int par, int64_t rs, double bv, int bp, int bk) {
-        double *me = meta + ((size_t)par * G + wg) * QT_META;
-        if (tid == 0) {
-            qr_st(me, bv);
-            qr_st(me + 1, (double)bp);
-            qr_st(me + 2, bk >= 0 ? (double)(wg + G * bk) : -1.0);
-        }
+    // publishes rows rs .. t0 - 1 (offsets from j0) of the local best column
+    // and then, once those stores are complete, the partial (norm, position,
+    // column) with the step's tag, into parity slot par
+    auto publish = [&](int par, int64_t rs, uint32_t tag, double bv, int bp, int bk) {
         if (bk >= 0) {
             double *dst = pdat + ((size_t)par * G + wg) * crows;
 #pragma unroll
@@ -1529,14 +1544,18 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
                 if (r >= rs && r < t0) qr_st(dst + (r - rs), y);
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) qt_meta_put(meta + ((size_t)par * G + wg) * QT_META, tag, bv, bp, bk >= 0 ? wg + G * bk : -1);
     };
+    // the cleared slots are seen by every workgroup before any partial is published
+    gbar_wait(gb, G, ++bar, &ctl->error);
     {
         double bv;
         int bp, bk;
         local_best(bv, bp, bk);
-        publish(0, 0, bv, bp, bk);
+        publish(0, 0, 1, bv, bp, bk);
     }
-    gbar_wait(gb, G, ++bar, &ctl->error);
     // the slab of the rows above j0 whose R12 entries this workgroup swaps
     const int64_t ur = (j0 + G - 1) / G;
     const int64_t ur0 = (int64_t)wg * ur, ur1 = ur0 + ur < j0 ? ur0 + ur : j0;
@@ -1547,17 +1566,34 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
             if (rank < 0) rank = j;
             break;
         }
-        // ---- the pivot: the G partials of this step (s_v, s_j and s_k are
-        // written again only a step later, after the barriers below)
+        // ---- the pivot: the G partials of this step, each read until it
+        // carries this step's tag (s_v, s_j and s_k are written again only a
+        // step later, after the barriers below)
         double uv = -1.0;
         int up = 0x7fffffff, uc = -1;
         {
+            const uint32_t tag = (uint32_t)(j - j0 + 1);
             double bv = -1.0;
             int bp = 0x7fffffff, bc = -1;
             for (int w = tid; w < G; w += QT_THREADS) {
-                const double *me = meta + ((size_t)par * G + w) * QT_META;
-                const double v = qr_ld(me), pd = qr_ld(me + 1), cd = qr_ld(me + 2);
-                if (qp_better(v, (int)pd, bv, bp)) { bv = v; bp = (int)pd; bc = (int)cd; }
+                const uint64_t *me = meta + ((size_t)par * G + w) * QT_META;
+                uint64_t w0, w1;
+                for (int spin = 0;; ++spin) {
+                    w0 = __hip_atomic_load(me, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    w1 = __hip_atomic_load(me + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(w0 >> 48) == tag && (uint32_t)(w1 >> 48) == tag) break;
+                    if (spin > GBAR_SPIN_LIMIT) {
+                        atomicOr(&ctl->error, 2);
+                        s_fail = 1;
+                        w0 = w1 = 0xffffffffull << 32;  // no column
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                const double v = __longlong_as_double((long long)(((w0 & 0xffffffffull) << 32) | (w1 & 0xffffffffull)));
+                const int pd = (int)((w0 >> 32) & 0xffff), cd = (int)((w1 >> 32) & 0xffff);
+                const int pv = pd == 0xffff ? 0x7fffffff : pd;
+                if (qp_better(v, pv, bv, bp)) { bv = v; bp = pv; bc = cd == 0xffff ? -1 : cd; }
             }
             // (norm, position) is a total order: the winner's column rides along
             double vv = bv;
@@ -1572,6 +1608,10 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
             for (int w = 1; w < QT_WAVES; ++w)
                 if (qp_better(s_v[w], s_j[w], uv, up)) { uv = s_v[w]; up = s_j[w]; wsel = w; }
             uc = s_k[wsel];
+            if (s_fail) {  // the same in every thread
+                done = 1;
+                break;
+            }
         }
         // ---- stopping test (as k_qp_select)
         if (nblocks == 0 && j == 0) amax = uv;
@@ -1625,20 +1665,6 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
             posv = rj;
         } else if (jm != j && actv && posv == rj) {
             posv = up;
-        }
-        // ---- the swap of positions j and jm in this workgroup's slab of the
-        // rows above j0, and in the permutation (workgroup 0)
-        if (jm != j) {
-            for (int64_t r = ur0 + tid; r < ur1; r += QT_THREADS) {
-                const double x1 = a.A[j * a.lda + r], x2 = a.A[jm * a.lda + r];
-                a.A[j * a.lda + r] = x2;
-                a.A[jm * a.lda + r] = x1;
-            }
-            if (wg == 0 && tid == 0) {
-                const int32_t p1 = a.perm[j], p2 = a.perm[jm];
-                a.perm[j] = p2;
-                a.perm[jm] = p1;
-            }
         }
         // ---- the reflector (larfg): alpha is row j, sp the sum of squares below it
         double sp = 0.0, xa = 0.0;
@@ -1731,14 +1757,28 @@ k_qp_tail(QrdmArgs a, double *pub, int32_t *flag, int crows, int launch) {
         }
         const uint32_t nm = (uint32_t)__ballot(nd);
         if (nm) recompute(nm, rj + 1);  // from the rows below j
-        // ---- publish for the step at j + 1, then the barrier
+        // ---- publish for the step at j + 1
         {
             double bv;
             int bp, bk;
             local_best(bv, bp, bk);
-            publish(par ^ 1, rj + 1, bv, bp, bk);
+            publish(par ^ 1, rj + 1, (uint32_t)(rj + 2), bv, bp, bk);
         }
-        gbar_wait(gb, G, ++bar, &ctl->error);
+        // ---- the swap of positions j and jm in this workgroup's slab of the
+        // rows above j0, and in the permutation (workgroup 0), off the path of
+        // the next step's pivot
+        if (jm != j) {
+            for (int64_t r = ur0 + tid; r < ur1; r += QT_THREADS) {
+                const double x1 = a.A[j * a.lda + r], x2 = a.A[jm * a.lda + r];
+                a.A[j * a.lda + r] = x2;
+                a.A[jm * a.lda + r] = x1;
+            }
+            if (wg == 0 && tid == 0) {
+                const int32_t p1 = a.perm[j], p2 = a.perm[jm];
+                a.perm[j] = p2;
+                a.perm[jm] = p1;
+            }
+        }
         j += 1;
     }
     // ---- the columns not pivoted (a stop): back to their final positions
