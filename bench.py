@@ -43,8 +43,8 @@ def flops_cols(m, n, r):
     return float(np.sum(4.0 * (m - s) * (n - s)))
 
 
-KERNEL_SOURCES = {"k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip", "k_qp_run": "k_qp3.hip",
-                  "k_qp_tail": "k_qp3.hip"}
+KERNEL_SOURCES = {"k_gemm1": "k_trail.hip", "k_gemm2": "k_trail.hip", "k_gemm2p": "k_trail.hip",
+                  "k_qp_run": "k_qp3.hip", "k_qp_tail": "k_qp3.hip"}
 
 
 def source_sha(kernel):
@@ -73,7 +73,7 @@ def measured_traffic(kernel, workload_tag):
         return None
 
 
-def roofline(prof, prec, Q, workload_tag=None):
+def roofline(prof, prec, Q, workload_tag=None, kmax=64):
     """Roofline of the kernel with the largest summed time among the column-
     pivoting kernel and the two trailing GEMMs (the panel and the DM selection
     are chains of short single-workgroup and grid launches, reported in
@@ -81,10 +81,13 @@ def roofline(prof, prec, Q, workload_tag=None):
     trailing matrix per pivot: 2 flop per 8 B) is HBM-bound; at 8192^2 the whole
     tail is one launch of the register-resident k_qp_tail, otherwise block launches
     of k_qp_run.  The trailing GEMMs are MFMA-bound; GEMM1's time includes the
-    partial sum and Z = T^T Y (k_zsum) between the same events."""
+    partial sum and Z = T^T Y (k_zsum) between the same events.  GEMM2 is the
+    persistent k_gemm2p for FP64 blocks of at most 64 reflectors, k_gemm2
+    otherwise."""
     qp_name = "k_qp_tail" if int(prof.get("nqp3_tail", 0)) > 0 and int(prof.get("nqp3_launch", 0)) == 1 \
         else "k_qp_run"
-    times = {qp_name: prof.get("qp3_run_ms", 0.0), "k_gemm1": prof["gemm1_ms"], "k_gemm2": prof["gemm2_ms"]}
+    g2_name = "k_gemm2p" if prec != Q.PREC_MIXED and kmax <= 64 else "k_gemm2"
+    times = {qp_name: prof.get("qp3_run_ms", 0.0), "k_gemm1": prof["gemm1_ms"], g2_name: prof["gemm2_ms"]}
     dom = max(times, key=times.get)
     nlaunch = max(int(prof["npanel"]), 1)  # one launch of each GEMM per block
     if dom in ("k_qp_run", "k_qp_tail"):
@@ -464,7 +467,7 @@ def main():
     roof = None
     if not args.no_profile_run:
         prof = step(profile=True).stats
-        roof = roofline(prof, prec, Q, tag)
+        roof = roofline(prof, prec, Q, tag, args.kmax)
     rank = outs[-1].rank
     st = outs[-1].stats
 

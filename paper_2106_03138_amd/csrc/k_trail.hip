@@ -15,7 +15,10 @@
 //            T^{-1} = diag(1/tau) + strict_upper(V^T V), Z solves the lower
 //            recurrence Z_a = tau_a (Y_a - sum_{b<a} (v_b^T v_a) Z_b) (Z_a = 0
 //            when tau_a = 0, the identity reflector);
-//   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once.
+//   k_gemm2  A_tr -= V Z on 128 x 128 tiles, A read once and written once;
+//            for FP64 blocks of at most 64 reflectors the persistent k_gemm2p
+//            (one workgroup per compute unit, V and Z of a tile whole in LDS,
+//            the next tile's A and Z loaded during the current tile's MFMAs).
 // Precision: FP64 MFMA (16x16x4 f64) by default; mixed mode runs both products
 // on FP32 MFMA with FP32 accumulation while A stays FP64 in memory and Z is
 // formed in FP64.
@@ -552,6 +555,132 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
         }
 }
 
+// A_tr -= V Z for an FP64 QRDM block of at most 64 reflectors, persistent:
+// one workgroup of 1024 threads per compute unit takes a run of 128 x 128
+// tiles (the tiles in row-major order, split evenly over the grid), so that
+// its tiles share a row of tiles.  V's rows of that tile row and Z's columns of
+// the tile are staged whole in LDS (all l reflectors), so the MFMA loop reads
+// no global memory, and the next tile's A and Z are loaded into registers while
+// the current tile's MFMAs run.  Wavefront w takes the 32 x 32 block at rows
+// 32 (w / 4), columns 32 (w % 4) of the tile; the products are k_gemm2's
+// (D = Z^T V^T, the accumulators starting as the A tile, the same order over k).
+#define G2P_KMAX 64
+#define G2P_TH 1024
+#define G2P_LD (G2_MT + 8)  // LDS row of the staged V and Z (doubles); the 8 spread the banks
+#define G2P_LDS ((size_t)2 * G2P_KMAX * G2P_LD * sizeof(double))
+__global__ void __launch_bounds__(G2P_TH) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_gemm2p(QrdmArgs a, const double *__restrict__ V, int64_t ldv, const double *__restrict__ Z, int64_t ldz) {
+    const QrdmCtl *ctl = a.ctl;
+    if (qrdm_dm_idle(ctl)) return;
+    const int64_t ns = ctl->ns, c0 = ctl->ns + ctl->c0off;  // c0off: k_s, or l after the Gram-matrix panel
+    const int l = ctl->l;
+    const int64_t t = a.m - ns, w2 = a.n - c0;
+    if (l <= 0 || t <= 0 || w2 <= 0) return;
+    if (l > G2P_KMAX) {  // the host takes this kernel for k_DM <= 64 only (cannot happen)
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.ctl->error, 4);
+        return;
+    }
+    const int64_t ntc = (w2 + G2_NT - 1) / G2_NT, ntiles = ((t + G2_MT - 1) / G2_MT) * ntc;
+    const int64_t tb = ntiles * blockIdx.x / gridDim.x, te = ntiles * (blockIdx.x + 1) / gridDim.x;
+    if (tb >= te) return;
+    extern __shared__ double g2p_lds[];
+    double *Vs = g2p_lds;                 // [k][row]
+    double *Zs = Vs + G2P_KMAX * G2P_LD;  // [k][col]
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = (wv >> 2) * 32, wc = (wv & 3) * 32;  // wave's 32 x 32 block (rows, cols)
+    const int rj = lane & 15;
+    const int lk = (l + 15) & ~15;  // reflectors in whole 16-chunks (zeros past l)
+    typedef Mfma<double>::acc_t acc_t;
+    // Addresses as a part common to the wavefront plus one 32-bit offset per
+    // thread (the host takes this kernel when 128 lda, 64 ldv and 64 ldz fit).
+    // A of a tile in the accumulator layout: (tc, tr) register v holds
+    // A[row wr + 16 tr + rj][col wc + 16 tc + 4 v + lane / 16] (Mfma::row).
+    const int lda = (int)a.lda, ldvi = (int)ldv, ldzi = (int)ldz;
+    const int aoff = (lane >> 4) * lda + wr + rj;           // + 16 tr, + (wc + 16 tc + 4 v) lda
+    const int koff = (tid >> 7), coff = tid & 127;          // staged element u G2P_TH + tid: (8 u + koff, coff)
+    auto a_load = [&](int64_t tile, double (&x)[16]) {
+        const int64_t rb = (tile / ntc) * G2_MT, jb = (tile % ntc) * G2_NT;
+        const int nrow = (int)((t - rb) < G2_MT ? (t - rb) : G2_MT);
+        const int ncol = (int)((w2 - jb) < G2_NT ? (w2 - jb) : G2_NT);
+        const double *Ab = a.A + (c0 + jb) * a.lda + ns + rb;
+#pragma unroll
+        for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int cu = wc + tc * 16 + 4 * v;
+                const double *pc = Ab + (int64_t)cu * lda;
+                const bool cok = cu + (lane >> 4) < ncol;
+#pragma unroll
+                for (int tr = 0; tr < 2; ++tr)
+                    x[(tc * 2 + tr) * 4 + v] = (cok && wr + tr * 16 + rj < nrow) ? pc[aoff + tr * 16] : 0.0;
+            }
+    };
+    auto z_load = [&](int64_t tile, double (&z)[8]) {
+        const int64_t jb = (tile % ntc) * G2_NT;
+        const int ncol = (int)((w2 - jb) < G2_NT ? (w2 - jb) : G2_NT);
+        const double *Zb = Z + jb + koff * ldzi + coff;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            z[u] = (8 * u + koff < l && coff < ncol) ? Zb[8 * u * ldzi] : 0.0;
+    };
+    double apf[16], zpf[8];
+    a_load(tb, apf);
+    z_load(tb, zpf);
+    int64_t vrow = -1;
+    for (int64_t tile = tb; tile < te; ++tile) {
+        const int64_t trow = tile / ntc, rb = trow * G2_MT, jb = (tile % ntc) * G2_NT;
+        const int nrow = (int)((t - rb) < G2_MT ? (t - rb) : G2_MT);
+        const int ncol = (int)((w2 - jb) < G2_NT ? (w2 - jb) : G2_NT);
+        if (trow != vrow) {  // V's rows of this tile row (all reflectors), once per row of tiles
+            const double *Vb = V + rb + koff * ldvi + coff;
+            double vr[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vr[u] = (8 * u + koff < l && coff < nrow) ? Vb[8 * u * ldvi] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) Vs[(8 * u + koff) * G2P_LD + coff] = vr[u];
+            vrow = trow;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Zs[(8 * u + koff) * G2P_LD + coff] = zpf[u];
+        acc_t acc[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][v] = apf[i * 4 + v];
+        __syncthreads();
+        if (tile + 1 < te) {  // the next tile's operands, in flight during the MFMAs
+            a_load(tile + 1, apf);
+            z_load(tile + 1, zpf);
+        }
+        for (int k = 0; k < lk; k += 4) {
+            double zo[2], vo[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) zo[u] = -Zs[(k + (lane >> 4)) * G2P_LD + wc + u * 16 + rj];  // A-operand: -Z^T[i][k]
+#pragma unroll
+            for (int u = 0; u < 2; ++u) vo[u] = Vs[(k + (lane >> 4)) * G2P_LD + wr + u * 16 + rj];  // B: V^T[k][j]
+#pragma unroll
+            for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+                for (int tr = 0; tr < 2; ++tr) acc[tc * 2 + tr] = Mfma<double>::op(zo[tc], vo[tr], acc[tc * 2 + tr]);
+        }
+        double *Ab = a.A + (c0 + jb) * a.lda + ns + rb;
+#pragma unroll
+        for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int cu = wc + tc * 16 + 4 * v;
+                double *pc = Ab + (int64_t)cu * lda;
+                if (cu + (lane >> 4) < ncol) {
+#pragma unroll
+                    for (int tr = 0; tr < 2; ++tr)
+                        if (wr + tr * 16 + rj < nrow) pc[aoff + tr * 16] = acc[tc * 2 + tr][v];
+                }
+            }
+        __syncthreads();  // Vs and Zs read before the next tile writes them
+    }
+}
+
 // Rows of the V^T A partials per split (k_DM rounded up to the 16-row MFMA
 // tiles) times the n columns: the stride between the splits in Yp.
 int64_t trail_ysplit(int kmax, int64_t n) {
@@ -589,7 +718,17 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     const size_t epi_xt = ((size_t)3 * 64 * ZT_LD + 64) * sizeof(double);
     const size_t epi_b = epi_rec > epi_xt ? epi_rec : epi_xt;
     static bool attr = false;
+    static int g2p_grid = 0;  // one workgroup per compute unit; 0: the tiled k_gemm2 instead
     if (!attr) {
+        int dev = 0, ncu = 0, per_cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipFuncSetAttribute((const void *)k_gemm2p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G2P_LDS) ==
+                hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gemm2p, G2P_TH, G2P_LDS) == hipSuccess &&
+            per_cu >= 1)
+            g2p_grid = ncu;
+        (void)hipGetLastError();
         const void *fs[6] = {(const void *)k_gemm1<double>,     (const void *)k_gemm1<float>,
                              (const void *)k_zsum<double, 32>, (const void *)k_zsum<double, 64>,
                              (const void *)k_zsum<float, 32>,  (const void *)k_zsum<float, 64>};
@@ -615,7 +754,10 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     }
     if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);
-    if (precision == 0)
+    if (precision == 0 && a.kmax <= G2P_KMAX && g2p_grid > 0 && a.lda <= (INT32_MAX / G2_NT) && ldv <= (INT32_MAX / 64) &&
+        ldz <= (INT32_MAX / 64))
+        hipLaunchKernelGGL(k_gemm2p, dim3((unsigned)g2p_grid), dim3(G2P_TH), G2P_LDS, s, a, Vw, ldv, (const double *)Z, ldz);
+    else if (precision == 0)
         hipLaunchKernelGGL((k_gemm2<double, 0>), g2, dim3(512), 0, s, a, Vw, ldv, (const double *)Z, ldz);
     else
         hipLaunchKernelGGL((k_gemm2<float, 0>), g2, dim3(512), 0, s, a, Vw32, ldv, (const float *)Z, ldz);
