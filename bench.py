@@ -258,6 +258,25 @@ def learned_leg(args, torch, Q, b, pristine, shapes, default_ms):
         torch.cuda.synchronize()
         times.append(1e3 * (time.perf_counter() - t0))
     ms = float(np.median(times))
+    # the breakdown: each stage between synchronizations, and the per-matrix
+    # clock ticks of the batched kernel with the predicted and the default
+    # parameters (the persistent launch lasts as long as its longest workgroup)
+    bd = {}
+    b.data.copy_(pristine)
+    Ld.predict_factor(b, plan, model, pristine, breakdown=bd)
+    tk_p = bd.pop("ticks").double()
+    b.data.copy_(pristine)
+    info = torch.zeros(4 * max(len(b), 1), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.factor(info=info)
+    torch.cuda.synchronize()
+    dflt_ms = 1e3 * (time.perf_counter() - t0)
+    tk_d = info.view(-1, 4)[:, 3].double()
+    breakdown = {k: round(v, 3) for k, v in bd.items()}
+    breakdown.update({"default_factor_ms": round(dflt_ms, 3),
+                      "ticks_sum_predicted_over_default": round(float(tk_p.sum() / tk_d.sum()), 4),
+                      "ticks_max_predicted_over_default": round(float(tk_p.max() / tk_d.max()), 4)})
     pm = Ld.predict_params(plan, model).cpu().numpy().view(
         np.dtype([("tau", "<f8"), ("delta", "<f8"), ("kmax", "<i4"), ("pad", "<i4")]))
     import collections
@@ -269,6 +288,7 @@ def learned_leg(args, torch, Q, b, pristine, shapes, default_ms):
             "fallbacks": nfb,
             "matrices_per_s": round(len(shapes) / (ms * 1e-3), 1), "quality": qual,
             "most_common_params": [[float(t), float(d), int(k), c] for (t, d, k), c in common],
+            "breakdown": breakdown,
             "timing": "wall clock around features + MLP + factorization + check + fallback (eager)"}
 
 

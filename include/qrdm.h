@@ -326,7 +326,9 @@ const char *qrdm_strerror(int code);
 #define QRDM_BATCH_CLASSES 4 /* size classes: m <= 64, <= 128, <= 256, > 256 */
 
 /* Per-matrix method parameters (device array, optional): tau, delta and k_DM
- * as in qrdm_params; used by the learned parameter predictor. */
+ * as in qrdm_params; used by the learned parameter predictor.  k_DM = 0 leaves
+ * the matrix as it is (A, tau_house, perm, rank, status and info untouched), so
+ * that some matrices of a plan can be factored again without a new plan. */
 typedef struct {
     double tau;
     double delta;

@@ -479,6 +479,10 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
             tau = q.pm[mi].tau;
             delta = q.pm[mi].delta;
             kmax = q.pm[mi].kmax;
+            if (kmax == 0) {  // this matrix is left as it is (the same in every thread)
+                __syncthreads();  // every thread has read S.idx before thread 0 takes the next
+                continue;
+            }
         }
         kmax = kmax < 1 ? 1 : (kmax > QB_KM ? QB_KM : kmax);  // the per-block arrays hold QB_KM
         const int p = m < n ? m : n;

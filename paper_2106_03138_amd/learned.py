@@ -167,27 +167,52 @@ def predict_params(plan: BatchPlan, model: Model):
 
 
 def predict_factor(batch: Batch, plan: BatchPlan, model: Model, pristine, band: float = 0.1,
-                   use_graph: bool = False):
+                   use_graph: bool = False, breakdown: dict = None):
     """Predicted parameters, factorization, online check, and a second
     factorization with the defaults for every matrix that fails the check.
     pristine: a copy of batch.data before the call (the factorization is in place).
+    breakdown: when a dict, the device is synchronized after each stage and the
+    stage times (ms) are stored in it, with the factorization's per-matrix
+    clock ticks ("ticks": int64 device tensor).
     Returns (params, number of fallbacks)."""
     import torch
+    clock = [time.perf_counter()]
+
+    def stage(name):
+        if breakdown is not None:
+            torch.cuda.synchronize()
+            now = time.perf_counter()
+            breakdown[name] = 1e3 * (now - clock[0])
+            clock[0] = now
+
+    if breakdown is not None:
+        torch.cuda.synchronize()
+        clock[0] = time.perf_counter()
     pm = predict_params(plan, model)
-    plan.factor(params=pm, use_graph=use_graph)
+    stage("features_mlp_snap_ms")
+    info = torch.zeros(4 * max(len(batch), 1), dtype=torch.int64, device="cuda") if breakdown is not None else None
+    plan.factor(params=pm, use_graph=use_graph, info=info)
+    stage("factor_ms")
+    if info is not None:
+        breakdown["ticks"] = info.view(-1, 4)[:, 3]
     ok, _ = plan.check(band)
     bad = torch.nonzero(ok == 0).flatten().cpu().numpy()
+    stage("check_ms")
     if len(bad):
-        sub = batch.subset(bad)
+        # the failures again with the defaults, through the same plan: per-matrix
+        # parameters with k_DM = 0 (left as it is) for every other matrix
         for i in bad:
             s0, s1 = int(batch.off[i]), int(batch.off[i + 1])
             batch.data[s0:s1].copy_(pristine[s0:s1])
         t, d, k = DEFAULT
-        subplan = BatchPlan(sub, tau=t, delta=d, kmax=k)
-        subplan.factor()
-        batch.rank[torch.as_tensor(bad).cuda()] = sub.rank[: len(bad)]
-        batch.status[torch.as_tensor(bad).cuda()] = sub.status[: len(bad)]
-        subplan.close()
+        pm2 = torch.zeros_like(pm)
+        sel = torch.as_tensor(bad, dtype=torch.int64, device=pm.device)
+        f64, i32 = pm2.view(torch.float64).view(-1, 3), pm2.view(torch.int32).view(-1, 6)
+        f64[sel, 0] = t
+        f64[sel, 1] = d
+        i32[sel, 4] = k
+        plan.factor(params=pm2)
+    stage("rerun_ms")
     return pm, len(bad)
 
 
