@@ -80,8 +80,9 @@ def roofline(prof, prec, Q, workload_tag=None, kmax=64):
     phase_ms).  The column-pivoting kernel (one matrix-vector product over the
     trailing matrix per pivot: 2 flop per 8 B) is HBM-bound; at 8192^2 the whole
     tail is one launch of the register-resident k_qp_tail, otherwise block launches
-    of k_qp_run.  The trailing GEMMs are MFMA-bound; GEMM1's time includes the
-    partial sum and Z = T^T Y (k_zsum) between the same events.  GEMM2 is the
+    of k_qp_run.  The trailing GEMMs are timed alone (the partial sum and
+    Z = T^T Y of k_zsum between them is reported apart); GEMM1 (8 B read per
+    2 l flop) is MFMA-bound, GEMM2 (16 B per 2 l flop) close to the ridge.  GEMM2 is the
     persistent k_gemm2p for FP64 blocks of at most 64 reflectors, k_gemm2
     otherwise."""
     qp_name = "k_qp_tail" if int(prof.get("nqp3_tail", 0)) > 0 and int(prof.get("nqp3_launch", 0)) == 1 \
@@ -106,11 +107,15 @@ def roofline(prof, prec, Q, workload_tag=None, kmax=64):
             "launches": nlaunch, "avg_launch_us": round(1e3 * times[dom] / nlaunch, 2),
             "algorithmic_per_launch": work / nlaunch,
             "phase_ms": {"dm_select": round(prof["dm_ms"], 3), "panel": round(prof["panel_ms"], 3),
-                         "gemm1": round(prof["gemm1_ms"], 3), "gemm2": round(prof["gemm2_ms"], 3),
+                         "gemm1": round(prof["gemm1_ms"], 3), "zsum": round(prof.get("zsum_ms", 0.0), 3),
+                         "gemm2": round(prof["gemm2_ms"], 3),
                          "downdate": round(prof["downdate_ms"], 3), "qp3_tail": round(prof["qp3_ms"], 3),
                          "qp3_kernel": round(prof.get("qp3_run_ms", 0.0), 3),
                          "loop_total": round(prof["total_ms"], 3)},
-            "gemm_tflops": {"gemm1_with_zsum": round(prof["gemm_flop"] / (prof["gemm1_ms"] * 1e-3) / 1e12, 3)
+            "gemm_tflops": {"gemm1": round(prof["gemm_flop"] / (prof["gemm1_ms"] * 1e-3) / 1e12, 3)
+                            if prof["gemm1_ms"] > 0 else None,
+                            "gemm1_with_zsum": round(prof["gemm_flop"] / ((prof["gemm1_ms"] + prof.get("zsum_ms", 0.0))
+                                                                          * 1e-3) / 1e12, 3)
                             if prof["gemm1_ms"] > 0 else None,
                             "gemm2": round(prof["gemm_flop"] / (prof["gemm2_ms"] * 1e-3) / 1e12, 3)
                             if prof["gemm2_ms"] > 0 else None}}

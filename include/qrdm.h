@@ -108,7 +108,7 @@ typedef struct {
     int64_t nrecompute;  /* partial norms recomputed from the data                        */
     int64_t ncols_factored; /* number of reflectors applied                               */
     /* filled when params.profile = 1 (zero otherwise):                                    */
-    double gemm1_ms;     /* summed event time of the V^T A GEMM launches                   */
+    double gemm1_ms;     /* summed event time of the V^T A GEMM launches (k_gemm1 alone)    */
     double gemm2_ms;     /* summed event time of the A -= V Z GEMM launches                */
     double gemm_flop;    /* algorithmic flops of ONE of the two GEMMs, summed over blocks:
                             sum 2 t l w (t rows, l reflectors, w trailing columns)         */
@@ -136,6 +136,8 @@ typedef struct {
                             kernel, which takes every step left once the trailing block has
                             at most 2048 rows and 8 columns per compute unit (0 or 1;
                             profile = 1)                                                     */
+    double zsum_ms;      /* summed event time of the partial sums of V^T A and Z = T^T Y
+                            (k_zsum, between the two GEMMs; profile = 1)                    */
 } qrdm_stats;
 
 /* One record per outer step of the DM loop, for tests and tracing.  When the

@@ -31,7 +31,7 @@ class Stats(ctypes.Structure):
                 ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64),
                 ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64),
                 ("qp3_start", ctypes.c_int64), ("ngram", ctypes.c_int64),
-                ("nqp3_tail", ctypes.c_int64)]
+                ("nqp3_tail", ctypes.c_int64), ("zsum_ms", ctypes.c_double)]
 
 
 class Block(ctypes.Structure):

@@ -745,14 +745,15 @@ hipError_t launch_trail(QrdmArgs a, int precision, const double *VV, const doubl
     if (ev) (void)hipEventRecord(ev[0], s);
     if (precision == 0) {
         hipLaunchKernelGGL(k_gemm1<double>, g1, dim3(G1_TH), main_b, s, a, Vw, ldv, Yp, ldz, ysplit);
+        if (ev) (void)hipEventRecord(ev[1], s);
         if (z32) hipLaunchKernelGGL((k_zsum<double, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (double *)Z, ldz, ysplit);
         else hipLaunchKernelGGL((k_zsum<double, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (double *)Z, ldz, ysplit);
     } else {
         hipLaunchKernelGGL(k_gemm1<float>, g1, dim3(G1_TH), main_b, s, a, Vw32, ldv, Yp, ldz, ysplit);
+        if (ev) (void)hipEventRecord(ev[1], s);
         if (z32) hipLaunchKernelGGL((k_zsum<float, 32>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (float *)Z, ldz, ysplit);
         else hipLaunchKernelGGL((k_zsum<float, 64>), gz, dim3(G1_TH), epi_b, s, a, VV, cpT, (const double *)Yp, (float *)Z, ldz, ysplit);
     }
-    if (ev) (void)hipEventRecord(ev[1], s);
     if (ev) (void)hipEventRecord(ev[2], s);
     if (precision == 0 && a.kmax <= G2P_KMAX && g2p_grid > 0 && a.lda <= (INT32_MAX / G2_NT) && ldv <= (INT32_MAX / 64) &&
         ldz <= (INT32_MAX / 64))

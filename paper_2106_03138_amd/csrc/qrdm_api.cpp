@@ -444,10 +444,12 @@ void prof_fill(const ProfRun &prof, PollCtx &pc, const QrdmCtl &cf, int64_t m, i
             if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) == hipSuccess) t[e] += ms;
         }
     }
-    // intervals (e, e+1): 0 DM selection, 1 panel, 3 GEMM1 (with Z), 5 GEMM2, 6 downdate
+    // intervals (e, e+1): 0 DM selection, 1 panel, 3 GEMM1, 4 partial sum and Z,
+    // 5 GEMM2, 6 downdate
     st->dm_ms = t[0];
     st->panel_ms = t[1];
     st->gemm1_ms = t[3];
+    st->zsum_ms = t[4];
     st->gemm2_ms = t[5];
     st->downdate_ms = t[6];
     st->gemm_flop = cf.flop_gemm;
