@@ -138,6 +138,8 @@ typedef struct {
                             profile = 1)                                                     */
     double zsum_ms;      /* summed event time of the partial sums of V^T A and Z = T^T Y
                             (k_zsum, between the two GEMMs; profile = 1)                    */
+    double gemm2_bytes;  /* algorithmic bytes of the A -= V Z GEMM, summed over blocks:
+                            sum 16 t w (A read and written once; profile = 1)               */
 } qrdm_stats;
 
 /* One record per outer step of the DM loop, for tests and tracing.  When the
@@ -381,6 +383,22 @@ int qrdm_batch_plan_create(const int32_t *m, const int32_t *n, const int32_t *ld
 int qrdm_batch_factor(qrdm_batch_plan *plan, double *const *A, double *const *tau_house, int32_t *const *perm,
                       int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info,
                       int32_t use_graph, void *stream);
+
+/* qrdm_batch_factor with per-matrix parameters pm (required) and the online
+ * check of qrdm_batch_check (Section 5's factor-10 rule, band = 0.1) taken in
+ * the same launch: a matrix whose factorization fails the check is restored
+ * from its pristine copy and factored again with the plan's parameters by the
+ * workgroup that factored it, while the other workgroups keep working.
+ * pristine: DEVICE array of `batch` device pointers, matrix i an unmodified
+ * copy of A[i] with the same leading dimension (read only).  ok: DEVICE array
+ * of `batch` int32: 1 = factored with pm[i] and kept, 0 = factored again with
+ * the plan's parameters.  Other arguments and the stream as in
+ * qrdm_batch_factor (no graph capture).  Returns -2 for a missing array, -9
+ * for band < 0 or NaN. */
+int qrdm_batch_factor_checked(qrdm_batch_plan *plan, double *const *A, double *const *tau_house,
+                              int32_t *const *perm, int64_t *rank, int32_t *status, const qrdm_batch_params *pm,
+                              const double *const *pristine, double band, int32_t *ok, int64_t *info,
+                              void *stream);
 
 /* Frees the plan, its device arrays and graphs (synchronizes the device). */
 void qrdm_batch_plan_destroy(qrdm_batch_plan *plan);

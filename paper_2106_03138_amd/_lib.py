@@ -31,7 +31,7 @@ class Stats(ctypes.Structure):
                 ("panel_bytes", ctypes.c_double), ("npanel", ctypes.c_int64),
                 ("qp3_run_ms", ctypes.c_double), ("qp3_bytes", ctypes.c_double), ("nqp3_launch", ctypes.c_int64),
                 ("qp3_start", ctypes.c_int64), ("ngram", ctypes.c_int64),
-                ("nqp3_tail", ctypes.c_int64), ("zsum_ms", ctypes.c_double)]
+                ("nqp3_tail", ctypes.c_int64), ("zsum_ms", ctypes.c_double), ("gemm2_bytes", ctypes.c_double)]
 
 
 class Block(ctypes.Structure):
@@ -82,6 +82,8 @@ SIGNATURES = {
     "qrdm_batch_plan_create": (ctypes.c_int, [_P(_i32), _P(_i32), _P(_i32), _i32, _P(Params), _P(BatchTune),
                                               _P(_vp)]),
     "qrdm_batch_factor": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "qrdm_batch_factor_checked": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp,
+                                                 _vp]),
     "qrdm_batch_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "qrdm_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     "qrdm_mlp_gradient": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),

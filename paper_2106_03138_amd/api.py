@@ -297,6 +297,13 @@ class Batch:
     def __len__(self):
         return len(self.shapes)
 
+    def pointers(self, t):
+        """Device array of per-matrix pointers into t, a tensor laid out like
+        self.data (e.g. a pristine copy made with data.clone())."""
+        torch = _torch()
+        base = t.data_ptr()
+        return torch.tensor([base + 8 * int(o) for o in self.off[:-1]] or [0], dtype=torch.int64, device=t.device)
+
     def load(self, mats):
         """Copy host matrices (numpy, any order) into the device buffer."""
         torch = _torch()
@@ -427,6 +434,27 @@ class BatchPlan:
                                              ctypes.c_void_p(bt.status.data_ptr()), pm, inf, 1 if use_graph else 0,
                                              _stream_ptr(stream))
         _lib.check("qrdm_batch_factor", code)
+
+    def factor_checked(self, params, pristine_ptrs, band: float = 0.1, stream=None, info=None):
+        """Factor with per-matrix parameters and the online check in the same
+        launch (qrdm_batch_factor_checked): a matrix that fails the check is
+        restored from pristine and factored again with the plan's parameters.
+        pristine_ptrs: Batch.pointers(pristine).  Returns ok (int32 device
+        tensor: 1 = kept, 0 = factored again)."""
+        torch = _torch()
+        bt = self.batch
+        ok = torch.zeros(max(len(bt), 1), dtype=torch.int32, device=bt.data.device)
+        inf = ctypes.c_void_p(info.data_ptr()) if info is not None else None
+        code = _lib.load().qrdm_batch_factor_checked(self._ptr, ctypes.c_void_p(bt.a_ptr.data_ptr()),
+                                                     ctypes.c_void_p(bt.t_ptr.data_ptr()),
+                                                     ctypes.c_void_p(bt.p_ptr.data_ptr()),
+                                                     ctypes.c_void_p(bt.rank.data_ptr()),
+                                                     ctypes.c_void_p(bt.status.data_ptr()),
+                                                     ctypes.c_void_p(params.data_ptr()),
+                                                     ctypes.c_void_p(pristine_ptrs.data_ptr()), float(band),
+                                                     ctypes.c_void_p(ok.data_ptr()), inf, _stream_ptr(stream))
+        _lib.check("qrdm_batch_factor_checked", code)
+        return ok[: len(bt)]
 
     def lstsq(self, rhs: BatchRHS, stream=None):
         """Basic least-squares solutions of the factored batch (qrdm_batch_lstsq)."""

@@ -77,6 +77,7 @@ struct QbShared {
     double umax, amax, eps_s, beta, tau_i, den;
     int64_t rank;
     int ns, l, ks, nL, nsw, nround, go, fb, idx, ncand, nstep, nbreak, nfb;
+    int redo, dflt, okv;  // checked form: factor the same matrix again with the plan's parameters
     int64_t t0;
 };
 
@@ -463,10 +464,20 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
     const double eps_w = DBL_EPSILON;
     const double tol3z = sqrt(eps_w);
 
+    if (tid == 0) S.redo = 0;
     for (;;) {
-        if (tid == 0) S.idx = (int)atomicAdd(&q.counters[0], 1u);
+        if (tid == 0) {
+            if (S.redo) {  // the matrix that failed the check, again with the plan's parameters
+                S.redo = 0;
+                S.dflt = 1;
+            } else {
+                S.idx = (int)atomicAdd(&q.counters[0], 1u);
+                S.dflt = 0;
+            }
+        }
         __syncthreads();
         const int qi = S.idx;
+        const bool dflt = S.dflt != 0;
         if (qi >= q.count) break;
         const int mi = q.order[qi];
         double *A = q.A[mi];
@@ -475,7 +486,7 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
         int32_t *perm = q.perm[mi];
         double tau = q.tau, delta = q.delta;
         int kmax = q.kmax;
-        if (q.pm) {
+        if (q.pm && !dflt) {
             tau = q.pm[mi].tau;
             delta = q.pm[mi].delta;
             kmax = q.pm[mi].kmax;
@@ -781,6 +792,32 @@ __global__ void __launch_bounds__(NT) k_qrdm_batched(QbArgs q) {
             }
         }
         sync_global();
+        if (q.pristine && q.pm && !dflt) {
+            // the online check (as qrdm_batch_check) on wavefront 0; a failure is
+            // restored from its pristine copy and factored again at the loop top
+            if (wv == 0) {
+                int64_t r = S.rank >= 0 ? S.rank : (amax > 0.0 ? S.ns : 0);
+                if (r > p) r = p;
+                int okv = 1;
+                if (r > 0) {
+                    double dmin;
+                    const double est = qb_ice(A, lda, (int)r, S.vn1, &dmin);
+                    okv = est >= q.band * dmin ? 1 : 0;
+                }
+                if (lane == 0) S.okv = okv;
+            }
+            __syncthreads();
+            const int okv = S.okv;
+            if (tid == 0 && q.ok) q.ok[mi] = okv;
+            if (!okv) {
+                const double *P = q.pristine[mi];
+                for (int c = 0; c < n; ++c)
+                    for (int r = tid; r < m; r += NT) A[(int64_t)c * lda + r] = P[(int64_t)c * lda + r];
+                sync_global();
+                if (tid == 0) S.redo = 1;
+            }
+            __syncthreads();
+        }
     }
     // last workgroup out resets the queue for the next launch
     if (tid == 0) {

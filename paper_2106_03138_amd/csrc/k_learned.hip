@@ -25,6 +25,9 @@
 #define LF_NT 256
 #define LF_SAMPLE 64
 #define LF_LOG_FLOOR (-30.0)
+typedef double lf_dbl4 __attribute__((ext_vector_type(4)));
+#define LF_PSORT 2048  // power of two >= LF_SAMPLE (LF_SAMPLE - 1) / 2, the cosines' sort
+static_assert(LF_PSORT >= LF_SAMPLE * (LF_SAMPLE - 1) / 2, "sort buffer");
 
 // ---------------------------------------------------------------- features
 __global__ void __launch_bounds__(LF_NT) k_features(LfArgs q, double *feat) {
@@ -32,7 +35,7 @@ __global__ void __launch_bounds__(LF_NT) k_features(LfArgs q, double *feat) {
     __shared__ double sl[QB_NMAX];
     __shared__ double sc[LF_SAMPLE * 65];  // staged sampled columns, 64 rows at a time
     __shared__ double sg[LF_SAMPLE * LF_SAMPLE];
-    __shared__ double sth[LF_SAMPLE * (LF_SAMPLE - 1) / 2];
+    __shared__ double sth[LF_PSORT];  // the sampled cosines, then sorted
     __shared__ double sred[LF_NT / 64];
     __shared__ int scnt[LF_NT / 64];
     const int mi = blockIdx.x;
@@ -49,15 +52,26 @@ __global__ void __launch_bounds__(LF_NT) k_features(LfArgs q, double *feat) {
         f[11] = (double)n / (double)(m > 1 ? m : 1);
     }
     if (n == 0 || m == 0) return;
-    // column norms (fixed-order wavefront sums)
-    for (int c = wv; c < n; c += NW) {
-        double s = 0.0;
-        for (int r = lane; r < m; r += 64) {
-            const double x = A[(int64_t)c * lda + r];
-            s += x * x;
+    // column norms (fixed-order wavefront sums), four columns of a wavefront at
+    // a time with every load issued before the sums (m <= QB_NMAX = 8 x 64 rows)
+    for (int c0 = 4 * wv; c0 < n; c0 += 4 * NW) {
+        double x[4][QB_NMAX / 64];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int u = 0; u < QB_NMAX / 64; ++u) {
+                const int c = c0 + cb, r = lane + 64 * u;
+                x[cb][u] = (c < n && r < m) ? A[(int64_t)c * lda + r] : 0.0;
+            }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            double s = 0.0;
+#pragma unroll
+            for (int u = 0; u < QB_NMAX / 64; ++u)
+                if (lane + 64 * u < m) s += x[cb][u] * x[cb][u];
+            s = wave_sum(s);
+            if (lane == 0 && c0 + cb < n) su[c0 + cb] = sqrt(s);
         }
-        s = wave_sum(s);
-        if (lane == 0) su[c] = sqrt(s);
     }
     __syncthreads();
     double um = 0.0;
@@ -94,44 +108,72 @@ __global__ void __launch_bounds__(LF_NT) k_features(LfArgs q, double *feat) {
             if (rk == (int)floor(qq * (double)(n - 1))) f[k] = v;
         }
     }
-    // Gram of the sampled columns floor(k n / s), staged 64 rows at a time
+    // Gram of the sampled columns floor(k n / s) on FP64 MFMA (16x16x4), the
+    // rows staged in LDS 64 at a time: wavefront w takes the upper 16 x 16 tiles
+    // w, w + 4, ... of the (at most) 4 x 4 grid; in a tile, lane (i, kk) holds
+    // the A operand X[16 bi + i][r + kk] and the B operand X[16 bj + i][r + kk]
     const int s = n < LF_SAMPLE ? n : LF_SAMPLE;
-    const int npair = s * (s + 1) / 2;
-    double acc[(LF_SAMPLE * (LF_SAMPLE + 1) / 2 + LF_NT - 1) / LF_NT];
-    constexpr int NP = (LF_SAMPLE * (LF_SAMPLE + 1) / 2 + LF_NT - 1) / LF_NT;
+    const int nt = (s + 15) >> 4, ntile = nt * (nt + 1) / 2;
+    const int ti = lane & 15, kk = lane >> 4;
+    constexpr int TPW = (LF_SAMPLE / 16 * (LF_SAMPLE / 16 + 1) / 2 + NW - 1) / NW;  // tiles per wavefront
+    lf_dbl4 acc[TPW];
 #pragma unroll
-    for (int u = 0; u < NP; ++u) acc[u] = 0.0;
+    for (int u = 0; u < TPW; ++u) acc[u] = lf_dbl4{0.0, 0.0, 0.0, 0.0};
+    auto tile_of = [&](int tile, int &bi, int &bj) {
+        bi = 0;
+        int rem = tile;
+        while (rem >= nt - bi) { rem -= nt - bi; ++bi; }
+        bj = bi + rem;
+    };
     for (int r0 = 0; r0 < m; r0 += 64) {
         __syncthreads();
-        for (int e = tid; e < 64 * s; e += LF_NT) {
-            const int k = e >> 6, r = e & 63;
-            const int col = (int)(((int64_t)k * n) / s);
-            sc[k * 65 + r] = (r0 + r < m) ? A[(int64_t)col * lda + r0 + r] : 0.0;
+        {  // every load of the chunk issued before the stores
+            double xv[64 * LF_SAMPLE / LF_NT];
+#pragma unroll
+            for (int u = 0; u < 64 * LF_SAMPLE / LF_NT; ++u) {
+                const int e = tid + LF_NT * u, k = e >> 6, r = e & 63;
+                const int col = (int)(((int64_t)k * n) / (s > 0 ? s : 1));
+                xv[u] = (k < s && r0 + r < m) ? A[(int64_t)col * lda + r0 + r] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 64 * LF_SAMPLE / LF_NT; ++u) {
+                const int e = tid + LF_NT * u;
+                // columns past s as zeros too, so that a tile's padding stays finite
+                sc[(e >> 6) * 65 + (e & 63)] = (e >> 6) < s ? xv[u] : 0.0;
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < NP; ++u) {
-            const int pidx = tid + u * LF_NT;
-            if (pidx < npair) {
-                // pair index -> (i, j), i <= j, row-major over the upper triangle
-                int i = 0, rem = pidx;
-                while (rem >= s - i) { rem -= s - i; ++i; }
-                const int j = i + rem;
-                double t = acc[u];
-                for (int r = 0; r < 64; ++r) t += sc[i * 65 + r] * sc[j * 65 + r];
-                acc[u] = t;
+        for (int u = 0; u < TPW; ++u) {
+            const int tile = wv + NW * u;
+            if (tile < ntile) {
+                int bi, bj;
+                tile_of(tile, bi, bj);
+#pragma unroll
+                for (int k = 0; k < 64; k += 4) {
+                    const double av = sc[(16 * bi + ti) * 65 + k + kk];
+                    const double bv = sc[(16 * bj + ti) * 65 + k + kk];
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                }
             }
         }
     }
+    // register v of a lane holds G[16 bi + 4 v + kk][16 bj + ti]; a diagonal
+    // tile holds both (row, cc) and (cc, row): each is stored once
 #pragma unroll
-    for (int u = 0; u < NP; ++u) {
-        const int pidx = tid + u * LF_NT;
-        if (pidx < npair) {
-            int i = 0, rem = pidx;
-            while (rem >= s - i) { rem -= s - i; ++i; }
-            const int j = i + rem;
-            sg[i * LF_SAMPLE + j] = acc[u];
-            sg[j * LF_SAMPLE + i] = acc[u];
+    for (int u = 0; u < TPW; ++u) {
+        const int tile = wv + NW * u;
+        if (tile < ntile) {
+            int bi, bj;
+            tile_of(tile, bi, bj);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * bi + 4 * v + kk, cc = 16 * bj + ti;
+                if (row < s && cc < s && row <= cc) {
+                    sg[row * LF_SAMPLE + cc] = acc[u][v];
+                    if (row < cc) sg[cc * LF_SAMPLE + row] = acc[u][v];
+                }
+            }
         }
     }
     __syncthreads();
@@ -185,16 +227,28 @@ __global__ void __launch_bounds__(LF_NT) k_features(LfArgs q, double *feat) {
         for (int i = 0; i < NW; ++i) tm = sred[i] > tm ? sred[i] : tm;
         f[14] = tm;
     }
+    // the order statistic: a bitonic sort of the P cosines in LDS (padded with
+    // DBL_MAX to the next power of two), then the entry at floor(0.95 (P - 1))
     const int want = (int)floor(0.95 * (double)(P - 1));
-    for (int e = tid; e < P; e += LF_NT) {
-        const double v = sth[e];
-        int rk = 0;
-        for (int o = 0; o < P; ++o) {
-            const double w = sth[o];
-            rk += (w < v || (w == v && o < e)) ? 1 : 0;
+    int ns = 1;
+    while (ns < P) ns <<= 1;
+    for (int i = P + tid; i < ns; i += LF_NT) sth[i] = DBL_MAX;
+    __syncthreads();
+    for (int k = 2; k <= ns; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < ns; i += LF_NT) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const double x = sth[i], y = sth[l];
+                    if ((x > y) == ((i & k) == 0)) {
+                        sth[i] = y;
+                        sth[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
         }
-        if (rk == want) f[13] = v;
-    }
+    if (tid == 0) f[13] = sth[want];
 }
 
 // ---------------------------------------------------------------- MLP
@@ -350,16 +404,12 @@ __global__ void k_predict(const float *__restrict__ Y, int B, qrdm_batch_params 
 }
 
 // ---------------------------------------------------------------- ICE check
-// One wavefront per matrix.  x (unit, growing) lives in LDS; per column j:
-// alpha = x . R[0:j, j], then the smallest eigenpair of the 2x2 matrix
-// [[est^2 + alpha^2, alpha gamma], [alpha gamma, gamma^2]] with
-// lambda_min = est^2 gamma^2 / lambda_max (its determinant over the larger root).
+// One wavefront per matrix: qb_ice on the leading rank x rank block of R.
 __global__ void __launch_bounds__(64) k_ice_check(LfArgs q, const int64_t *rank, double band, double *est_out,
                                                  int32_t *ok) {
     __shared__ double sx[QB_NMAX];
     const int mi = blockIdx.x, lane = threadIdx.x;
     const int m = q.m[mi], n = q.n[mi], lda = q.lda[mi];
-    const double *A = q.A[mi];
     int64_t r = rank[mi];
     const int p = m < n ? m : n;
     if (r > p) r = p;
@@ -370,44 +420,8 @@ __global__ void __launch_bounds__(64) k_ice_check(LfArgs q, const int64_t *rank,
         }
         return;
     }
-    double dmin = DBL_MAX;
-    for (int i = lane; i < r; i += 64) {
-        const double d = fabs(A[(int64_t)i * lda + i]);
-        dmin = d < dmin ? d : dmin;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double od = __shfl_xor(dmin, o, 64);
-        dmin = od < dmin ? od : dmin;
-    }
-    double est = fabs(A[0]);
-    if (lane == 0) sx[0] = 1.0;
-    __syncthreads();
-    for (int j = 1; j < r; ++j) {
-        const double *col = A + (int64_t)j * lda;
-        double a = 0.0;
-        for (int i = lane; i < j; i += 64) a += sx[i] * col[i];
-        const double alpha = wave_sum(a);
-        const double gamma = col[j];
-        const double pp = est * est + alpha * alpha, qq = alpha * gamma, rr = gamma * gamma;
-        const double lmax = 0.5 * (pp + rr) + hypot(0.5 * (pp - rr), qq);
-        const double lmin = lmax > 0.0 ? (est * est) * rr / lmax : 0.0;
-        const double v1a = -qq, v1b = pp - lmin, v2a = rr - lmin, v2b = -qq;
-        const bool first = hypot(v1a, v1b) >= hypot(v2a, v2b);
-        double sa = first ? v1a : v2a, cb = first ? v1b : v2b;
-        const double nv = hypot(sa, cb);
-        if (nv > 0.0) {
-            sa /= nv;
-            cb /= nv;
-        } else {
-            sa = 1.0;
-            cb = 0.0;
-        }
-        for (int i = lane; i < j; i += 64) sx[i] *= sa;
-        if (lane == 0) sx[j] = cb;
-        est = sqrt(lmin);
-        __syncthreads();
-    }
+    double dmin;
+    const double est = qb_ice(q.A[mi], lda, (int)r, sx, &dmin);
     if (lane == 0) {
         if (est_out) est_out[mi] = est;
         ok[mi] = est >= band * dmin ? 1 : 0;

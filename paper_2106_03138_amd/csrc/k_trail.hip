@@ -114,6 +114,7 @@ k_gemm1(QrdmArgs a, const T *__restrict__ V, int64_t ldv, double *Yp, int64_t ld
     const int sp = blockIdx.y, zg = blockIdx.z;
     if (blockIdx.x == 0 && sp == 0 && zg == 0 && threadIdx.x == 0) {
         ctl->flop_gemm += 2.0 * (double)t * (double)l * (double)w2;
+        ctl->bytes_gemm2 += 16.0 * (double)t * (double)w2;
         if (nsplit > (int)gridDim.y) atomicOr(&ctl->error, 4);  // a split without a workgroup
     }
     if (sp >= nsplit || zg >= nz) return;

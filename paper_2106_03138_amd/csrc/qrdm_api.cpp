@@ -453,6 +453,7 @@ void prof_fill(const ProfRun &prof, PollCtx &pc, const QrdmCtl &cf, int64_t m, i
     st->gemm2_ms = t[5];
     st->downdate_ms = t[6];
     st->gemm_flop = cf.flop_gemm;
+    st->gemm2_bytes = cf.bytes_gemm2;
     st->panel_flop = cf.flop_panel;
     st->panel_bytes = cf.bytes_panel;
     float ms = 0.f;

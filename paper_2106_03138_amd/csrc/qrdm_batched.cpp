@@ -49,7 +49,8 @@ double flops(int64_t m, int64_t n) {
 const qrdm_batch_tune kDefaultTune[QRDM_BATCH_CLASSES] = {{0, 0}, {0, 0}, {1, 0}, {1, 0}};
 
 hipError_t enqueue(qrdm_batch_plan *pl, double *const *A, double *const *tau_house, int32_t *const *perm,
-                   int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info, hipStream_t s) {
+                   int64_t *rank, int32_t *status, const qrdm_batch_params *pm, int64_t *info, hipStream_t s,
+                   const double *const *pristine = nullptr, double band = 0.0, int32_t *ok = nullptr) {
     for (int c = 0; c < QRDM_BATCH_CLASSES; ++c) {
         if (pl->count[c] == 0) continue;
         QbArgs q;
@@ -72,6 +73,9 @@ hipError_t enqueue(qrdm_batch_plan *pl, double *const *A, double *const *tau_hou
         q.stop_rule = pl->p.stop_rule;
         q.eps1_scale = pl->p.eps1_scale;
         q.certified = pl->p.certified;
+        q.pristine = pristine;
+        q.band = band;
+        q.ok = ok;
         hipError_t e = launch_qrdm_batched(q, pl->tune[c].variant, pl->grid[c], s);
         if (e != hipSuccess) return e;
     }
@@ -205,6 +209,21 @@ int qb_plan_sizes(const qrdm_batch_plan *pl, int32_t *batch, const int32_t **m, 
     *lda = pl->d_lda;
     *device = pl->device;
     return 0;
+}
+
+int qrdm_batch_factor_checked(qrdm_batch_plan *pl, double *const *A, double *const *tau_house,
+                              int32_t *const *perm, int64_t *rank, int32_t *status, const qrdm_batch_params *pm,
+                              const double *const *pristine, double band, int32_t *ok, int64_t *info, void *stream) {
+    if (!pl) return -1;
+    if (pl->batch > 0 && (!A || !tau_house || !perm || !rank || !status || !pm || !pristine || !ok)) return -2;
+    if (!(band >= 0.0)) return -9;
+    if (pl->batch == 0) return QRDM_OK;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return QRDM_ERR_HIP + (int)e;
+    if (dev != pl->device) return -1;
+    e = enqueue(pl, A, tau_house, perm, rank, status, pm, info, (hipStream_t)stream, pristine, band, ok);
+    return e == hipSuccess ? QRDM_OK : QRDM_ERR_HIP + (int)e;
 }
 
 void qrdm_batch_plan_destroy(qrdm_batch_plan *pl) {

@@ -60,6 +60,7 @@ struct QrdmCtl {
     int32_t c0off;           // first column of the trailing update, from n_s: k_s, or l when cpath
     int32_t Ai[QK_KM];       // candidate index (row of the Gram matrix) of each accepted column
     int64_t ngram;           // panels formed from the Gram matrix
+    double bytes_gemm2;      // algorithmic bytes of GEMM2 (A read and written once: 16 t w), summed over blocks
 };
 
 // Region of the workspace for the Gram-matrix panel (doubles, 64 x 64 each):

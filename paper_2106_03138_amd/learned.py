@@ -167,14 +167,18 @@ def predict_params(plan: BatchPlan, model: Model):
 
 
 def predict_factor(batch: Batch, plan: BatchPlan, model: Model, pristine, band: float = 0.1,
-                   use_graph: bool = False, breakdown: dict = None):
-    """Predicted parameters, factorization, online check, and a second
-    factorization with the defaults for every matrix that fails the check.
-    pristine: a copy of batch.data before the call (the factorization is in place).
+                   use_graph: bool = False, breakdown: dict = None, pristine_ptrs=None):
+    """Predicted parameters, then the factorization with the online check in the
+    same launch: a matrix that fails the check is factored again with the
+    defaults (the plan's parameters) by its own workgroup.
+    pristine: a copy of batch.data before the call (the factorization is in
+    place); pristine_ptrs: batch.pointers(pristine), made here when not given.
+    use_graph is accepted for the caller's convenience; the checked launch is
+    not captured.
     breakdown: when a dict, the device is synchronized after each stage and the
     stage times (ms) are stored in it, with the factorization's per-matrix
     clock ticks ("ticks": int64 device tensor).
-    Returns (params, number of fallbacks)."""
+    Returns (params, number of matrices factored again)."""
     import torch
     clock = [time.perf_counter()]
 
@@ -191,29 +195,12 @@ def predict_factor(batch: Batch, plan: BatchPlan, model: Model, pristine, band: 
     pm = predict_params(plan, model)
     stage("features_mlp_snap_ms")
     info = torch.zeros(4 * max(len(batch), 1), dtype=torch.int64, device="cuda") if breakdown is not None else None
-    plan.factor(params=pm, use_graph=use_graph, info=info)
-    stage("factor_ms")
+    ptrs = pristine_ptrs if pristine_ptrs is not None else batch.pointers(pristine)
+    ok = plan.factor_checked(pm, ptrs, band, info=info)
+    stage("factor_check_rerun_ms")
     if info is not None:
         breakdown["ticks"] = info.view(-1, 4)[:, 3]
-    ok, _ = plan.check(band)
-    bad = torch.nonzero(ok == 0).flatten().cpu().numpy()
-    stage("check_ms")
-    if len(bad):
-        # the failures again with the defaults, through the same plan: per-matrix
-        # parameters with k_DM = 0 (left as it is) for every other matrix
-        for i in bad:
-            s0, s1 = int(batch.off[i]), int(batch.off[i + 1])
-            batch.data[s0:s1].copy_(pristine[s0:s1])
-        t, d, k = DEFAULT
-        pm2 = torch.zeros_like(pm)
-        sel = torch.as_tensor(bad, dtype=torch.int64, device=pm.device)
-        f64, i32 = pm2.view(torch.float64).view(-1, 3), pm2.view(torch.int32).view(-1, 6)
-        f64[sel, 0] = t
-        f64[sel, 1] = d
-        i32[sel, 4] = k
-        plan.factor(params=pm2)
-    stage("rerun_ms")
-    return pm, len(bad)
+    return pm, int((ok == 0).sum())
 
 
 def main():

@@ -6,9 +6,13 @@
 //
 // in:  int32 count, variant, grid; double tau, delta; int32 kmax, stop_rule;
 //      double eps1_scale; int32 certified; then per matrix int32 m, n and the
-//      m x n column-major float64 data.
+//      m x n column-major float64 data; optionally int32 mode (1: per-matrix
+//      parameters; 2: per-matrix parameters and the online check with the
+//      re-run of the failures, as qrdm_batch_factor_checked), double band, and
+//      per matrix double tau, delta, int32 kmax, pad (qrdm_batch_params).
 // out: per matrix int64 rank, int32 status, float64 tau_house[min(m, n)],
-//      int32 perm[n], float64 A[m x n] (the factored matrix), int64 info[4].
+//      int32 perm[n], float64 A[m x n] (the factored matrix), int64 info[4],
+//      int32 ok (mode 2; -1 otherwise).
 // Variants 0-2 are the library's (256 threads); 3 is the 512-thread form
 // with one column tile per wavefront and register panels.
 #include "hip/hip_runtime.h"
@@ -95,7 +99,19 @@ int main(int argc, char **argv) {
         tp[i] = th[i].data();
         pp[i] = perm[i].data();
     }
+    int32_t mode = 0;
+    double band = 0.0;
+    std::vector<qrdm_batch_params> pmv;
+    if (fread(&mode, sizeof mode, 1, f) == 1 && mode > 0) {
+        rd(f, &band, 1);
+        pmv.resize(count);
+        rd(f, pmv.data(), (size_t)count);
+    }
     fclose(f);
+    std::vector<std::vector<double>> P(A);  // pristine copies
+    std::vector<const double *> Pp(count);
+    for (int i = 0; i < count; ++i) Pp[i] = P[i].data();
+    std::vector<int32_t> ok(count, -1);
     // longest first, as the library orders a size class
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
@@ -114,7 +130,10 @@ int main(int argc, char **argv) {
     q.rank = rank.data();
     q.status = status.data();
     q.info = info.data();
-    q.pm = nullptr;
+    q.pm = mode > 0 ? pmv.data() : nullptr;
+    q.pristine = mode == 2 ? Pp.data() : nullptr;
+    q.band = band;
+    q.ok = mode == 2 ? ok.data() : nullptr;
     q.order = order.data();
     q.count = count;
     q.counters = counters;
@@ -144,6 +163,7 @@ int main(int argc, char **argv) {
         fwrite(perm[i].data(), 4, perm[i].size(), g);
         fwrite(A[i].data(), 8, A[i].size(), g);
         fwrite(&info[4 * (size_t)i], 8, 4, g);
+        fwrite(&ok[i], 4, 1, g);
     }
     fclose(g);
     return 0;

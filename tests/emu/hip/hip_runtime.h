@@ -107,6 +107,8 @@ inline emu_dbl4 emu_mfma_f64_16x16x4(double a, double b, emu_dbl4 c, int, int, i
     return d;
 }
 #define __builtin_amdgcn_mfma_f64_16x16x4f64 emu_mfma_f64_16x16x4
+// a scheduling barrier over the wavefront: here a barrier of its 64 threads
+#define __builtin_amdgcn_wave_barrier() emu_wave_sync()
 
 // memory operations: host atomics (ThreadSanitizer sees them), waits are no-ops
 template <typename T>

@@ -84,3 +84,51 @@ def test_emulation_catches_unfenced_handoff(tmp_path):
     assert bad.returncode == 66 and "data race" in bad.stderr
     lanes = subprocess.run([exe, "lanes"], env=env, capture_output=True, text=True, timeout=120)
     assert lanes.returncode == 0 and "lanes ok" in lanes.stdout, lanes.stdout + lanes.stderr[-2000:]
+
+
+def test_checked_form_emulated(emu_exe):
+    """The checked form (per-matrix parameters, the online check, the re-run of
+    a failure from its pristine copy with the launch's parameters, all in the
+    workgroup's loop) under ThreadSanitizer: a matrix it keeps equals the run
+    with its per-matrix parameters alone, a matrix it factors again equals the
+    run with the launch's parameters, bit for bit; the ok flags follow the
+    oracle's condition estimate where it is not at the threshold."""
+    from oracle import learned as Lr
+    exe, d = emu_exe
+    mats = _cases() + [I.batch_matrix(120, 90, 80, np.random.SeedSequence(7)),
+                       I.from_spectrum(96, 96, np.geomspace(1.0, 1e-12, 96), 8)]
+    # aggressive parameters (tau = 0, delta = 1 admits almost any block) for some
+    params = [(0.0, 1.0, 64) if i % 2 == 0 else (0.3, 0.7, 32) for i in range(len(mats))]
+    own, _ = emurun.run(exe, mats, str(d), variant=1, params=params, env=TSAN, timeout=900)
+    # a band between two of the estimate-to-diagonal ratios, so that some
+    # matrices pass the check and some are factored again
+    ratios = []
+    for o in own:
+        r = int(o["rank"])
+        if r > 0:
+            R = np.triu(o["qr"][:r, :r])
+            ratios.append(Lr.ice_sigma_min(R) / np.min(np.abs(np.diag(R))))
+    ratios = np.sort(ratios)
+    h = len(ratios) // 2
+    band = float(np.sqrt(ratios[h - 1] * ratios[h]))
+    chk, _ = emurun.run(exe, mats, str(d), variant=1, params=params, band=band, env=TSAN, timeout=900)
+    dflt, _ = emurun.run(exe, mats, str(d), variant=1, env=TSAN, timeout=900)
+    kept = redo = 0
+    for i, (c, o, f) in enumerate(zip(chk, own, dflt)):
+        ref = o if c["ok"] == 1 else f
+        kept += c["ok"] == 1
+        redo += c["ok"] == 0
+        assert c["ok"] in (0, 1)
+        for key in ("rank", "status"):
+            assert c[key] == ref[key], (i, key)
+        for key in ("tau", "perm", "qr"):
+            assert np.array_equal(c[key], ref[key]), (i, key)
+        r = int(o["rank"])
+        if r > 0:
+            R = np.triu(o["qr"][:r, :r])
+            est = Lr.ice_sigma_min(R)
+            thr = band * np.min(np.abs(np.diag(R)))
+            scale = np.max(np.abs(np.diag(R)))
+            if abs(est - thr) > 1e-8 * max(est, thr) + 1e-12 * scale:
+                assert c["ok"] == int(est >= thr), (i, est, thr)
+    assert kept >= 1 and redo >= 1, (kept, redo)

@@ -150,6 +150,50 @@ def test_predict_factor_fallback_equals_default():
     assert torch.equal(got[0], b2.data) and torch.equal(got[1], b2.rank) and torch.equal(got[2], b2.perm)
 
 
+def test_checked_factor_matches_separate_launches():
+    """The checked launch (factorization with the predicted parameters, the
+    online check, and the re-run of the failures with the plan's parameters, all
+    in one launch) equals the same steps as separate launches: factor with the
+    predictions, qrdm_batch_check, then the failures restored and factored again
+    with per-matrix parameters that leave every other matrix as it is (k_DM = 0).
+    Bit for bit, and the same failures."""
+    import torch
+    Q = _gpu()
+    from paper_2106_03138_amd import learned as Ld
+    mats = _mats(seed=29, count=24)
+    mats += [I.batch_matrix(200, 150, 140, np.random.SeedSequence(5)),
+             I.from_spectrum(300, 280, np.geomspace(1.0, 1e-15, 280), 6)]
+    model = Ld.Model(I.mlp_init(7) * 3.0, np.concatenate([np.zeros(16), np.ones(16)]))
+    for band in (0.1, 0.5):
+        b, plan = _plan(mats)
+        pristine = b.data.clone()
+        pm = Ld.predict_params(plan, model)
+        ok = plan.factor_checked(pm, b.pointers(pristine), band)
+        torch.cuda.synchronize()
+        got = (b.data.clone(), b.rank.clone(), b.perm.clone(), b.tau.clone(), ok.clone())
+        # the same steps as separate launches
+        b2, plan2 = _plan(mats)
+        plan2.factor(params=pm)
+        ok2, _ = plan2.check(band)
+        bad = torch.nonzero(ok2 == 0).flatten()
+        if len(bad):
+            for i in bad.cpu().numpy():
+                s0, s1 = int(b2.off[i]), int(b2.off[i + 1])
+                b2.data[s0:s1].copy_(pristine[s0:s1])
+            pm2 = torch.zeros_like(pm)
+            f64, i32 = pm2.view(torch.float64).view(-1, 3), pm2.view(torch.int32).view(-1, 6)
+            t, d, k = Ld.DEFAULT
+            f64[bad, 0] = t
+            f64[bad, 1] = d
+            i32[bad, 4] = k
+            plan2.factor(params=pm2)
+        torch.cuda.synchronize()
+        print(f"[checked] band {band}: {len(bad)} of {len(mats)} factored again", flush=True)
+        assert torch.equal(got[4], ok2)
+        assert torch.equal(got[0], b2.data) and torch.equal(got[1], b2.rank)
+        assert torch.equal(got[2], b2.perm) and torch.equal(got[3], b2.tau)
+
+
 def test_predicted_parameters_match_oracle_factorization():
     """Each matrix factored with its predicted (tau, delta, k_DM) equals the
     oracle's factorization with those parameters."""
