@@ -31,6 +31,9 @@
 // column whose Cholesky diagonal falls below 1e-4 of its norm, a Cholesky
 // breakdown, or max|E| > 1e-9) is left to k_panel, which the host always
 // launches after these and which runs only when cpath = 0.
+#include <type_traits>
+#include <utility>
+
 #include "qrdm_internal.h"
 
 #define CP_K 64          // largest block of the Gram route
@@ -50,6 +53,24 @@ __device__ __forceinline__ double cp_readlane(double v, int l) {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// value of lane 16 (lane / 16) + K in every lane (a DPP row broadcast: one
+// move for the 64-bit value, where a read of a lane into scalar registers
+// takes two)
+template <int K>
+__device__ __forceinline__ double cp_rowbcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, true);
+}
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
+template <typename F, int... I>
+__device__ __forceinline__ void cp_static_for_seq(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void cp_static_for(F &&f) {
+    cp_static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
 // 1 / x from the hardware reciprocal and two Newton steps (relative error a
@@ -200,9 +221,11 @@ k_cpchol(QrdmArgs a, const double *G, double *cp, int enable) {
     for (int kb = 0; kb < 4; ++kb) {
         const int j0 = 16 * kb;
         if (j0 >= l) break;
-        // (a) the diagonal block on wavefront 0, lane i16 holding row j0 + i16.
-        // Row j keeps S_j. as it stood when it was eliminated, and is scaled to
-        // R1_j. once the block is done; the rows below take S_ic -= (S_ij / d) S_jc.
+        // (a) the diagonal block on wavefront 0, lane i16 holding row j0 + i16
+        // (each 16-lane row of the wavefront holds the same copy, so row jj is
+        // broadcast within the rows).  Row j keeps S_j. as it stood when it was
+        // eliminated, and is scaled to R1_j. once the block is done; the rows
+        // below take S_ic -= (S_ij / d) S_jc.
         if (wv == 0) {
             double g[16], d0b[16];
 #pragma unroll
@@ -211,22 +234,26 @@ k_cpchol(QrdmArgs a, const double *G, double *cp, int enable) {
             for (int jj = 0; jj < 16; ++jj) d0b[jj] = d0[j0 + jj];
             int f = 0, lb = l;
             double myd = 1.0;  // the pivot d of this lane's row
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
+            // The steps past k_s run too, as no-ops (al = 0, no flag, myd kept):
+            // with no branch between them the next pivot's reciprocal overlaps
+            // the current step's updates.
+            cp_static_for<16>([&](auto jc) {
+                constexpr int jj = decltype(jc)::value;
                 const int j = j0 + jj;
-                if (j < ks) {
-                    const double d = cp_readlane(g[jj], jj);
-                    const int fj = (j >= 1 && !(d >= eps2)) ? 1
-                                 : ((!(d > 0.0) || !(d >= CP_SAFE * CP_SAFE * d0b[jj])) ? 2 : 0);
-                    const bool first = f == 0 && fj != 0;  // the first failing column decides
-                    lb = first ? j : lb;
-                    f = first ? fj : f;
-                    const double al = i16 > jj ? g[jj] * cp_rcp(d) : 0.0;
+                const bool valid = j < ks;
+                const double d = cp_readlane(g[jj], jj);
+                const bool c1 = (j >= 1) & !(d >= eps2);
+                const bool c2 = !(d > 0.0) | !(d >= CP_SAFE * CP_SAFE * d0b[jj]);
+                const int fj = valid ? (c1 ? 1 : (c2 ? 2 : 0)) : 0;
+                const bool first = (f == 0) & (fj != 0);  // the first failing column decides
+                lb = first ? j : lb;
+                f = first ? fj : f;
+                const double rd = cp_rcp(d);
+                const double al = (valid & (i16 > jj)) ? g[jj] * rd : 0.0;
 #pragma unroll
-                    for (int c = jj + 1; c < 16; ++c) g[c] -= al * cp_readlane(g[c], jj);
-                    myd = i16 == jj ? d : myd;
-                }
-            }
+                for (int c = jj + 1; c < 16; ++c) g[c] -= al * cp_rowbcast<jj>(g[c]);
+                myd = (valid & (i16 == jj)) ? d : myd;
+            });
             const double ri = cp_rsqrt(myd);
             if (lane < 16) {
 #pragma unroll
@@ -565,18 +592,19 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
             double p[16];
 #pragma unroll
             for (int c = 0; c < 16; ++c) p[c] = A4[lane * CP_LD + j0 + c];
+            // the steps past l run too, as no-ops (m = 0, p kept): no branch
+            // between the steps
 #pragma unroll
             for (int jj = 0; jj < 16; ++jj) {
                 const int j = j0 + jj;
-                if (j < l) {
-                    const double dq = cp_readlane(p[jj], j);
-                    const double sj = dq >= 0.0 ? -1.0 : 1.0;
-                    const double f = -sj * cp_rcp(1.0 - sj * dq);
-                    const double m = lane > j ? f * p[jj] : 0.0;  // zero on the finished rows
+                const bool act = (j < l) & (lane > j);
+                const double dq = cp_readlane(p[jj], j);
+                const double sj = dq >= 0.0 ? -1.0 : 1.0;
+                const double f = -sj * cp_rcp(1.0 - sj * dq);
+                const double m = act ? f * p[jj] : 0.0;  // zero on the finished rows
 #pragma unroll
-                    for (int c = jj + 1; c < 16; ++c) p[c] -= m * cp_readlane(p[c], j);
-                    p[jj] = lane > j ? m : p[jj];
-                }
+                for (int c = jj + 1; c < 16; ++c) p[c] -= m * cp_readlane(p[c], j);
+                p[jj] = act ? m : p[jj];
             }
             if (lane >= j0) {
 #pragma unroll

@@ -190,16 +190,23 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
         nsel = total;
     } else {
         // radix select of the cap-th largest key (bit patterns of non-negative
-        // doubles order like the values)
-        unsigned long long prefix = 0, pmask = 0;
+        // doubles order like the values).  Every candidate lies in [thr, umax],
+        // so its bits agree with those of umax down to the first bit where thr
+        // and umax differ: the digits start below that common prefix.
+        const unsigned long long bthr = (unsigned long long)__double_as_longlong(thr),
+                                 bmax = (unsigned long long)__double_as_longlong(s_umax);
+        int dec = bthr == bmax ? 64 : __clzll((long long)(bthr ^ bmax));  // bits decided
+        unsigned long long pmask = dec == 0 ? 0ull : (dec >= 64 ? ~0ull : (~0ull << (64 - dec)));
+        unsigned long long prefix = bmax & pmask;
         if (tid == 0) {
             s_krem = cap;
             s_exact = 0;
         }
-        bool fin = false;  // the same in every thread
+        bool fin = dec >= 64;  // the same in every thread
         for (int pass = 0; pass < 8; ++pass) {
             if (fin) continue;
-            const int shift = 56 - 8 * pass;
+            // the last digit may overlap decided bits, which every key counted shares
+            const int shift = 64 - dec - 8 > 0 ? 64 - dec - 8 : 0;
             if (tid < 256) s_hist[tid] = 0;
             __syncthreads();
 #pragma unroll
@@ -250,9 +257,10 @@ __global__ void __launch_bounds__(SEL_THREADS) k_select(QrdmArgs a) {
             __syncthreads();
             prefix = s_prefix;
             pmask |= (255ull << shift);
+            dec = 64 - shift;
             const int exact = s_exact;
             __syncthreads();
-            fin = exact != 0;
+            fin = exact != 0 || dec >= 64;
         }
         // from here keys compare with the chosen bin [lo, hi] of the bits decided
         // so far (one value unless the loop stopped early, when the whole last
@@ -498,15 +506,29 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
         const double delta = a.certified ? fmin(a.delta, a.tau * a.tau / (double)(nL - 1)) : a.delta;
         // conflicts |theta_ij| >= delta (or undefined) of every candidate i with
         // every earlier j, as bit masks, all wavefronts in parallel
-        for (int i = tid >> 6; i < nL; i += 4) {
-            const double di = sd[i];
-            bool bad0 = false, bad1 = false;
-            if (lane < i) bad0 = !(fabs(G[i * QK_KM + lane] / (di * sd[lane])) < delta);
-            if (lane + 64 < i) bad1 = !(fabs(G[i * QK_KM + lane + 64] / (di * sd[lane + 64])) < delta);
-            const unsigned long long m0 = __ballot(bad0), m1 = __ballot(bad1);
-            if (lane == 0) {
-                sbad[i][0] = m0;
-                sbad[i][1] = m1;
+        // (four rows per wavefront at a time, every load and quotient issued
+        // before the ballots: the divisions overlap; rows past nL are computed
+        // on row nL - 1 and not stored)
+        const double sdl0 = sd[lane], sdl1 = sd[lane + 64];
+        for (int i0 = tid >> 6; i0 < nL; i0 += 16) {
+            double q0[4], q1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = min(i0 + 4 * u, nL - 1);
+                const double di = sd[i];
+                q0[u] = G[i * QK_KM + lane] / (di * sdl0);
+                q1[u] = G[i * QK_KM + lane + 64] / (di * sdl1);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 4 * u;
+                const bool bad0 = lane < i && !(fabs(q0[u]) < delta);
+                const bool bad1 = lane + 64 < i && !(fabs(q1[u]) < delta);
+                const unsigned long long m0 = __ballot(bad0), m1 = __ballot(bad1);
+                if (lane == 0 && i < nL) {
+                    sbad[i][0] = m0;
+                    sbad[i][1] = m1;
+                }
             }
         }
         __syncthreads();
