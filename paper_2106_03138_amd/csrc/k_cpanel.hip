@@ -120,34 +120,51 @@ __device__ __forceinline__ dbl4 cp_mm16(FA fa, FB fb, dbl4 acc) {
 // (lane c < 16 forms column c), then the blocks above the diagonal follow by
 // block diagonals on MFMA, X_ij = -X_ii sum_{i < k <= j} R_ik X_kj, one
 // barrier per diagonal.  xr(i, j) reads X (on and above the diagonal blocks
-// only), xw(i, j, v) writes it; Tmp holds four 16 x CP_LD16 blocks.  Every
-// thread of the workgroup calls it.
-template <typename RA, typename RI, typename XR, typename XW>
-__device__ __forceinline__ void cp_trinv(RA r, RI rinv, XR xr, XW xw, double *Tmp) {
+// only), xw(i, j, v) writes it.  With TWO, a second, independent inverse
+// (r2, rinv2, xr2, xw2) is formed beside the first, step for step, so that the
+// two dependent chains overlap; each is computed exactly as it would be alone.
+// Tmp holds four 16 x CP_LD16 blocks per inverse.  Every thread of the
+// workgroup calls it.
+template <bool TWO, typename RA, typename RI, typename XR, typename XW, typename RA2, typename RI2, typename XR2,
+          typename XW2>
+__device__ __forceinline__ void cp_trinv_n(RA r, RI rinv, XR xr, XW xw, RA2 r2, RI2 rinv2, XR2 xr2, XW2 xw2,
+                                           double *Tmp) {
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, k4 = lane >> 4;
     {
         // column i16 of the block's inverse, right-looking from the bottom: x_k is
         // final once scaled, then swept out of the rows above it
         const int b0 = 16 * wv;
-        double x[16], rin[16];
+        double x[16], rin[16], x2[16], rin2[16];
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) {
             x[ii] = ii == i16 ? 1.0 : 0.0;
             rin[ii] = rinv(b0 + ii);
+            x2[ii] = x[ii];
+            rin2[ii] = TWO ? rinv2(b0 + ii) : 0.0;
         }
 #pragma unroll
         for (int kk = 15; kk >= 0; --kk) {
-            double rv[16];
+            double rv[16], rv2[16];
 #pragma unroll
-            for (int ii = 0; ii < kk; ++ii) rv[ii] = r(b0 + ii, b0 + kk);
+            for (int ii = 0; ii < kk; ++ii) {
+                rv[ii] = r(b0 + ii, b0 + kk);
+                rv2[ii] = TWO ? r2(b0 + ii, b0 + kk) : 0.0;
+            }
             x[kk] *= rin[kk];
+            if (TWO) x2[kk] *= rin2[kk];
 #pragma unroll
-            for (int ii = 0; ii < kk; ++ii) x[ii] -= rv[ii] * x[kk];
+            for (int ii = 0; ii < kk; ++ii) {
+                x[ii] -= rv[ii] * x[kk];
+                if (TWO) x2[ii] -= rv2[ii] * x2[kk];
+            }
         }
         if (lane < 16) {
 #pragma unroll
-            for (int ii = 0; ii < 16; ++ii) xw(b0 + ii, b0 + i16, x[ii]);
+            for (int ii = 0; ii < 16; ++ii) {
+                xw(b0 + ii, b0 + i16, x[ii]);
+                if (TWO) xw2(b0 + ii, b0 + i16, x2[ii]);
+            }
         }
     }
     __syncthreads();
@@ -155,21 +172,39 @@ __device__ __forceinline__ void cp_trinv(RA r, RI rinv, XR xr, XW xw, double *Tm
     for (int d = 1; d < 4; ++d) {
         const int bi = wv, bj = wv + d;
         if (bj < 4) {
-            double *M = Tmp + wv * 16 * CP_LD16;
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int kb = bi + 1; kb <= bj; ++kb)
+            double *M = Tmp + wv * 16 * CP_LD16, *M2 = Tmp + (4 + wv) * 16 * CP_LD16;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+            for (int kb = bi + 1; kb <= bj; ++kb) {
                 acc = cp_mm16([&](int i, int k) { return r(16 * bi + i, 16 * kb + k); },
                               [&](int k, int j) { return xr(16 * kb + k, 16 * bj + j); }, acc);
+                if (TWO)
+                    acc2 = cp_mm16([&](int i, int k) { return r2(16 * bi + i, 16 * kb + k); },
+                                   [&](int k, int j) { return xr2(16 * kb + k, 16 * bj + j); }, acc2);
+            }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) M[(4 * v + k4) * CP_LD16 + i16] = acc[v];
+            for (int v = 0; v < 4; ++v) {
+                M[(4 * v + k4) * CP_LD16 + i16] = acc[v];
+                if (TWO) M2[(4 * v + k4) * CP_LD16 + i16] = acc2[v];
+            }
             __builtin_amdgcn_wave_barrier();  // M is this wavefront's own: LDS keeps its order
             acc = cp_mm16([&](int i, int k) { return xr(16 * bi + i, 16 * bi + k); },
                           [&](int k, int j) { return M[k * CP_LD16 + j]; }, dbl4{0.0, 0.0, 0.0, 0.0});
+            if (TWO)
+                acc2 = cp_mm16([&](int i, int k) { return xr2(16 * bi + i, 16 * bi + k); },
+                               [&](int k, int j) { return M2[k * CP_LD16 + j]; }, dbl4{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
-            for (int v = 0; v < 4; ++v) xw(16 * bi + 4 * v + k4, 16 * bj + i16, -acc[v]);
+            for (int v = 0; v < 4; ++v) {
+                xw(16 * bi + 4 * v + k4, 16 * bj + i16, -acc[v]);
+                if (TWO) xw2(16 * bi + 4 * v + k4, 16 * bj + i16, -acc2[v]);
+            }
         }
         __syncthreads();
     }
+}
+
+template <typename RA, typename RI, typename XR, typename XW>
+__device__ __forceinline__ void cp_trinv(RA r, RI rinv, XR xr, XW xw, double *Tmp) {
+    cp_trinv_n<false>(r, rinv, xr, xw, r, rinv, xr, xw, Tmp);
 }
 
 // ------------------------------------------------------------------ k_cpchol
@@ -484,8 +519,11 @@ hipError_t launch_cpreduce(QrdmArgs a, const double *Gp, int kp, double *cp, hip
 // row tile rt on wavefront rt; MODE 2 (A and B upper triangular): the ten
 // tiles on and above the diagonal, k-tiles rt .. ct, five k-tiles per
 // wavefront.  A tile's operands for one k-tile are loaded before its MFMAs.
-template <int MODE, typename FA, typename FB, typename OUT>
-__device__ __forceinline__ void cp_mm(FA fa, FB fb, OUT out) {
+// With TWO, a second product of the same shape (fa2, fb2, out2) is formed
+// beside the first, tile for tile, so that the two accumulation chains
+// overlap; each tile is summed exactly as it would be alone.
+template <int MODE, bool TWO, typename FA, typename FB, typename OUT, typename FA2, typename FB2, typename OUT2>
+__device__ __forceinline__ void cp_mm_n(FA fa, FB fb, OUT out, FA2 fa2, FB2 fb2, OUT2 out2) {
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, k4 = lane >> 4;
     // MODE 2: the tiles (4 rt + ct, plus one; 0 = none) of each wavefront, five bits each
@@ -496,20 +534,33 @@ __device__ __forceinline__ void cp_mm(FA fa, FB fb, OUT out) {
         const int t = MODE == 1 ? 4 * wv + u : (int)((pk >> (5 * u)) & 31u) - 1;
         if (t < 0) break;
         const int rt = t >> 2, ct = t & 3, k0 = MODE == 2 ? rt : 0;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
         for (int kt = k0; kt <= ct; ++kt) {
-            double av[4], bv[4];
+            double av[4], bv[4], av2[4], bv2[4];
 #pragma unroll
             for (int kb = 0; kb < 4; ++kb) {
                 av[kb] = fa(rt * 16 + i16, kt * 16 + 4 * kb + k4);
                 bv[kb] = fb(kt * 16 + 4 * kb + k4, ct * 16 + i16);
+                av2[kb] = TWO ? fa2(rt * 16 + i16, kt * 16 + 4 * kb + k4) : 0.0;
+                bv2[kb] = TWO ? fb2(kt * 16 + 4 * kb + k4, ct * 16 + i16) : 0.0;
             }
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) acc = cp_mfma(av[kb], bv[kb], acc);
+            for (int kb = 0; kb < 4; ++kb) {
+                acc = cp_mfma(av[kb], bv[kb], acc);
+                if (TWO) acc2 = cp_mfma(av2[kb], bv2[kb], acc2);
+            }
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out(rt * 16 + 4 * v + k4, ct * 16 + i16, acc[v]);
+        for (int v = 0; v < 4; ++v) {
+            out(rt * 16 + 4 * v + k4, ct * 16 + i16, acc[v]);
+            if (TWO) out2(rt * 16 + 4 * v + k4, ct * 16 + i16, acc2[v]);
+        }
     }
+}
+
+template <int MODE, typename FA, typename FB, typename OUT>
+__device__ __forceinline__ void cp_mm(FA fa, FB fb, OUT out) {
+    cp_mm_n<MODE, false>(fa, fb, out, fa, fb, out);
 }
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -525,7 +576,7 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
     // dq on it, Y above)
     extern __shared__ double cp_lds[];
     double *A1 = cp_lds, *A2 = A1 + CP_K * CP_LD, *A3 = A2 + CP_K * CP_LD, *A4 = A3 + CP_K * CP_LD;
-    double *Tmp = A4 + CP_K * CP_LD;  // four 16 x CP_LD16 blocks for the triangular inverses
+    double *Tmp = A4 + CP_K * CP_LD;  // eight 16 x CP_LD16 blocks for the two triangular inverses
     const int i16 = lane & 15, k4 = lane >> 4;
     __shared__ double sS[CP_K], sUd[CP_K], sUi[CP_K], s_red[4];
     double *Tg = cp + CP_OFF_T, *Pg = cp + CP_OFF_P;
@@ -659,17 +710,18 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
     // longer needed) and Linv = L^{-1} into A2 below the diagonal, as the
     // inverse of the unit upper L^T (A2 keeps N above)
     // (the accessors load first and select after: their addresses are always in range)
-    cp_trinv([&](int i, int k) { const double y = A4[i * CP_LD + k], sk = sS[k]; return k < l ? -sk * y : 0.0; },
-             [&](int i) { const double v = sUi[i]; return i < l ? v : 1.0; },
-             [&](int i, int j) { return A1[i * CP_LD + j]; },
-             [&](int i, int j, double v) { A1[i * CP_LD + j] = v; }, Tmp);
-    cp_trinv([&](int i, int k) { const double v = A4[k * CP_LD + i]; return k < l ? v : 0.0; },
-             [&](int) { return 1.0; },
-             [&](int i, int j) { const double v = A2[j * CP_LD + i]; return i < j ? v : (i == j ? 1.0 : 0.0); },
-             [&](int i, int j, double v) {
-                 if (i < j) A2[j * CP_LD + i] = v;
-             },
-             Tmp);
+    cp_trinv_n<true>(
+          [&](int i, int k) { const double y = A4[i * CP_LD + k], sk = sS[k]; return k < l ? -sk * y : 0.0; },
+          [&](int i) { const double v = sUi[i]; return i < l ? v : 1.0; },
+          [&](int i, int j) { return A1[i * CP_LD + j]; },
+          [&](int i, int j, double v) { A1[i * CP_LD + j] = v; },
+          [&](int i, int k) { const double v = A4[k * CP_LD + i]; return k < l ? v : 0.0; },
+          [&](int) { return 1.0; },
+          [&](int i, int j) { const double v = A2[j * CP_LD + i]; return i < j ? v : (i == j ? 1.0 : 0.0); },
+          [&](int i, int j, double v) {
+              if (i < j) A2[j * CP_LD + i] = v;
+          },
+          Tmp);
     // ---- T = U Linv^T and P = -(I - N) S Uinv.  A block that reaches the last
     // row (t = l) ends with a column of one row: larfg leaves it alone (tau = 0,
     // beta = alpha), where the reconstruction reflects it (tau = 2, v = e); its
@@ -679,15 +731,15 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
         const double y = A4[i * CP_LD + k], sk = sS[k], ud = sUd[i];  // loads first, then selects
         return (i >= l || k >= l || k < i) ? 0.0 : (k == i ? ud : -sk * y);
     };
-    cp_mm<2>(uval,
+    cp_mm_n<2, true>(
+          uval,
           [&](int k, int j) {
               const double v = A2[j * CP_LD + k];
               return (j >= l || k >= l) ? 0.0 : (j == k ? 1.0 : (j > k ? v : 0.0));
           },
           [&](int i, int j, double v) {
               if (i < l && j < l && !(lastrow && j == l - 1)) Tg[i * CP_K + j] = v;
-          });
-    cp_mm<2>(
+          },
           [&](int i, int k) {
               const double n = A2[i * CP_LD + k], sk = sS[k];
               return (i >= l || k >= l || k < i) ? 0.0 : (k == i ? -(1.0 - n) * sk : n * sk);
@@ -725,7 +777,7 @@ k_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo,
 
 hipError_t launch_cpanel2(QrdmArgs a, double *cp, const double *Vw, int64_t ldv, double *Vo, float *Vo32,
                           hipStream_t s) {
-    const unsigned lds = (4 * CP_K * CP_LD + 4 * 16 * CP_LD16) * sizeof(double);
+    const unsigned lds = (4 * CP_K * CP_LD + 8 * 16 * CP_LD16) * sizeof(double);
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_cpanel2, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
