@@ -470,9 +470,10 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     __shared__ int sJ[QK_KM];
     __shared__ int sAi[QK_KM];  // candidate index (row of G) of each accepted column
     __shared__ unsigned long long sbad[QK_KM][2];  // bit j of row i: candidate j conflicts with i
-    __shared__ int sjslot[QK_KM];
     __shared__ int s_cont[QK_SWAP_MAX], s_pos[QK_SWAP_MAX];  // transposition bookkeeping (slots)
     __shared__ int soutpos[QK_KM];
+    __shared__ double s_v1[QK_SWAP_MAX], s_v2[QK_SWAP_MAX];  // vn1, vn2 and perm by slot
+    __shared__ int s_pm[QK_SWAP_MAX];
     __shared__ int s_ks;
     const int tid = threadIdx.x, lane = tid & 63;
     const int nL = ctl->nL;
@@ -576,8 +577,8 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     // ---- Lemma 1 on the accepted columns (second wavefront, beside the swap
     // bookkeeping of the first): gamma = min_i (1 - sum_{j != i} |theta_ij|)
     // over J, tau_J = min_J ||c_j|| / max_J ||c_j||, bound sqrt(gamma + tau_J^2 - 1)
-    // max_J ||c_j|| (row sums in the order of J)
-    if (tid >= 64 && tid < 128) {
+    // max_J ||c_j|| (row sums in the order of J).  Only the step log reads them.
+    if (tid >= 64 && tid < 128 && a.lemma) {
         double cmax = 0.0, cmin = INFINITY, gmin = INFINITY;
         if (nL > 1) {
             // lane L holds accepted columns L and L + 64: their candidate index and norm
@@ -638,6 +639,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
     // accepted columns outside that range in list order.
     if (tid < 64) {
         int nout = 0;
+        int js0 = 0, js1 = 0;  // the slots of J_lane and J_{lane + 64}
         for (int base = 0; base < ks; base += 64) {
             const int i = base + lane;
             const bool valid = i < ks;
@@ -645,13 +647,27 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             const bool outside = valid && (jp >= ns + ks);
             unsigned long long bo = __ballot(outside);
             const int oi = nout + __popcll(bo & ((1ull << lane) - 1));
-            if (valid) {
-                sjslot[i] = outside ? ks + oi : (int)(jp - ns);
-                if (outside) soutpos[oi] = jp;
-            }
+            const int sl = outside ? ks + oi : (int)(jp - ns);
+            if (valid && outside) soutpos[oi] = jp;
+            if (base == 0) js0 = sl;
+            else js1 = sl;
             nout += __popcll(bo);
         }
         const int nslots = ks + nout;
+        // vn1, vn2 and perm of every slot, loaded before the transpositions so
+        // that their latency overlaps them (every load before any store below)
+        double pv1[4], pv2[4];
+        int ppm[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = lane + 64 * u;
+            const int pos = (sl < ks) ? (int)(ns + sl) : (sl < nslots ? soutpos[sl - ks] : 0);
+            if (sl < nslots) {
+                pv1[u] = a.vn1[pos];
+                pv2[u] = a.vn2[pos];
+                ppm[u] = a.perm[pos];
+            }
+        }
         // cont[s]: slot whose original column sits in slot s; posof[c]: slot of
         // column c.  The transpositions are applied in order by the whole
         // wavefront on the same LDS words (same addresses, same values in every
@@ -661,7 +677,7 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             s_pos[lane + 64 * u] = lane + 64 * u;
         }
         for (int i = 0; i < ks; ++i) {
-            const int js = sjslot[i];
+            const int js = __builtin_amdgcn_readlane(i < 64 ? js0 : js1, i & 63);
             const int q = s_pos[js];
             const int c = s_cont[i];
             s_cont[i] = js;
@@ -669,7 +685,18 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             s_pos[c] = q;
             s_pos[js] = i;
         }
-        // moves: slot s receives the column that was at slot cont[s]
+        // the loaded values by slot
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int sl = lane + 64 * u;
+            if (sl < nslots) {
+                s_v1[sl] = pv1[u];
+                s_v2[sl] = pv2[u];
+                s_pm[sl] = ppm[u];
+            }
+        }
+        // moves: slot s receives the column that was at slot cont[s] (one
+        // wavefront: its LDS accesses complete in order)
         int nmv = 0;
         double ov1[4], ov2[4];
         int opm[4], dpos[4], spos[4];
@@ -682,9 +709,9 @@ __global__ void __launch_bounds__(256) k_dm_finish(QrdmArgs a, const double *G, 
             dpos[u] = (sl < ks) ? (int)(ns + sl) : (sl < nslots ? soutpos[sl - ks] : 0);
             spos[u] = (cs < ks) ? (int)(ns + cs) : (cs < nslots ? soutpos[cs - ks] : 0);
             if (mv[u]) {
-                ov1[u] = a.vn1[spos[u]];
-                ov2[u] = a.vn2[spos[u]];
-                opm[u] = a.perm[spos[u]];
+                ov1[u] = s_v1[cs];
+                ov2[u] = s_v2[cs];
+                opm[u] = s_pm[cs];
             }
         }
         __builtin_amdgcn_s_barrier();  // single wave: orders the reads above before the writes

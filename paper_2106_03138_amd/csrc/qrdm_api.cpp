@@ -502,6 +502,7 @@ int qrdm_run(double *A, int64_t m, int64_t n, int64_t lda, const qrdm_params &p,
     a.kmax = p.kmax;
     a.stop_rule = p.stop_rule;
     a.certified = p.certified;
+    a.lemma = (env.log != nullptr || p.certified) ? 1 : 0;
     // eps_w, the unit roundoff of the trailing data: 2^-52 (FP64) or 2^-23 in
     // mixed mode, where every trailing update rounds to FP32.  The stopping
     // test (eps_1 = n eps_w) and the recompute tolerance sqrt(eps_w) follow the

@@ -79,6 +79,7 @@ struct QrdmArgs {
     int32_t kmax;
     int32_t stop_rule;
     int32_t certified = 0;  // delta <= tau^2 / (nL - 1) per step (eq. delta_max)
+    int32_t lemma = 1;      // form Lemma 1's gamma and sigma bound of each step (read by the step log only)
     double eps1;    // eps_1 * (applied as eps1 * amax) of the stopping test
     double fbeps;   // eps_w * n: scalar pivoting when max partial norm <= fbeps * amax
     double tol3z;   // sqrt(eps_w): recompute a partial norm when the downdate lost this much
