@@ -565,6 +565,8 @@ k_gemm2(QrdmArgs a, const T *__restrict__ V, int64_t ldv, const T *__restrict__ 
 // the current tile's MFMAs run.  Wavefront w takes the 32 x 32 block at rows
 // 32 (w / 4), columns 32 (w % 4) of the tile; the products are k_gemm2's
 // (D = Z^T V^T, the accumulators starting as the A tile, the same order over k).
+// A is read once here, with non-temporal loads, so that its stream does not
+// evict the V rows and Z columns that other workgroups of the same L2 read.
 #define G2P_KMAX 64
 #define G2P_TH 1024
 #define G2P_LD (G2_MT + 8)  // LDS row of the staged V and Z (doubles); the 8 spread the banks
@@ -614,7 +616,8 @@ k_gemm2p(QrdmArgs a, const double *__restrict__ V, int64_t ldv, const double *__
                 const bool cok = cu + (lane >> 4) < ncol;
 #pragma unroll
                 for (int tr = 0; tr < 2; ++tr)
-                    x[(tc * 2 + tr) * 4 + v] = (cok && wr + tr * 16 + rj < nrow) ? pc[aoff + tr * 16] : 0.0;
+                    x[(tc * 2 + tr) * 4 + v] =
+                          (cok && wr + tr * 16 + rj < nrow) ? __builtin_nontemporal_load(pc + aoff + tr * 16) : 0.0;
             }
     };
     auto z_load = [&](int64_t tile, double (&z)[8]) {
