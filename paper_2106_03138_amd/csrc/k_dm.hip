@@ -746,12 +746,14 @@ hipError_t launch_dm_finish(QrdmArgs a, const double *G, double *theta_out, hipS
 }
 
 // ================================================================= k_swap
-// Column moves of a DM block on a 64-row band per workgroup: wavefront w moves
-// columns w, w+4, ... with one row per lane; every source is read into
-// registers before any destination is written (a destination is often another
-// move's source).
-#define SW_ROWS 64
-#define SW_PER (QK_SWAP_MAX / 4)
+// Column moves of a DM block on a 32-row band per workgroup (so that a
+// factorization of 8192 rows fills 256 compute units): the eight 32-lane
+// halves of the wavefronts move columns h, h+8, ... with one row per lane;
+// every source is read into registers before any destination is written (a
+// destination is often another move's source).  The bands are disjoint, so no
+// two workgroups touch the same element.
+#define SW_ROWS 32
+#define SW_PER (QK_SWAP_MAX / 8)
 
 __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     const QrdmCtl *ctl = a.ctl;
@@ -762,22 +764,22 @@ __global__ void __launch_bounds__(256) k_swap(QrdmArgs a) {
     const int64_t r0 = (int64_t)blockIdx.x * SW_ROWS;
     if (r0 >= a.m) return;
     __shared__ int sdst[QK_SWAP_MAX], ssrc[QK_SWAP_MAX];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, rl = tid & 31, h = tid >> 5;
     for (int e = tid; e < nsw; e += 256) { sdst[e] = ctl->swp_dst[e]; ssrc[e] = ctl->swp_src[e]; }
     __syncthreads();
-    const bool in = r0 + lane < a.m;
+    const bool in = r0 + rl < a.m;
     double v[SW_PER];
 #pragma unroll
     for (int u = 0; u < SW_PER; ++u) {
-        const int e = wv + 4 * u;
-        v[u] = (e < nsw && in) ? a.A[(int64_t)ssrc[e] * a.lda + r0 + lane] : 0.0;
+        const int e = h + 8 * u;
+        v[u] = (e < nsw && in) ? a.A[(int64_t)ssrc[e] * a.lda + r0 + rl] : 0.0;
     }
     __builtin_amdgcn_s_waitcnt(0);  // every read has returned before any write
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < SW_PER; ++u) {
-        const int e = wv + 4 * u;
-        if (e < nsw && in) a.A[(int64_t)sdst[e] * a.lda + r0 + lane] = v[u];
+        const int e = h + 8 * u;
+        if (e < nsw && in) a.A[(int64_t)sdst[e] * a.lda + r0 + rl] = v[u];
     }
 }
 
