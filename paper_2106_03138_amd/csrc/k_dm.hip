@@ -14,9 +14,13 @@
 //  k_dm_finish    cosines Theta = D^-1 G D^-1 with D = sqrt(diag G) (Section 4,
 //                 option (ii)), greedy |theta| < delta acceptance in candidate
 //                 order, and the column transpositions of Section 4 ("swap
-//                 column n_s+i with column j_i"), simulated in registers of one
-//                 wavefront; vn1/vn2/perm are permuted here.
-//  k_swap         moves the affected columns of A (all m rows) through LDS.
+//                 column n_s+i with column j_i"), applied in order by one
+//                 wavefront to slot tables in LDS; vn1/vn2/perm are permuted
+//                 here.  Lemma 1's record of the step (gamma and the sigma_min
+//                 bound) is formed beside it when the step log or certified
+//                 mode reads it.
+//  k_swap         moves the affected columns of A (all m rows) through
+//                 registers, on 32-row bands.
 #include <float.h>
 
 #include "qrdm_internal.h"
